@@ -1,0 +1,298 @@
+"""Plain FP64 CPU oracle of the condensed-space interior-point method for LQ-MPC.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or call this package; the HIP library and
+its Python binding never do, and this package imports nothing from them.
+
+It follows Cole, Shin, Pacaud, Zavala and Anitescu, "Exploiting GPU/SIMD architectures for
+solving linear-quadratic MPC problems" (arXiv 2209.13049):
+
+* ``reduce_problem``  -- Section 2, eqns. (K_constraint), (x_def) and (dense): eliminate the
+  states, giving min 1/2 v'Hv + h'v + h0  s.t.  Jv <= d.
+* ``condensed_step``  -- Section 3, eqns. (aug_KKT) and (cond_KKT) and the recovery
+  formulas that follow them: one Newton step through the condensed matrix H + J'Sigma J,
+  factored by dense Cholesky.
+* ``solve``           -- Algorithm 1 (condensed-space IPM), with the readings listed below.
+
+Everything is written from the definitions, in float64, with numpy/scipy primitives
+(matrix products, Cholesky) as steps and no blocking or reordering.
+
+Readings where the paper is silent or ambiguous (each one is also exercised by a test):
+
+R1  Objective carries a 1/2 on every quadratic term (eqn. (dense) and the PDE objective
+    have it; eqn. (sparse) does not; the minimiser is the same).
+R2  Q_f defaults to Q.
+R3  State-bound rows at t = 0 are constants and are dropped; bounds apply for t = 1..N.
+    Rows whose bound is infinite are dropped.
+R4  Stabilising feedback K = 0 (v = u).
+R5  The right-hand side of eqn. (cond_KKT) is -r1 + J'r2 - J'Sigma r3 (the printed "J r2"
+    is read as J'r2, which the block elimination of eqn. (aug_KKT) gives).
+R6  Sigma in the p^z formula of Algorithm 1 is Sigma_s = S^-1 Z.
+R7  Start: mu = 0.1, v = 0, s = max(d - Jv, 1e-2), lambda = z = mu / s.
+R8  Barrier parameter: monotone (Fiacco-McCormick) rule of Waechter and Biegler's IPOPT
+    paper, with kappa_eps = 10, kappa_mu = 0.2, theta_mu = 1.5, mu_min = tol / 10.
+R9  "Line search" = fraction-to-the-boundary step lengths alpha (for v, s, lambda) and
+    alpha_z (for z) with tau = max(0.99, 1 - mu); no merit backtracking (the problem is a
+    convex QP with linear constraints).
+R10 After each update z is safeguarded into [mu / (kappa_S s), kappa_S mu / s],
+    kappa_S = 1e10.
+R11 Termination: E_0 = max(|r1|, |r3|, |lambda - z|, |s z|) <= tol (unscaled inf-norms),
+    checked at the top of every iteration; iteration limit 200.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+KAPPA_EPS = 10.0
+KAPPA_MU = 0.2
+THETA_MU = 1.5
+KAPPA_SIGMA = 1e10
+TAU_MIN = 0.99
+MU_INIT = 0.1
+S_INIT_MIN = 1e-2
+ALPHA_MIN = 1e-14
+
+STATUS_CONVERGED = 0
+STATUS_MAX_ITER = 1
+STATUS_SMALL_STEP = 2
+
+
+@dataclass
+class Reduced:
+    """The dense QP of eqn. (dense) plus the pieces of eqn. (x_def) it was built from."""
+
+    Gamma: np.ndarray      # (ns N) x (nu N): block (t, j) = A^(t-1-j) B for j < t, t = 1..N
+    c: np.ndarray          # (ns N): free response A^t x0, t = 1..N
+    Rbar: np.ndarray       # block diag(R, ..., R) over t = 0..N-1
+    H: np.ndarray
+    h: np.ndarray
+    h0: float
+    J: np.ndarray          # inequality rows that are kept (finite bounds)
+    d: np.ndarray
+    groups: np.ndarray     # 0: x <= xu, 1: -x <= -xl, 2: u <= uu, 3: -u <= -ul (kept rows)
+    index: np.ndarray      # row index inside its group (kept rows)
+
+
+def powers_times(A: np.ndarray, X: np.ndarray, N: int):
+    """[X, A X, A^2 X, ..., A^N X] by repeated multiplication (A^k X, k = 0..N)."""
+    out = [np.array(X, dtype=np.float64)]
+    for _ in range(N):
+        out.append(A @ out[-1])
+    return out
+
+
+def reduce_problem(prob) -> Reduced:
+    """State elimination of Section 2 (eqn. (x_def)) with K = 0 and w = 0.
+
+    x = bA x0 + bB v, where bA stacks A^t and bB is block lower-triangular with block
+    (t, j) = A^(t-1-j) B.  Rows of x_0 (t = 0) are constants and are not kept (reading R3).
+    Substituting into the objective (reading R1: 1/2 convention) gives
+        H = bB' Qbar bB + Rbar,  h = bB' Qbar c,  h0 = 1/2 x0'Q x0 + 1/2 c'Qbar c,
+    with c = (A^t x0)_{t=1..N} and Qbar = blockdiag(Q, ..., Q, Q_f), and the inequalities
+    J v <= d with J = [Gamma; -Gamma; I; -I],  d = [xu - c; c - xl; uu; -ul].
+    Qbar is block diagonal, so it is applied block by block instead of being formed.
+    """
+    A, B, Q, R, Qf = prob.A, prob.B, prob.Q, prob.R, prob.Qf
+    ns, nu, N = A.shape[0], B.shape[1], int(prob.N)
+    G = powers_times(A, B, N - 1)                      # G[k] = A^k B
+    xs = powers_times(A, prob.x0, N)                   # xs[t] = A^t x0
+    Gamma = np.zeros((ns * N, nu * N))
+    for t in range(1, N + 1):
+        for j in range(t):
+            Gamma[(t - 1) * ns:t * ns, j * nu:(j + 1) * nu] = G[t - 1 - j]
+    c = np.concatenate(xs[1:])
+
+    def qbar_times(X):
+        """Qbar X for X with ns N rows."""
+        out = np.empty_like(X)
+        for t in range(1, N + 1):
+            W = Qf if t == N else Q
+            out[(t - 1) * ns:t * ns] = W @ X[(t - 1) * ns:t * ns]
+        return out
+
+    Rbar = np.kron(np.eye(N), R)
+    H = Gamma.T @ qbar_times(Gamma) + Rbar
+    H = 0.5 * (H + H.T)
+    h = Gamma.T @ qbar_times(c)
+    h0 = 0.5 * prob.x0 @ Q @ prob.x0 + 0.5 * c @ qbar_times(c)
+    I = np.eye(nu * N)
+    xu = np.tile(prob.xu, N)
+    xl = np.tile(prob.xl, N)
+    uu = np.tile(prob.uu, N)
+    ul = np.tile(prob.ul, N)
+    J_all = np.vstack([Gamma, -Gamma, I, -I])
+    d_all = np.concatenate([xu - c, c - xl, uu, -ul])
+    g_all = np.concatenate([np.full(ns * N, 0), np.full(ns * N, 1), np.full(nu * N, 2),
+                            np.full(nu * N, 3)])
+    i_all = np.concatenate([np.arange(ns * N), np.arange(ns * N), np.arange(nu * N),
+                            np.arange(nu * N)])
+    keep = np.isfinite(d_all)
+    return Reduced(Gamma=Gamma, c=c, Rbar=Rbar, H=H, h=h, h0=float(h0),
+                   J=J_all[keep], d=d_all[keep], groups=g_all[keep], index=i_all[keep])
+
+
+def objective(red: Reduced, v: np.ndarray) -> float:
+    """1/2 v'Hv + h'v + h0 (eqn. (dense))."""
+    return float(0.5 * v @ red.H @ v + red.h @ v + red.h0)
+
+
+def residuals(red: Reduced, v, s, lam, mu):
+    """r1, r2, r3 as defined under eqn. (aug_KKT)."""
+    r1 = red.H @ v + red.h + red.J.T @ lam
+    r2 = lam - mu / s
+    r3 = red.J @ v - red.d + s
+    return r1, r2, r3
+
+
+def condensed_matrix(red: Reduced, sigma: np.ndarray) -> np.ndarray:
+    """H + J' Sigma_s J (left-hand side of eqn. (cond_KKT))."""
+    return red.H + red.J.T @ (sigma[:, None] * red.J)
+
+
+def condensed_step(red: Reduced, v, s, lam, z, mu):
+    """One Newton direction through the condensed system (Section 3).
+
+    Sigma_s = S^-1 Z; (H + J'Sigma J) p_v = -r1 + J'r2 - J'Sigma r3 (reading R5), solved by
+    Cholesky; p_s = -r3 - J p_v; p_lambda = -r2 + Sigma r3 + Sigma J p_v;
+    p_z = mu S^-1 1 - z - Sigma p_s (reading R6).
+    """
+    sigma = z / s
+    r1, r2, r3 = residuals(red, v, s, lam, mu)
+    K = condensed_matrix(red, sigma)
+    rhs = -r1 + red.J.T @ r2 - red.J.T @ (sigma * r3)
+    factor = sla.cho_factor(K, lower=True)
+    pv = sla.cho_solve(factor, rhs)
+    Jpv = red.J @ pv
+    ps = -r3 - Jpv
+    plam = -r2 + sigma * r3 + sigma * Jpv
+    pz = mu / s - z - sigma * ps
+    return dict(pv=pv, ps=ps, plam=plam, pz=pz, sigma=sigma, K=K, rhs=rhs, r1=r1, r2=r2, r3=r3)
+
+
+def fraction_to_boundary(x: np.ndarray, p: np.ndarray, tau: float) -> float:
+    """Largest alpha in (0, 1] with x + alpha p >= (1 - tau) x (reading R9)."""
+    neg = p < 0
+    if not np.any(neg):
+        return 1.0
+    return float(min(1.0, np.min(-tau * x[neg] / p[neg])))
+
+
+def kkt_error(red: Reduced, v, s, lam, z, mu):
+    """E_mu = max(|r1|, |r3|, |lambda - z|, |s z - mu|) in the inf-norm (reading R11)."""
+    r1 = red.H @ v + red.h + red.J.T @ lam
+    r3 = red.J @ v - red.d + s
+    parts = [np.max(np.abs(r1), initial=0.0), np.max(np.abs(r3), initial=0.0),
+             np.max(np.abs(lam - z), initial=0.0), np.max(np.abs(s * z - mu), initial=0.0)]
+    return float(max(parts)), parts
+
+
+@dataclass
+class Result:
+    status: int
+    iters: int
+    v: np.ndarray
+    s: np.ndarray
+    lam: np.ndarray
+    z: np.ndarray
+    mu: float
+    obj: float
+    primal_res: float
+    dual_res: float
+    compl_res: float
+    gap: float
+    x: np.ndarray
+    history: list = field(default_factory=list)
+
+
+def initial_point(red: Reduced, mu0: float = MU_INIT):
+    """Reading R7."""
+    n = red.H.shape[0]
+    v = np.zeros(n)
+    s = np.maximum(red.d - red.J @ v, S_INIT_MIN)
+    lam = mu0 / s
+    z = lam.copy()
+    return v, s, lam, z
+
+
+def solve(prob, tol: float = 1e-8, max_iter: int = 200, red: Reduced | None = None,
+          callback=None, record: bool = False) -> Result:
+    """Algorithm 1 (condensed-space interior-point method) with readings R7-R11."""
+    if red is None:
+        red = reduce_problem(prob)
+    mu = MU_INIT
+    mu_min = tol / 10.0
+    v, s, lam, z = initial_point(red, mu)
+    history = []
+    status, k = STATUS_MAX_ITER, 0
+    for k in range(max_iter + 1):
+        e0, parts0 = kkt_error(red, v, s, lam, z, 0.0)
+        if e0 <= tol:
+            status = STATUS_CONVERGED
+            break
+        if k == max_iter:
+            status = STATUS_MAX_ITER
+            break
+        # barrier update (reading R8)
+        while mu > mu_min:
+            emu, _ = kkt_error(red, v, s, lam, z, mu)
+            if emu > KAPPA_EPS * mu:
+                break
+            mu = max(mu_min, min(KAPPA_MU * mu, mu ** THETA_MU))
+        tau = max(TAU_MIN, 1.0 - mu)
+        step = condensed_step(red, v, s, lam, z, mu)
+        alpha = fraction_to_boundary(s, step["ps"], tau)
+        alpha_z = fraction_to_boundary(z, step["pz"], tau)
+        if callback is not None:
+            callback(dict(k=k, v=v, s=s, lam=lam, z=z, mu=mu, tau=tau, alpha=alpha,
+                          alpha_z=alpha_z, **step))
+        if record:
+            history.append(dict(k=k, mu=mu, alpha=alpha, alpha_z=alpha_z, err=e0))
+        if alpha < ALPHA_MIN:
+            status = STATUS_SMALL_STEP
+            break
+        v = v + alpha * step["pv"]
+        s = s + alpha * step["ps"]
+        lam = lam + alpha * step["plam"]
+        z = z + alpha_z * step["pz"]
+        # safeguard (reading R10)
+        z = np.minimum(np.maximum(z, mu / (KAPPA_SIGMA * s)), KAPPA_SIGMA * mu / s)
+    r1 = red.H @ v + red.h + red.J.T @ lam
+    r3 = red.J @ v - red.d + s
+    x = red.c + red.Gamma @ v
+    return Result(status=status, iters=k, v=v, s=s, lam=lam, z=z, mu=mu,
+                  obj=objective(red, v), primal_res=float(np.max(np.abs(r3), initial=0.0)),
+                  dual_res=float(np.max(np.abs(r1), initial=0.0)),
+                  compl_res=float(np.max(np.abs(s * z), initial=0.0)), gap=float(s @ z),
+                  x=x, history=history)
+
+
+def simulate(prob, u: np.ndarray) -> np.ndarray:
+    """Forward simulation x_{t+1} = A x_t + B u_t, t = 0..N-1 (eqn. (dyn) with w = 0).
+
+    Returns the states x_1..x_N stacked (length ns N).
+    """
+    ns, nu, N = prob.A.shape[0], prob.B.shape[1], int(prob.N)
+    x = prob.x0.copy()
+    out = []
+    for t in range(N):
+        x = prob.A @ x + prob.B @ u[t * nu:(t + 1) * nu]
+        out.append(x)
+    return np.concatenate(out)
+
+
+def sparse_objective(prob, u: np.ndarray) -> float:
+    """Objective of eqn. (sparse) with the 1/2 convention (reading R1), by simulation."""
+    ns, nu, N = prob.A.shape[0], prob.B.shape[1], int(prob.N)
+    xs = simulate(prob, u)
+    f = 0.5 * prob.x0 @ prob.Q @ prob.x0
+    for t in range(N):
+        ut = u[t * nu:(t + 1) * nu]
+        f += 0.5 * ut @ prob.R @ ut
+    for t in range(1, N + 1):
+        xt = xs[(t - 1) * ns:t * ns]
+        W = prob.Qf if t == N else prob.Q
+        f += 0.5 * xt @ W @ xt
+    return float(f)

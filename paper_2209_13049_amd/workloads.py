@@ -1,0 +1,217 @@
+"""Seeded synthetic problem generators for linear-quadratic MPC (problem data only).
+
+This module builds the data of the sparse linear-quadratic MPC problem (the paper's
+Section 2, eqn. (sparse)): the dynamics A, B, the weights Q, R, Q_f, the bounds and the
+initial state. It holds none of the method's arithmetic (no state elimination, no
+interior-point step); both the HIP library's tests and the CPU oracle take their inputs
+from here.
+
+Workloads are explicit-Euler finite-difference heat equations with boundary or distributed
+actuators, the family of the paper's Section 4 (a PDE temperature-control problem whose
+states are interior grid temperatures and whose inputs act through the boundary).
+
+Seeds: ``numpy.random.default_rng([config_id, instance_id])``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "LQProblem",
+    "heat1d",
+    "heat2d",
+    "heat1d_config",
+    "batch_instances",
+    "smooth_x0",
+    "CONFIG_SMALL",
+    "CONFIG_1D",
+    "CONFIG_2D",
+]
+
+
+@dataclass
+class LQProblem:
+    """Data of eqn. (sparse) with S = 0, E = F = 0, w = 0 (feedback gain K = 0).
+
+    Arrays are float64, row-major.  ``A`` is ns x ns, ``B`` ns x nu, ``Q``/``Qf`` ns x ns,
+    ``R`` nu x nu, ``xl``/``xu`` length ns, ``ul``/``uu`` length nu, ``x0`` length ns.
+    ``N`` is the horizon (the paper's T).  Infinite bounds mean "no bound".
+    """
+
+    A: np.ndarray
+    B: np.ndarray
+    Q: np.ndarray
+    R: np.ndarray
+    Qf: np.ndarray
+    xl: np.ndarray
+    xu: np.ndarray
+    ul: np.ndarray
+    uu: np.ndarray
+    x0: np.ndarray
+    N: int
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ns(self) -> int:
+        return int(self.A.shape[0])
+
+    @property
+    def nu(self) -> int:
+        return int(self.B.shape[1])
+
+    @property
+    def n(self) -> int:
+        return self.nu * self.N
+
+    def with_x0(self, x0) -> "LQProblem":
+        return LQProblem(self.A, self.B, self.Q, self.R, self.Qf, self.xl, self.xu, self.ul,
+                         self.uu, np.ascontiguousarray(x0, dtype=np.float64), self.N,
+                         self.name, dict(self.meta))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def heat1d_dynamics(ns: int, nu: int, r: float = 0.25, amp: float = 0.1):
+    """1-D explicit-Euler heat step with zero Dirichlet ends and Gaussian-bump actuators.
+
+    A = tridiag(r, 1 - 2r, r); B[i, j] = amp * exp(-0.5 ((i - c_j) / w)^2) with
+    c_j = (j + 1/2) ns / nu - 1/2 and w = ns / (4 nu).
+    """
+    A = np.zeros((ns, ns))
+    idx = np.arange(ns)
+    A[idx, idx] = 1.0 - 2.0 * r
+    A[idx[1:], idx[:-1]] = r
+    A[idx[:-1], idx[1:]] = r
+    c = (np.arange(nu) + 0.5) * ns / nu - 0.5
+    w = ns / (4.0 * nu)
+    B = amp * np.exp(-0.5 * ((idx[:, None] - c[None, :]) / w) ** 2)
+    return _f64(A), _f64(B)
+
+
+def heat1d(ns: int, nu: int, N: int, seed=(0, 0), *, r: float = 0.25, amp: float = 0.1,
+           q: float = 1.0, rw: float = 1e-2, xb: float = 0.5, ub: float = 1.0,
+           x0_range=(-0.4, 0.4), xu=None, xl=None, name: str = "") -> LQProblem:
+    """1-D heat problem: Q = q I, R = rw I, Q_f = Q, |x| <= xb, |u| <= ub, x0 ~ U(x0_range)."""
+    A, B = heat1d_dynamics(ns, nu, r, amp)
+    rng = np.random.default_rng(list(seed))
+    x0 = rng.uniform(x0_range[0], x0_range[1], size=ns)
+    xu_v = np.full(ns, xb if xu is None else xu)
+    xl_v = np.full(ns, -xb if xl is None else xl)
+    Q = q * np.eye(ns)
+    return LQProblem(A=A, B=B, Q=_f64(Q), R=_f64(rw * np.eye(nu)), Qf=_f64(Q),
+                     xl=_f64(xl_v), xu=_f64(xu_v), ul=_f64(np.full(nu, -ub)),
+                     uu=_f64(np.full(nu, ub)), x0=_f64(x0), N=int(N),
+                     name=name or f"heat1d_ns{ns}_nu{nu}_N{N}",
+                     meta={"seed": list(seed)})
+
+
+def heat2d_dynamics(g: int, nu_per_edge: int = 5, r: float = 0.2):
+    """2-D 5-point explicit heat step on a g x g interior grid with boundary actuators.
+
+    Each of the 4 edges is cut into ``nu_per_edge`` equal segments; an actuator sets the
+    Dirichlet value of one segment, so B[p, i] = r for every interior node p next to a
+    boundary node of segment i (corner nodes touch two edges).
+    """
+    ns = g * g
+    A = np.zeros((ns, ns))
+
+    def node(ix, iy):
+        return ix * g + iy
+
+    for ix in range(g):
+        for iy in range(g):
+            p = node(ix, iy)
+            A[p, p] = 1.0 - 4.0 * r
+            for jx, jy in ((ix - 1, iy), (ix + 1, iy), (ix, iy - 1), (ix, iy + 1)):
+                if 0 <= jx < g and 0 <= jy < g:
+                    A[p, node(jx, jy)] = r
+    if g % nu_per_edge:
+        raise ValueError("grid size must be a multiple of the segments per edge")
+    seg = g // nu_per_edge
+    nu = 4 * nu_per_edge
+    B = np.zeros((ns, nu))
+    for k in range(g):
+        s = k // seg
+        B[node(0, k), 0 * nu_per_edge + s] += r          # edge x = 0
+        B[node(g - 1, k), 1 * nu_per_edge + s] += r      # edge x = L
+        B[node(k, 0), 2 * nu_per_edge + s] += r          # edge y = 0
+        B[node(k, g - 1), 3 * nu_per_edge + s] += r      # edge y = L
+    return _f64(A), _f64(B)
+
+
+def heat2d(g: int = 70, nu_per_edge: int = 5, N: int = 100, seed=(2, 0), *, r: float = 0.2,
+           q: float = 1.0, rw: float = 1e-2, xb: float = 0.5, ub: float = 1.0,
+           x0_range=(-0.4, 0.4), name: str = "") -> LQProblem:
+    A, B = heat2d_dynamics(g, nu_per_edge, r)
+    ns, nu = B.shape
+    rng = np.random.default_rng(list(seed))
+    x0 = rng.uniform(x0_range[0], x0_range[1], size=ns)
+    Q = q * np.eye(ns)
+    return LQProblem(A=A, B=B, Q=_f64(Q), R=_f64(rw * np.eye(nu)), Qf=_f64(Q),
+                     xl=_f64(np.full(ns, -xb)), xu=_f64(np.full(ns, xb)),
+                     ul=_f64(np.full(nu, -ub)), uu=_f64(np.full(nu, ub)), x0=_f64(x0),
+                     N=int(N), name=name or f"heat2d_{g}x{g}_nu{nu}_N{N}",
+                     meta={"seed": list(seed)})
+
+
+# Named workloads (sizes of the benchmark and parity cases).
+CONFIG_SMALL = dict(ns=50, nu=5, N=10)       # K is 50 x 50, 500 state rows
+CONFIG_1D = dict(ns=1000, nu=10, N=50)       # K is 500 x 500, 50,000 state rows
+CONFIG_2D = dict(g=70, nu_per_edge=5, N=100)  # K is 2000 x 2000, 490,000 state rows
+
+
+def heat1d_config(which: str = "1d", instance: int = 0, **kw) -> LQProblem:
+    """The named 1-D workloads: 'small' (config id 0) and '1d' (config id 1)."""
+    if which == "small":
+        return heat1d(**CONFIG_SMALL, seed=(0, instance), **kw)
+    if which == "1d":
+        return heat1d(**CONFIG_1D, seed=(1, instance), **kw)
+    raise ValueError(which)
+
+
+def batch_instances(count: int = 512, seed: int = 3, ns_range=(100, 2000), nu_range=(2, 16),
+                    N_range=(16, 64)) -> list:
+    """Independent 1-D heat instances of uneven size for batched solves.
+
+    ns ~ U{ns_range}, nu ~ U{nu_range}, N ~ U{N_range}, x^u = -x^l ~ U(0.45, 0.6),
+    u^u = -u^l ~ U(0.5, 1.5), x0 ~ U(-0.4, 0.4); instance i uses default_rng([seed, i]).
+    """
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng([seed, i])
+        ns = int(rng.integers(ns_range[0], ns_range[1] + 1))
+        nu = int(rng.integers(nu_range[0], nu_range[1] + 1))
+        N = int(rng.integers(N_range[0], N_range[1] + 1))
+        xb = float(rng.uniform(0.45, 0.6))
+        ub = float(rng.uniform(0.5, 1.5))
+        A, B = heat1d_dynamics(ns, nu)
+        x0 = rng.uniform(-0.4, 0.4, size=ns)
+        Q = np.eye(ns)
+        out.append(LQProblem(A=A, B=B, Q=Q, R=1e-2 * np.eye(nu), Qf=Q.copy(),
+                             xl=np.full(ns, -xb), xu=np.full(ns, xb), ul=np.full(nu, -ub),
+                             uu=np.full(nu, ub), x0=_f64(x0), N=N,
+                             name=f"batch{seed}_{i}", meta={"seed": [seed, i]}))
+    return out
+
+
+def smooth_x0(ns: int, count: int, seed: int = 4, amp: float = 0.4, modes: int = 8) -> np.ndarray:
+    """Smooth random initial temperature fields, one per row (count x ns).
+
+    f = sum_k a_k sin(k pi (i + 1) / (ns + 1)), a_k ~ N(0, k^-2), k = 1..modes;
+    x0 = rho * amp * f / max|f| with rho ~ U(0, 1].
+    """
+    rng = np.random.default_rng([seed, ns])
+    i = np.arange(ns)
+    k = np.arange(1, modes + 1)
+    basis = np.sin(np.outer(k, (i + 1)) * np.pi / (ns + 1))      # modes x ns
+    a = rng.normal(size=(count, modes)) / k[None, :]
+    f = a @ basis
+    rho = 1.0 - rng.uniform(0.0, 1.0, size=count)                  # (0, 1]
+    scale = np.max(np.abs(f), axis=1)
+    scale[scale == 0] = 1.0
+    return _f64(rho[:, None] * amp * f / scale[:, None])

@@ -1,0 +1,149 @@
+"""Planted mistakes in the oracle must be caught by the pins (CPU only).
+
+Each case edits one expression of ``oracle/condensed_ipm.py`` in memory (a dropped term, a
+wrong sign, an off-by-one power, a transposed operand, a wrong constant), loads the edited
+source as a separate module and runs the independent checks of ``test_oracle_pins`` against
+it.  At least one check must fail for every mutant; the unedited source passes them all.
+"""
+import os
+import sys
+import types
+
+import numpy as np
+import pytest
+
+import brute_force as bf
+from paper_2209_13049_amd import workloads as W
+from test_oracle_pins import random_stable, _binding_case, _pairs, _interior_point
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
+                   "condensed_ipm.py")
+
+MUTATIONS = {
+    "gamma_power_off_by_one": ("Gamma[(t - 1) * ns:t * ns, j * nu:(j + 1) * nu] = G[t - 1 - j]",
+                               "Gamma[(t - 1) * ns:t * ns, j * nu:(j + 1) * nu] = G[max(t - 2 - j, 0)]"),
+    "gamma_transposed_power": ("out.append(A @ out[-1])", "out.append(A.T @ out[-1])"),
+    "terminal_weight_dropped": ("W = Qf if t == N else Q", "W = Q"),
+    "h0_half_dropped": ("h0 = 0.5 * prob.x0 @ Q @ prob.x0 + 0.5 * c @ qbar_times(c)",
+                        "h0 = 0.5 * c @ qbar_times(c)"),
+    "rhs_sigma_r3_sign": ("rhs = -r1 + red.J.T @ r2 - red.J.T @ (sigma * r3)",
+                          "rhs = -r1 + red.J.T @ r2 + red.J.T @ (sigma * r3)"),
+    "rhs_r2_dropped": ("rhs = -r1 + red.J.T @ r2 - red.J.T @ (sigma * r3)",
+                       "rhs = -r1 - red.J.T @ (sigma * r3)"),
+    "plam_sigma_r3_dropped": ("plam = -r2 + sigma * r3 + sigma * Jpv", "plam = -r2 + sigma * Jpv"),
+    "pz_sign": ("pz = mu / s - z - sigma * ps", "pz = mu / s - z + sigma * ps"),
+    "ps_sign": ("ps = -r3 - Jpv", "ps = -r3 + Jpv"),
+    "sigma_inverted": ("sigma = z / s\n    r1, r2, r3", "sigma = s / z\n    r1, r2, r3"),
+    "ftb_no_tau": ("return float(min(1.0, np.min(-tau * x[neg] / p[neg])))",
+                   "return float(min(1.0, np.min(-x[neg] / p[neg])))"),
+    "lower_state_rows_sign": ("d_all = np.concatenate([xu - c, c - xl, uu, -ul])",
+                              "d_all = np.concatenate([xu - c, c + xl, uu, -ul])"),
+    "r1_lambda_dropped": ("r1 = red.H @ v + red.h + red.J.T @ lam\n    r2",
+                          "r1 = red.H @ v + red.h\n    r2"),
+    "alpha_z_for_lambda": ("lam = lam + alpha * step[\"plam\"]", "lam = lam + alpha_z * step[\"plam\"]"),
+}
+
+
+def load_variant(name=None):
+    src = open(SRC).read()
+    if name is not None:
+        old, new = MUTATIONS[name]
+        assert src.count(old) >= 1, f"mutation anchor for {name} not found"
+        src = src.replace(old, new, 1)
+    mod = types.ModuleType(f"oracle_variant_{name}")
+    sys.modules[mod.__name__] = mod        # dataclasses look their module up here
+    exec(compile(src, SRC, "exec"), mod.__dict__)
+    return mod
+
+
+def check_simulation(m):
+    p = random_stable(4, 2, 4, 1)
+    red = m.reduce_problem(p)
+    v = np.random.default_rng(0).normal(size=p.n)
+    np.testing.assert_allclose(red.c + red.Gamma @ v, m.simulate(p, v), rtol=1e-12, atol=1e-12)
+
+
+def check_objective(m):
+    p = random_stable(3, 2, 3, 2)
+    red = m.reduce_problem(p)
+    v = np.random.default_rng(1).normal(size=p.n)
+    assert abs(m.objective(red, v) - m.sparse_objective(p, v)) <= 1e-12 * 10
+
+
+def check_full_space(m):
+    p = random_stable(3, 1, 3, 1)
+    red = m.reduce_problem(p)
+    v, s, lam, z, mu = _interior_point(red, 1)
+    st = m.condensed_step(red, v, s, lam, z, mu)
+    pu, ps, plam, pz = bf.full_space_step(p, v, s, lam, z, mu)
+    np.testing.assert_allclose(st["pv"], pu, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(st["ps"], ps, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(st["plam"], plam, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(st["pz"], pz, rtol=1e-9, atol=1e-9)
+
+
+def check_ftb(m):
+    s = np.array([1.0, 2.0, 0.5, 3.0])
+    p = np.array([-2.0, 1.0, -0.1, -0.5])
+    assert abs(m.fraction_to_boundary(s, p, 0.99) - 0.495) <= 1e-15
+
+
+def check_riccati(m):
+    p = random_stable(4, 2, 6, 1, bound_x=1e3, bound_u=1e3)
+    r = m.solve(p, max_iter=60)
+    u_ric, f_ric = bf.riccati(p)
+    assert r.status == 0
+    assert np.max(np.abs(r.v - u_ric)) <= 1e-7 * max(1.0, np.max(np.abs(u_ric)))
+
+
+def check_active_set(m):
+    for seed, kind in ((40, "u"), (40, "x")):
+        p = _binding_case(seed, kind)
+        red = m.reduce_problem(p)
+        r = m.solve(p, max_iter=60)
+        assert r.status == 0
+        v_ex, _ = bf.active_set(red.H, red.h, red.J, red.d, _pairs(red, 2, 1, 3))
+        f_ex = m.objective(red, v_ex)
+        assert r.obj >= f_ex - 1e-12 and r.obj - f_ex <= r.gap + 1e-12
+
+
+def check_tight_converges(m):
+    p = W.heat1d(30, 3, 6, seed=(0, 1), xu=0.05, x0_range=(-0.4, 0.04))
+    r = m.solve(p, max_iter=60)
+    assert r.status == 0 and r.primal_res <= 1e-8 and r.dual_res <= 1e-8
+
+
+def check_linear_residual_decay(m):
+    """r1 and r3 are affine in (v, lambda, s): a step of length alpha shrinks both by
+    exactly (1 - alpha)."""
+    p = W.heat1d(20, 2, 5, seed=(5, 0), xu=0.05, x0_range=(0.045, 0.05))
+    log = []
+    m.solve(p, callback=log.append, max_iter=60)
+    for a, b in zip(log[:-1], log[1:]):
+        np.testing.assert_allclose(b["r3"], (1 - a["alpha"]) * a["r3"], atol=1e-12)
+        np.testing.assert_allclose(b["r1"], (1 - a["alpha"]) * a["r1"], atol=1e-10)
+
+
+CHECKS = [check_simulation, check_objective, check_full_space, check_ftb, check_riccati,
+          check_active_set, check_tight_converges, check_linear_residual_decay]
+
+
+def run_checks(m):
+    failed = []
+    for chk in CHECKS:
+        try:
+            chk(m)
+        except Exception:
+            failed.append(chk.__name__)
+    return failed
+
+
+def test_unmutated_oracle_passes_all_checks():
+    assert run_checks(load_variant(None)) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name):
+    with np.errstate(all="ignore"):
+        failed = run_checks(load_variant(name))
+    assert failed, f"mutation {name} escaped every pin"
