@@ -1,0 +1,170 @@
+/*
+ * condmpc -- condensed-space interior-point method for linear-quadratic MPC on MI355X.
+ *
+ * C ABI of the hot path of Cole, Shin, Pacaud, Zavala and Anitescu, "Exploiting GPU/SIMD
+ * architectures for solving linear-quadratic MPC problems" (arXiv 2209.13049):
+ *   - Section 2, eqns. (sparse), (x_def), (dense): the problem data and the elimination of
+ *     the states, which leaves a dense QP  min 1/2 v'Hv + h'v + h0  s.t.  Jv <= d  in the
+ *     n = nu*N controls;
+ *   - Section 3, eqns. (aug_KKT), (cond_KKT) and Algorithm 1: each interior-point iteration
+ *     forms K = H + J' Sigma_s J, factors it by dense Cholesky and recovers the step.
+ *
+ * Conventions (all functions):
+ *   - Matrices are row-major float64.  A host pointer is read or written synchronously; a
+ *     "device" pointer must address MI355X memory that stays valid until the call's work on
+ *     the stream has finished.
+ *   - The library copies every input it keeps.  A cmpc_problem owns all device memory it
+ *     allocates and releases it in cmpc_problem_destroy.
+ *   - Work is issued on the HIP stream given at creation (NULL = the default stream).
+ *   - Return value: 0 on success, a positive solver outcome, or a negative error code
+ *     (below).  cmpc_last_error() gives a message for the calling thread's last error.
+ *   - The library has no global state besides per-thread error messages.
+ *
+ * Readings of the paper that the library implements (Algorithm 1 leaves them open):
+ *   objective with 1/2 on every quadratic term; Q_f = Q when NULL; state bounds for
+ *   t = 1..N only (x_0 is data); feedback gain K = 0 (v = u); right-hand side
+ *   -r1 + J'r2 - J'Sigma r3; start mu = 0.1, v = 0, s = max(d - Jv, 1e-2),
+ *   lambda = z = mu/s; monotone barrier rule (kappa_eps = 10, kappa_mu = 0.2,
+ *   theta_mu = 1.5, mu_min = tol/10); fraction-to-boundary step lengths alpha (v, s,
+ *   lambda) and alpha_z (z) with tau = max(0.99, 1 - mu); z safeguarded into
+ *   [mu/(1e10 s), 1e10 mu/s]; stop when max(|r1|, |r3|, |lambda - z|, |s z|) <= tol.
+ */
+#ifndef CONDMPC_H
+#define CONDMPC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define CMPC_OK 0               /* converged to tol */
+#define CMPC_MAX_ITER 1         /* iteration limit reached */
+#define CMPC_SMALL_STEP 2       /* step length below 1e-14 */
+#define CMPC_ERR_INVALID (-1)   /* bad argument or dimensions */
+#define CMPC_ERR_NONFINITE (-2) /* NaN or Inf where a finite number is required */
+#define CMPC_ERR_X0_BOUNDS (-3) /* x0 violates a state bound (the t = 0 rows) */
+#define CMPC_ERR_CHOLESKY (-4)  /* K not numerically positive definite */
+#define CMPC_ERR_HIP (-5)       /* HIP runtime error */
+#define CMPC_ERR_NOMEM (-6)     /* device allocation failed */
+
+/* ---- precision of the SYRK that forms K (Section 3 forms K in one precision; the
+ *      mixed modes are this library's extension, with FP64 Cholesky and FP64 iterative
+ *      refinement against the exact K) ---- */
+#define CMPC_FP64 0
+#define CMPC_FP32_SYRK 1
+#define CMPC_BF16_SYRK 2
+
+typedef struct cmpc_problem cmpc_problem;
+
+/* Problem data of eqn. (sparse) restricted to S = 0, E = F = 0, w = 0 (host pointers).
+ * A: ns x ns, B: ns x nu, Q, Qf: ns x ns (Qf may be NULL -> Q), R: nu x nu symmetric
+ * positive definite.  xl, xu: length ns; ul, uu: length nu; an infinite bound drops its
+ * rows (+INFINITY upper, -INFINITY lower).  N >= 1 is the horizon (the paper's T). */
+typedef struct {
+  int ns, nu, N;
+  const double *A, *B, *Q, *R, *Qf;
+  const double *xl, *xu, *ul, *uu;
+} cmpc_lq_desc;
+
+typedef struct {
+  double tol;        /* KKT tolerance of the stopping test (default 1e-8) */
+  int max_iter;      /* iteration limit (default 200) */
+  int precision;     /* CMPC_FP64 (default), CMPC_FP32_SYRK or CMPC_BF16_SYRK */
+  int max_refine;    /* mixed modes: refinement steps per solve (default 5) */
+  double mu_switch;  /* mixed modes: use the FP64 SYRK once mu < mu_switch (default 1e-6) */
+  int check_every;   /* read the convergence flag every this many iterations (default 1) */
+} cmpc_options;
+
+typedef struct {
+  int status;          /* CMPC_OK, CMPC_MAX_ITER, CMPC_SMALL_STEP or a negative error */
+  int iters;           /* interior-point iterations taken */
+  int precision_switch_iter; /* mixed modes: first FP64-SYRK iteration (-1 if none) */
+  int refine_steps;    /* mixed modes: refinement steps over the solve */
+  double obj;          /* 1/2 v'Hv + h'v + h0 at the returned iterate */
+  double primal_res;   /* |Jv - d + s|_inf */
+  double dual_res;     /* |Hv + h + J'lambda|_inf */
+  double compl_res;    /* |s z|_inf */
+  double mu;           /* final barrier parameter */
+  double gap;          /* s'z */
+  double ms_total;     /* wall time of the solve on the stream, milliseconds */
+} cmpc_result;
+
+/* Default options (values above). */
+void cmpc_default_options(cmpc_options* opts);
+
+/* Build the reduced problem of Section 2: G_k = A^k B, the packed block-Toeplitz
+ * Gamma (block (t, j) = A^(t-1-j) B, t = 1..N, j < t), and H = Gamma'Qbar Gamma + Rbar.
+ * stream: a hipStream_t (NULL = default).  On success *out owns device memory of about
+ * 8 (ns nu N(N+1)/2 + 3 (nu N)^2 + 8 ns N) bytes.  Errors: CMPC_ERR_INVALID (dimensions,
+ * NULL data), CMPC_ERR_NONFINITE, CMPC_ERR_NOMEM, CMPC_ERR_HIP. */
+int cmpc_problem_create(const cmpc_lq_desc* desc, void* stream, cmpc_problem** out);
+
+/* Release all device memory of the problem (NULL is ignored).  Synchronises its stream. */
+void cmpc_problem_destroy(cmpc_problem* p);
+
+/* n = nu N (size of K), mx = ns N (rows of Gamma), m = 2 mx + 2 n (inequality rows of
+ * eqn. (dense) before rows with infinite bounds are dropped).  Any output may be NULL. */
+int cmpc_problem_dims(const cmpc_problem* p, int* n, int* mx, int* m);
+
+/* Set the initial state (length ns; host or device pointer by on_device) and form the
+ * x0-dependent data of eqn. (dense): c = (A^t x0)_{t=1..N}, h = Gamma'Qbar c,
+ * h0 = 1/2 x0'Q x0 + 1/2 c'Qbar c, d = [xu - c; c - xl; uu; -ul].
+ * Errors: CMPC_ERR_NONFINITE, CMPC_ERR_X0_BOUNDS (x0 outside [xl, xu]). */
+int cmpc_set_x0(cmpc_problem* p, const double* x0, int on_device);
+
+/* Run Algorithm 1 from the start point above.  opts NULL = defaults.  res may be NULL.
+ * Returns the solver status (also in res->status). */
+int cmpc_solve(cmpc_problem* p, const cmpc_options* opts, cmpc_result* res);
+
+/* Copy out the last solve's controls u = v (length nu N) and, if x != NULL, the states
+ * x_1..x_N = c + Gamma v (length ns N).  Host or device pointers by on_device. */
+int cmpc_get_solution(const cmpc_problem* p, double* u, double* x, int on_device);
+
+/* Copy out the current iterate: v (n), s, lambda, z (m each, rows in the order
+ * [x <= xu | -x <= -xl | u <= uu | -u <= -ul]; rows with an infinite bound hold
+ * s = 1, lambda = z = 0).  Any output may be NULL. */
+int cmpc_get_iterate(const cmpc_problem* p, double* v, double* s, double* lam, double* z,
+                     int on_device);
+
+/* Copy the reduced problem to host memory for checking: H (n x n), h (n), h0 (1),
+ * d (m; rows with an infinite bound hold +INFINITY), c (mx), Gamma (mx x n dense,
+ * row-major, structural zeros written).  Any output may be NULL. */
+int cmpc_export_dense(const cmpc_problem* p, double* H, double* h, double* h0, double* d,
+                      double* c, double* Gamma);
+
+/* Form the condensed matrix of eqn. (cond_KKT), K = H + J' diag(sigma) J (the lower
+ * triangle; the strict upper triangle of K is left unchanged), for a given sigma >= 0
+ * (length m, device; sigma of a dropped row is ignored).  K: n x n device, leading
+ * dimension n.  precision selects the SYRK arithmetic (CMPC_FP64, CMPC_FP32_SYRK,
+ * CMPC_BF16_SYRK); H is always added in FP64. */
+int cmpc_form_condensed(cmpc_problem* p, const double* sigma, double* K, int precision);
+
+/* One Newton direction of Section 3 from a given interior iterate (all device pointers):
+ * v (n); s, lam, z (m, s > 0 and z > 0 on kept rows); barrier mu > 0; fraction tau.
+ * Writes p_v (n), p_s, p_lambda, p_z (m) and, to host memory, alphas[0] = alpha,
+ * alphas[1] = alpha_z (fraction-to-boundary lengths).  Uses the FP64 path.
+ * Errors: CMPC_ERR_CHOLESKY. */
+int cmpc_newton_step(cmpc_problem* p, const double* v, const double* s, const double* lam,
+                     const double* z, double mu, double tau, double* pv, double* ps,
+                     double* plam, double* pz, double* alphas);
+
+/* Dense Cholesky K = L L' in place (lower triangle of K, row-major, leading dimension
+ * ld >= n, device).  The strict upper triangle is not referenced.  *info (host, may be
+ * NULL) receives 0 or the 1-based column where a pivot was not positive, in which case
+ * CMPC_ERR_CHOLESKY is returned.  stream: hipStream_t (NULL = default).  Synchronises
+ * the stream. */
+int cmpc_potrf(double* K, int n, int ld, void* stream, int* info);
+
+/* Solve L L' x = b in place (b: n, device) with the factor from cmpc_potrf. */
+int cmpc_potrs(const double* L, int n, int ld, double* b, void* stream);
+
+/* Message of the calling thread's last error ("" if none). */
+const char* cmpc_last_error(void);
+
+/* Text for a status code. */
+const char* cmpc_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CONDMPC_H */

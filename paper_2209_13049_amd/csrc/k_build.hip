@@ -1,0 +1,228 @@
+// Setup kernels: the state elimination of Section 2 (eqn. (x_def)) and the x0-dependent
+// data of eqn. (dense).  They run once per problem or once per initial state, not per
+// interior-point iteration.
+#include "problem.hpp"
+
+namespace cmpc {
+
+// C (M x Nc, leading dimension ldc) = alpha * op(A) op(B) + beta * C with strided operands:
+// op(A)(i, k) = A[i * a_i + k * a_k], op(B)(k, j) = B[k * b_k + j * b_j].  16 x 16 output
+// tiles, 16-deep slabs staged in LDS.  Setup only (G_k = A G_{k-1}, general-Q Hessian).
+__global__ __launch_bounds__(256) void gemm_f64_kernel(int M, int Nc, int Kd, double alpha,
+                                                       const double* __restrict__ A, long long a_i,
+                                                       long long a_k, const double* __restrict__ B,
+                                                       long long b_k, long long b_j, double beta,
+                                                       double* __restrict__ C, long long ldc) {
+  __shared__ double As[16][17];
+  __shared__ double Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < Kd; k0 += 16) {
+    const int ia = blockIdx.y * 16 + ty, ka = k0 + tx;
+    As[ty][tx] = (ia < M && ka < Kd) ? A[ia * a_i + ka * a_k] : 0.0;
+    const int kb = k0 + ty, jb = blockIdx.x * 16 + tx;
+    Bs[ty][tx] = (kb < Kd && jb < Nc) ? B[kb * b_k + jb * b_j] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) acc = fma(As[ty][kk], Bs[kk][tx], acc);
+    __syncthreads();
+  }
+  if (i < M && j < Nc) {
+    double* cp = C + i * ldc + j;
+    *cp = alpha * acc + (beta == 0.0 ? 0.0 : beta * *cp);
+  }
+}
+
+int launch_gemm_f64(hipStream_t s, int M, int Nc, int Kd, double alpha, const double* A,
+                    long long a_i, long long a_k, const double* B, long long b_k, long long b_j,
+                    double beta, double* C, long long ldc) {
+  if (M <= 0 || Nc <= 0) return 0;
+  dim3 grid(ceil_div(Nc, 16), ceil_div(M, 16));
+  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, s, M, Nc, Kd, alpha, A, a_i, a_k, B,
+                     b_k, b_j, beta, C, ldc);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// Packed Gamma: block t (1..N) holds rows (t-1) ns + i, columns a = j nu + k < t nu, with
+// entry G_{t-1-j}[i][k] = (A^(t-1-j) B)[i][k]  (eqn. (x_def) with K = 0).
+__global__ void pack_gamma_kernel(const double* __restrict__ G, const long long* __restrict__ off,
+                                  double* __restrict__ Gam, int ns, int nu) {
+  const int t = blockIdx.y + 1;
+  const long long len = (long long)t * nu;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)ns * len) return;
+  const int i = (int)(e / len);
+  const int a = (int)(e - (long long)i * len);
+  const int j = a / nu, k = a - j * nu;
+  Gam[off[t - 1] + e] = G[((long long)(t - 1 - j) * ns + i) * nu + k];
+}
+
+int launch_pack_gamma(Problem& p) {
+  dim3 grid(ceil_div((long long)p.ns * p.N * p.nu, 256), p.N);
+  hipLaunchKernelGGL(pack_gamma_kernel, grid, dim3(256), 0, p.stream, p.G, p.goff, p.Gam, p.ns,
+                     p.nu);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// y = A x (A rows x cols, row-major): one wavefront per row, lanes stride the row.
+__global__ __launch_bounds__(256) void gemv_kernel(const double* __restrict__ A,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ y, int rows, int cols) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const double* a = A + (long long)row * cols;
+  double acc = 0.0;
+  for (int j = lane; j < cols; j += 64) acc = fma(a[j], x[j], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) y[row] = acc;
+}
+
+int launch_gemv(hipStream_t s, const double* A, const double* x, double* y, int rows, int cols) {
+  hipLaunchKernelGGL(gemv_kernel, dim3(ceil_div(rows, 4)), dim3(256), 0, s, A, x, y, rows, cols);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// out = Qbar in, Qbar = blockdiag(Q, ..., Q, Q_f) over t = 1..N (ns N rows).
+__global__ __launch_bounds__(256) void block_diag_kernel(const double* __restrict__ Q,
+                                                         const double* __restrict__ Qf,
+                                                         const double* __restrict__ in,
+                                                         double* __restrict__ out, int ns, int N) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= ns * N) return;
+  const int t = row / ns + 1, i = row - (t - 1) * ns;
+  const double* W = (t == N ? Qf : Q) + (long long)i * ns;
+  const double* x = in + (long long)(t - 1) * ns;
+  double acc = 0.0;
+  for (int j = lane; j < ns; j += 64) acc = fma(W[j], x[j], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) out[row] = acc;
+}
+
+__global__ void diag_weight_kernel(const double* __restrict__ q, const double* __restrict__ in,
+                                   double* __restrict__ out, int mx) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < mx) out[r] = q[r] * in[r];
+}
+
+int launch_block_diag_weight(Problem& p, const double* in, double* out) {
+  if (p.q_diag) {
+    hipLaunchKernelGGL(diag_weight_kernel, dim3(ceil_div(p.mx, 256)), dim3(256), 0, p.stream,
+                       p.qdiag, in, out, p.mx);
+  } else {
+    hipLaunchKernelGGL(block_diag_kernel, dim3(ceil_div(p.mx, 4)), dim3(256), 0, p.stream, p.Q,
+                       p.Qf, in, out, p.ns, p.N);
+  }
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// d = [xu - c; c - xl; uu; -ul]; an infinite bound gives an infinite entry (dropped row).
+__global__ void make_d_kernel(const double* __restrict__ c, const double* __restrict__ xl,
+                              const double* __restrict__ xu, const double* __restrict__ ul,
+                              const double* __restrict__ uu, double* __restrict__ d, int ns,
+                              int nu, int mx, int n) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < mx) {
+    const int i = r % ns;
+    d[r] = isinf(xu[i]) ? INFINITY : xu[i] - c[r];
+    d[mx + r] = isinf(xl[i]) ? INFINITY : c[r] - xl[i];
+  }
+  if (r < n) {
+    const int k = r % nu;
+    d[2 * mx + r] = isinf(uu[k]) ? INFINITY : uu[k];
+    d[2 * mx + n + r] = isinf(ul[k]) ? INFINITY : -ul[k];
+  }
+}
+
+int launch_make_d(Problem& p) {
+  const int len = p.mx > p.n ? p.mx : p.n;
+  hipLaunchKernelGGL(make_d_kernel, dim3(ceil_div(len, 256)), dim3(256), 0, p.stream, p.c, p.xl,
+                     p.xu, p.ul, p.uu, p.d, p.ns, p.nu, p.mx, p.n);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// h0 = 1/2 x0' (Q x0) + 1/2 c' (Qbar c); Q x0 is in tmp (ns), Qbar c in qc (mx).
+__global__ __launch_bounds__(256) void h0_kernel(const double* __restrict__ x0,
+                                                 const double* __restrict__ qx0,
+                                                 const double* __restrict__ c,
+                                                 const double* __restrict__ qc, int ns, int mx,
+                                                 IpmState* st) {
+  __shared__ double sh[4];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < ns; i += 256) a = fma(x0[i], qx0[i], a);
+  for (int r = threadIdx.x; r < mx; r += 256) b = fma(c[r], qc[r], b);
+  a = block_sum256(a, sh);
+  b = block_sum256(b, sh);
+  if (threadIdx.x == 0) st->h0 = 0.5 * a + 0.5 * b;
+}
+
+int launch_h0(Problem& p) {
+  // tmpn2 has room for max(n, ns) doubles
+  if (launch_gemv(p.stream, p.Q, p.x0, p.tmpn2, p.ns, p.ns)) return CMPC_ERR_HIP;
+  hipLaunchKernelGGL(h0_kernel, dim3(1), dim3(256), 0, p.stream, p.x0, p.tmpn2, p.c, p.qc, p.ns,
+                     p.mx, p.st);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// Hb = Rbar = blockdiag(R, ..., R) (n x n, full).
+__global__ void rbar_kernel(const double* __restrict__ R, double* __restrict__ Hb, int nu, int n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * n) return;
+  const int i = (int)(e / n), j = (int)(e - (long long)i * n);
+  double v = 0.0;
+  if (i / nu == j / nu) v = R[(i % nu) * nu + (j % nu)];
+  Hb[e] = v;
+}
+
+int launch_rbar(Problem& p, double* Hb) {
+  hipLaunchKernelGGL(rbar_kernel, dim3(ceil_div((long long)p.n * p.n, 256)), dim3(256), 0,
+                     p.stream, p.R, Hb, p.nu, p.n);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// H[j][i] = H[i][j] for i > j.
+__global__ void mirror_lower_kernel(double* __restrict__ H, int n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * n) return;
+  const int i = (int)(e / n), j = (int)(e - (long long)i * n);
+  if (j > i) H[e] = H[(long long)j * n + i];
+}
+
+int launch_mirror_lower(hipStream_t s, double* H, int n) {
+  hipLaunchKernelGGL(mirror_lower_kernel, dim3(ceil_div((long long)n * n, 256)), dim3(256), 0, s,
+                     H, n);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// Dense Gamma (mx x n) from the packed blocks, structural zeros written.
+__global__ void dense_gamma_kernel(const double* __restrict__ Gam,
+                                   const long long* __restrict__ off, double* __restrict__ out,
+                                   int ns, int nu, int N) {
+  const int n = nu * N;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)ns * N * n) return;
+  const long long r = e / n;
+  const int a = (int)(e - r * n);
+  const int t = (int)(r / ns) + 1, i = (int)(r - (long long)(t - 1) * ns);
+  const int len = t * nu;
+  out[e] = a < len ? Gam[off[t - 1] + (long long)i * len + a] : 0.0;
+}
+
+int launch_dense_gamma(Problem& p, double* dense) {
+  hipLaunchKernelGGL(dense_gamma_kernel, dim3(ceil_div((long long)p.mx * p.n, 256)), dim3(256), 0,
+                     p.stream, p.Gam, p.goff, dense, p.ns, p.nu, p.N);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+}  // namespace cmpc

@@ -1,0 +1,642 @@
+// Interior-point iteration kernels (Algorithm 1 of the paper) other than the formation and
+// factorisation of K.  All of them read the device-side IpmState and return at entry once
+// the solve is done, so a whole iteration can be queued (or graph-replayed) without a host
+// round trip.
+//
+// Rows of the inequality system J v <= d, with J = [Gamma; -Gamma; I; -I], are kept in the
+// order [x <= xu (mx) | -x <= -xl (mx) | u <= uu (n) | -u <= -ul (n)].  A "pair" is the
+// upper/lower couple of one bounded quantity: pair p < mx is state row p, pair mx + c is
+// control c.  Because the two rows of a pair share one row of Gamma (with opposite sign),
+// J' diag(sigma) J = Gamma' diag(sigma_up + sigma_lo) Gamma + diag(sigma_up + sigma_lo)_u
+// and J' y = Gamma' (y_up - y_lo) + (y_up - y_lo)_u.  A row whose bound is infinite has
+// d = +inf and takes no part (s = 1, lambda = z = 0, sigma = 0).
+#include "problem.hpp"
+
+namespace cmpc {
+
+constexpr double kKappaEps = 10.0, kKappaMu = 0.2, kThetaMu = 1.5, kKappaSigma = 1e10;
+constexpr double kTauMin = 0.99, kMuInit = 0.1, kSInitMin = 1e-2, kAlphaMin = 1e-14;
+
+int ipm_alloc_work(Problem& p) {
+  const size_t n = p.n, m = p.m, mx = p.mx;
+  const size_t nmax = (size_t)(p.n > p.ns ? p.n : p.ns);
+  double** vecs_n[] = {&p.v, &p.pv, &p.rhs, &p.Du, &p.Hv, &p.h, &p.tmpn};
+  for (double** q : vecs_n) CMPC_HIP(hipMalloc(q, sizeof(double) * n));
+  CMPC_HIP(hipMalloc(&p.tmpn2, sizeof(double) * nmax));
+  double** vecs_m[] = {&p.s, &p.lam, &p.z, &p.ps, &p.plam, &p.pz, &p.d};
+  for (double** q : vecs_m) CMPC_HIP(hipMalloc(q, sizeof(double) * m));
+  double** vecs_mx[] = {&p.gv, &p.gpv, &p.c, &p.qc, &p.Dx, &p.tmpmx};
+  for (double** q : vecs_mx) CMPC_HIP(hipMalloc(q, sizeof(double) * mx));
+  CMPC_HIP(hipMalloc(&p.x0, sizeof(double) * p.ns));
+  CMPC_HIP(hipMalloc(&p.wx, sizeof(double) * 3 * mx));
+  CMPC_HIP(hipMalloc(&p.wu, sizeof(double) * 3 * n));
+  CMPC_HIP(hipMalloc(&p.gt, sizeof(double) * 3 * n));
+  p.n_prep_blocks = ceil_div((long long)mx + n, 256);
+  p.n_step_blocks = p.n_prep_blocks;
+  CMPC_HIP(hipMalloc(&p.norm_part, sizeof(double) * 4 * p.n_prep_blocks));
+  CMPC_HIP(hipMalloc(&p.alpha_part, sizeof(double) * 2 * p.n_step_blocks));
+  int rc = 128;
+  while ((long long)ceil_div(p.ns, rc) * p.N > 2048 && rc < 4096) rc *= 2;
+  p.gt_rows = rc;
+  p.gt_chunks = ceil_div(p.ns, rc) * p.N;
+  CMPC_HIP(hipMalloc(&p.gt_part, sizeof(double) * 3 * n * (size_t)p.gt_chunks));
+  CMPC_HIP(hipMalloc(&p.st, sizeof(IpmState)));
+  CMPC_HIP(hipMemset(p.st, 0, sizeof(IpmState)));
+  return 0;
+}
+
+// ---------------------------------------------------------------- Gamma' W  (NV vectors)
+// Partial sums of chunk (t, q): rows [q rc, (q+1) rc) of row block t, columns a < t nu.
+template <int NV>
+__global__ __launch_bounds__(256) void gamma_t_partial_kernel(
+    const double* __restrict__ Gam, const long long* __restrict__ off,
+    const double* __restrict__ W, long long wstride, double* __restrict__ part, int ns, int nu,
+    int n, int rc, int cpb, const int* __restrict__ done) {
+  __shared__ double wsh[NV][512];
+  if (done != nullptr && *done) return;
+  const int chunk = blockIdx.x;
+  const int t = chunk / cpb + 1, q = chunk - (t - 1) * cpb;
+  const int len = t * nu;
+  const int r0 = q * rc, r1 = min(ns, r0 + rc);
+  double acc[NV][8];
+  const int ncol_iter = (len + 255) / 256;  // <= 8 handled per pass
+  for (int cbase = 0; cbase < ncol_iter; cbase += 8) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[k][u] = 0.0;
+    for (int rr = r0; rr < r1; rr += 512) {
+      const int rend = min(r1, rr + 512);
+      __syncthreads();
+      for (int r = rr + threadIdx.x; r < rend; r += 256)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) wsh[k][r - rr] = W[k * wstride + (long long)(t - 1) * ns + r];
+      __syncthreads();
+      for (int r = rr; r < rend; ++r) {
+        const double* row = Gam + off[t - 1] + (long long)r * len;
+        double wv[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) wv[k] = wsh[k][r - rr];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int a = (cbase + u) * 256 + threadIdx.x;
+          if (cbase + u < ncol_iter && a < len) {
+            const double g = row[a];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) acc[k][u] = fma(g, wv[k], acc[k][u]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int a = (cbase + u) * 256 + threadIdx.x;
+      if (cbase + u < ncol_iter && a < len)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) part[((long long)chunk * NV + k) * n + a] = acc[k][u];
+    }
+  }
+}
+
+// out[k][a] = sum over chunks whose block covers column a (fixed order).
+template <int NV>
+__global__ __launch_bounds__(256) void gamma_t_reduce_kernel(const double* __restrict__ part,
+                                                             double* __restrict__ out, int n,
+                                                             int nu, int cpb, int nchunks,
+                                                             const int* __restrict__ done) {
+  __shared__ double sh[4][NV][64];
+  if (done != nullptr && *done) return;
+  const int a = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  if (a < n) {
+    const int tmin = a / nu + 1;  // first block with t nu > a
+    const int c0 = (tmin - 1) * cpb;
+    for (int ch = c0 + g; ch < nchunks; ch += 4)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) acc[k] += part[((long long)ch * NV + k) * n + a];
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) sh[g][k][threadIdx.x & 63] = acc[k];
+  __syncthreads();
+  if (g == 0 && a < n) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int l = threadIdx.x & 63;
+      out[(long long)k * n + a] = (sh[0][k][l] + sh[1][k][l]) + (sh[2][k][l] + sh[3][k][l]);
+    }
+  }
+}
+
+int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int* done) {
+  const int cpb = ceil_div(p.ns, p.gt_rows);
+  if (nvec == 3) {
+    hipLaunchKernelGGL(gamma_t_partial_kernel<3>, dim3(p.gt_chunks), dim3(256), 0, p.stream,
+                       p.Gam, p.goff, w, (long long)p.mx, p.gt_part, p.ns, p.nu, p.n, p.gt_rows,
+                       cpb, done);
+    CMPC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(gamma_t_reduce_kernel<3>, dim3(ceil_div(p.n, 64)), dim3(256), 0, p.stream,
+                       p.gt_part, out, p.n, p.nu, cpb, p.gt_chunks, done);
+  } else {
+    hipLaunchKernelGGL(gamma_t_partial_kernel<1>, dim3(p.gt_chunks), dim3(256), 0, p.stream,
+                       p.Gam, p.goff, w, (long long)p.mx, p.gt_part, p.ns, p.nu, p.n, p.gt_rows,
+                       cpb, done);
+    CMPC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(gamma_t_reduce_kernel<1>, dim3(ceil_div(p.n, 64)), dim3(256), 0, p.stream,
+                       p.gt_part, out, p.n, p.nu, cpb, p.gt_chunks, done);
+  }
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// ---------------------------------------------------------------- y = Gamma x
+__global__ __launch_bounds__(256) void gamma_mv_kernel(const double* __restrict__ Gam,
+                                                       const long long* __restrict__ off,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y, int ns, int nu,
+                                                       int mx, const int* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= mx) return;
+  const int t = r / ns + 1, i = r - (t - 1) * ns;
+  const int len = t * nu;
+  const double* row = Gam + off[t - 1] + (long long)i * len;
+  double acc = 0.0;
+  for (int a = lane; a < len; a += 64) acc = fma(row[a], x[a], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) y[r] = acc;
+}
+
+int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done) {
+  hipLaunchKernelGGL(gamma_mv_kernel, dim3(ceil_div(p.mx, 4)), dim3(256), 0, p.stream, p.Gam,
+                     p.goff, x, y, p.ns, p.nu, p.mx, done);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// ---------------------------------------------------------------- y = H x (H symmetric)
+__global__ __launch_bounds__(256) void hv_kernel(const double* __restrict__ H,
+                                                 const double* __restrict__ x,
+                                                 double* __restrict__ y, int n,
+                                                 const int* __restrict__ done) {
+  __shared__ double sh[4][64];
+  if (done != nullptr && *done) return;
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
+  double acc = 0.0;
+  if (c < n)
+    for (int j = g; j < n; j += 4) acc = fma(H[(long long)j * n + c], x[j], acc);
+  sh[g][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (g == 0 && c < n) {
+    const int l = threadIdx.x & 63;
+    y[c] = (sh[0][l] + sh[1][l]) + (sh[2][l] + sh[3][l]);
+  }
+}
+
+static int launch_hv(Problem& p, const double* x, double* y, const int* done) {
+  hipLaunchKernelGGL(hv_kernel, dim3(ceil_div(p.n, 64)), dim3(256), 0, p.stream, p.H, x, y, p.n,
+                     done);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// ---------------------------------------------------------------- start point
+__global__ void ipm_init_kernel(const double* __restrict__ d, double* __restrict__ s,
+                                double* __restrict__ lam, double* __restrict__ z,
+                                double* __restrict__ v, double* __restrict__ gv, int m, int n,
+                                int mx, IpmState* st, double tol, int max_iter) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) {
+    const double di = d[i];
+    if (isinf(di)) {
+      s[i] = 1.0;
+      lam[i] = 0.0;
+      z[i] = 0.0;
+    } else {
+      const double si = fmax(di, kSInitMin);  // v = 0, so d - J v = d
+      s[i] = si;
+      lam[i] = kMuInit / si;
+      z[i] = kMuInit / si;
+    }
+  }
+  if (i < n) v[i] = 0.0;
+  if (i < mx) gv[i] = 0.0;
+  if (i == 0) {
+    st->mu = kMuInit;
+    st->tau = fmax(kTauMin, 1.0 - kMuInit);
+    st->alpha = st->alpha_z = 0.0;
+    st->tol = tol;
+    st->mu_min = tol / 10.0;
+    st->iter = 0;
+    st->status = kRunning;
+    st->done = 0;
+    st->info = 0;
+    st->max_iter = max_iter;
+    st->switch_iter = -1;
+    st->refine_steps = 0;
+    st->nonc = 0;
+  }
+}
+
+int launch_ipm_init(Problem& p, const cmpc_options& o) {
+  const long long len = p.m;
+  hipLaunchKernelGGL(ipm_init_kernel, dim3(ceil_div(len, 256)), dim3(256), 0, p.stream, p.d, p.s,
+                     p.lam, p.z, p.v, p.gv, p.m, p.n, p.mx, p.st, o.tol, o.max_iter);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// ---------------------------------------------------------------- per-pair helpers
+struct PairRows {
+  long long up, lo;
+  double jv;  // (J v) of the upper row; the lower row has -jv
+};
+
+__device__ inline PairRows pair_rows(int p, int mx, int n, const double* gv, const double* v) {
+  PairRows pr;
+  if (p < mx) {
+    pr.up = p;
+    pr.lo = (long long)mx + p;
+    pr.jv = gv[p];
+  } else {
+    const int c = p - mx;
+    pr.up = 2LL * mx + c;
+    pr.lo = 2LL * mx + n + c;
+    pr.jv = v[c];
+  }
+  return pr;
+}
+
+// sigma, folded weights, Gamma' right-hand sides and the residual norms of the iterate.
+__global__ __launch_bounds__(256) void prep_kernel(
+    const double* __restrict__ d, const double* __restrict__ s, const double* __restrict__ lam,
+    const double* __restrict__ z, const double* __restrict__ gv, const double* __restrict__ v,
+    double* __restrict__ Dx, double* __restrict__ Du, double* __restrict__ wx,
+    double* __restrict__ wu, double* __restrict__ norm_part, int mx, int n,
+    const int* __restrict__ done) {
+  __shared__ double sh[4];
+  if (*done) return;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  double nr3 = 0.0, nlz = 0.0, szmax = 0.0, szmin = INFINITY;
+  if (p < mx + n) {
+    const PairRows pr = pair_rows(p, mx, n, gv, v);
+    double sig[2] = {0.0, 0.0}, dl[2] = {0.0, 0.0}, inv[2] = {0.0, 0.0}, y3[2] = {0.0, 0.0};
+    const long long rows[2] = {pr.up, pr.lo};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const long long r = rows[q];
+      const double dr = d[r];
+      if (!isinf(dr)) {
+        const double sr = s[r], zr = z[r], lr = lam[r];
+        const double jv = q == 0 ? pr.jv : -pr.jv;
+        const double r3 = jv - dr + sr;
+        sig[q] = zr / sr;
+        inv[q] = 1.0 / sr;
+        y3[q] = sig[q] * r3;
+        dl[q] = lr;
+        nr3 = fmax(nr3, fabs(r3));
+        nlz = fmax(nlz, fabs(lr - zr));
+        const double sz = sr * zr;
+        szmax = fmax(szmax, sz);
+        szmin = fmin(szmin, sz);
+      }
+    }
+    const double D = sig[0] + sig[1];
+    if (p < mx) {
+      Dx[p] = D;
+      wx[p] = dl[0] - dl[1];
+      wx[(long long)mx + p] = inv[0] - inv[1];
+      wx[2LL * mx + p] = y3[0] - y3[1];
+    } else {
+      const int c = p - mx;
+      Du[c] = D;
+      wu[c] = dl[0] - dl[1];
+      wu[n + c] = inv[0] - inv[1];
+      wu[2 * n + c] = y3[0] - y3[1];
+    }
+  }
+  nr3 = block_max256(nr3, sh);
+  nlz = block_max256(nlz, sh);
+  szmax = block_max256(szmax, sh);
+  szmin = block_min256(szmin, sh);
+  if (threadIdx.x == 0) {
+    double* np = norm_part + 4LL * blockIdx.x;
+    np[0] = nr3;
+    np[1] = nlz;
+    np[2] = szmax;
+    np[3] = szmin;
+  }
+}
+
+int launch_prep(Problem& p) {
+  hipLaunchKernelGGL(prep_kernel, dim3(p.n_prep_blocks), dim3(256), 0, p.stream, p.d, p.s, p.lam,
+                     p.z, p.gv, p.v, p.Dx, p.Du, p.wx, p.wu, p.norm_part, p.mx, p.n, &p.st->done);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// Termination test, barrier update and right-hand side of eqn. (cond_KKT):
+//   r1 = H v + h + J' lambda,   E_0 = max(|r1|, |r3|, |lambda - z|, |s z|),
+//   while E_mu <= kappa_eps mu: mu <- max(mu_min, min(kappa_mu mu, mu^theta_mu)),
+//   rhs = -r1 + J' r2 - J' Sigma r3 = -(H v + h) - mu J' S^-1 1 - J' Sigma r3.
+// fixed_mu != 0: no test and no update (used for a single step from a given iterate).
+__global__ __launch_bounds__(256) void mu_rhs_kernel(
+    const double* __restrict__ Hv, const double* __restrict__ h, const double* __restrict__ gt,
+    const double* __restrict__ wu, const double* __restrict__ norm_part, int nparts,
+    double* __restrict__ rhs, int n, IpmState* st, int fixed_mu) {
+  __shared__ double sh[4];
+  if (st->done) return;
+  double nr1 = 0.0;
+  for (int c = threadIdx.x; c < n; c += 256) {
+    const double r1 = Hv[c] + h[c] + (gt[c] + wu[c]);
+    nr1 = fmax(nr1, fabs(r1));
+  }
+  nr1 = block_max256(nr1, sh);
+  double nr3 = 0.0, nlz = 0.0, szmax = 0.0, szmin = INFINITY;
+  for (int b = threadIdx.x; b < nparts; b += 256) {
+    nr3 = fmax(nr3, norm_part[4LL * b]);
+    nlz = fmax(nlz, norm_part[4LL * b + 1]);
+    szmax = fmax(szmax, norm_part[4LL * b + 2]);
+    szmin = fmin(szmin, norm_part[4LL * b + 3]);
+  }
+  nr3 = block_max256(nr3, sh);
+  nlz = block_max256(nlz, sh);
+  szmax = block_max256(szmax, sh);
+  szmin = block_min256(szmin, sh);
+  double mu = st->mu;
+  bool stop = false;
+  if (!fixed_mu) {
+    const double e0 = fmax(fmax(nr1, nr3), fmax(nlz, szmax));
+    if (threadIdx.x == 0) {
+      st->nr1 = nr1;
+      st->nr3 = nr3;
+      st->nlz = nlz;
+      st->szmax = szmax;
+      st->szmin = szmin;
+      st->err0 = e0;
+    }
+    if (e0 <= st->tol) {
+      if (threadIdx.x == 0) {
+        st->status = CMPC_OK;
+        st->done = 1;
+      }
+      stop = true;
+    } else if (st->iter >= st->max_iter) {
+      if (threadIdx.x == 0) {
+        st->status = CMPC_MAX_ITER;
+        st->done = 1;
+      }
+      stop = true;
+    } else {
+      const double base = fmax(fmax(nr1, nr3), nlz);
+      while (mu > st->mu_min) {
+        const double emu = fmax(base, fmax(szmax - mu, mu - szmin));
+        if (emu > kKappaEps * mu) break;
+        mu = fmax(st->mu_min, fmin(kKappaMu * mu, pow(mu, kThetaMu)));
+      }
+    }
+  }
+  if (stop) return;
+  for (int c = threadIdx.x; c < n; c += 256)
+    rhs[c] = -(Hv[c] + h[c]) - mu * (gt[n + c] + wu[n + c]) - (gt[2 * n + c] + wu[2 * n + c]);
+  if (threadIdx.x == 0 && !fixed_mu) {
+    st->mu = mu;
+    st->tau = fmax(kTauMin, 1.0 - mu);
+  }
+}
+
+int launch_mu_rhs(Problem& p) {
+  const int* done = &p.st->done;
+  if (launch_gamma_t(p, p.wx, 3, p.gt, done)) return CMPC_ERR_HIP;
+  if (launch_hv(p, p.v, p.Hv, done)) return CMPC_ERR_HIP;
+  hipLaunchKernelGGL(mu_rhs_kernel, dim3(1), dim3(256), 0, p.stream, p.Hv, p.h, p.gt, p.wu,
+                     p.norm_part, p.n_prep_blocks, p.rhs, p.n, p.st, 0);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// ---------------------------------------------------------------- step recovery
+// p_s = -r3 - J p_v;  p_lambda = -r2 + Sigma r3 + Sigma J p_v = -r2 - Sigma p_s;
+// p_z = mu S^-1 1 - z - Sigma p_s;  per-block minima of the fraction-to-boundary ratios.
+__global__ __launch_bounds__(256) void step_kernel(
+    const double* __restrict__ d, const double* __restrict__ s, const double* __restrict__ lam,
+    const double* __restrict__ z, const double* __restrict__ gv, const double* __restrict__ v,
+    const double* __restrict__ gpv, const double* __restrict__ pv, double* __restrict__ ps,
+    double* __restrict__ plam, double* __restrict__ pz, double* __restrict__ alpha_part, int mx,
+    int n, const IpmState* st) {
+  __shared__ double sh[4];
+  if (st->done) return;
+  const double mu = st->mu, tau = st->tau;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  double amin = INFINITY, azmin = INFINITY;
+  if (p < mx + n) {
+    const PairRows pr = pair_rows(p, mx, n, gv, v);
+    const double jp = p < mx ? gpv[p] : pv[p - mx];
+    const long long rows[2] = {pr.up, pr.lo};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const long long r = rows[q];
+      const double dr = d[r];
+      double a = 0.0, b = 0.0, c = 0.0;
+      if (!isinf(dr)) {
+        const double sr = s[r], zr = z[r], lr = lam[r];
+        const double jv = q == 0 ? pr.jv : -pr.jv;
+        const double jpv = q == 0 ? jp : -jp;
+        const double r3 = jv - dr + sr;
+        const double sig = zr / sr;
+        const double r2 = lr - mu / sr;
+        a = -r3 - jpv;
+        b = -r2 - sig * a;
+        c = mu / sr - zr - sig * a;
+        if (a < 0.0) amin = fmin(amin, -tau * sr / a);
+        if (c < 0.0) azmin = fmin(azmin, -tau * zr / c);
+      }
+      ps[r] = a;
+      plam[r] = b;
+      pz[r] = c;
+    }
+  }
+  amin = block_min256(amin, sh);
+  azmin = block_min256(azmin, sh);
+  if (threadIdx.x == 0) {
+    alpha_part[2LL * blockIdx.x] = amin;
+    alpha_part[2LL * blockIdx.x + 1] = azmin;
+  }
+}
+
+int launch_step(Problem& p) {
+  const int* done = &p.st->done;
+  hipMemcpyAsync(p.pv, p.rhs, sizeof(double) * p.n, hipMemcpyDeviceToDevice, p.stream);
+  if (launch_potrs(p.stream, p.K, p.n, p.n, p.pv, done)) return CMPC_ERR_HIP;
+  if (launch_gamma_mv(p, p.pv, p.gpv, done)) return CMPC_ERR_HIP;
+  hipLaunchKernelGGL(step_kernel, dim3(p.n_step_blocks), dim3(256), 0, p.stream, p.d, p.s, p.lam,
+                     p.z, p.gv, p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part, p.mx, p.n,
+                     p.st);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// ---------------------------------------------------------------- update
+// Every workgroup reduces the step-length partials itself (min is order independent), then
+// v += alpha p_v, s += alpha p_s, lambda += alpha p_lambda, z += alpha_z p_z, and z is
+// safeguarded into [mu/(kappa s), kappa mu/s].  apply == 0 only records alpha, alpha_z.
+__global__ __launch_bounds__(256) void update_kernel(
+    const double* __restrict__ d, double* __restrict__ s, double* __restrict__ lam,
+    double* __restrict__ z, double* __restrict__ gv, double* __restrict__ v,
+    const double* __restrict__ gpv, const double* __restrict__ pv, const double* __restrict__ ps,
+    const double* __restrict__ plam, const double* __restrict__ pz,
+    const double* __restrict__ alpha_part, int nparts, int mx, int n, IpmState* st, int apply) {
+  __shared__ double sh[4];
+  if (st->done) return;
+  double amin = 1.0, azmin = 1.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) {
+    amin = fmin(amin, alpha_part[2LL * b]);
+    azmin = fmin(azmin, alpha_part[2LL * b + 1]);
+  }
+  const double alpha = block_min256(amin, sh);
+  const double alpha_z = block_min256(azmin, sh);
+  const double mu = st->mu;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->alpha = alpha;
+    st->alpha_z = alpha_z;
+  }
+  if (!apply) return;
+  if (alpha < kAlphaMin) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->status = CMPC_SMALL_STEP;
+      st->done = 1;
+    }
+    return;
+  }
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p < mx + n) {
+    long long rows[2];
+    if (p < mx) {
+      rows[0] = p;
+      rows[1] = (long long)mx + p;
+      gv[p] += alpha * gpv[p];
+    } else {
+      const int c = p - mx;
+      rows[0] = 2LL * mx + c;
+      rows[1] = 2LL * mx + n + c;
+      v[c] += alpha * pv[c];
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const long long r = rows[q];
+      if (isinf(d[r])) continue;
+      const double sn = s[r] + alpha * ps[r];
+      const double ln = lam[r] + alpha * plam[r];
+      double zn = z[r] + alpha_z * pz[r];
+      zn = fmin(fmax(zn, mu / (kKappaSigma * sn)), kKappaSigma * mu / sn);
+      s[r] = sn;
+      lam[r] = ln;
+      z[r] = zn;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->iter += 1;
+}
+
+int launch_update(Problem& p) {
+  hipLaunchKernelGGL(update_kernel, dim3(p.n_step_blocks), dim3(256), 0, p.stream, p.d, p.s,
+                     p.lam, p.z, p.gv, p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part,
+                     p.n_step_blocks, p.mx, p.n, p.st, 1);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// ---------------------------------------------------------------- final objective, gap
+__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ Hv,
+                                                       const double* __restrict__ h,
+                                                       const double* __restrict__ v,
+                                                       const double* __restrict__ s,
+                                                       const double* __restrict__ z,
+                                                       const double* __restrict__ d, int n,
+                                                       long long m, IpmState* st,
+                                                       double* __restrict__ gap_out) {
+  __shared__ double sh[4];
+  double f = 0.0, g = 0.0;
+  for (int c = threadIdx.x; c < n; c += 256) f += v[c] * (0.5 * Hv[c] + h[c]);
+  for (long long r = threadIdx.x; r < m; r += 256)
+    if (!isinf(d[r])) g = fma(s[r], z[r], g);
+  f = block_sum256(f, sh);
+  g = block_sum256(g, sh);
+  if (threadIdx.x == 0) {
+    st->obj = f + st->h0;
+    *gap_out = g;
+  }
+}
+
+int launch_finalize(Problem& p) {
+  if (launch_hv(p, p.v, p.Hv, nullptr)) return CMPC_ERR_HIP;
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, p.stream, p.Hv, p.h, p.v, p.s, p.z,
+                     p.d, p.n, (long long)p.m, p.st, p.tmpn);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// ---------------------------------------------------------------- sigma folding (testing)
+__global__ void sigma_fold_kernel(const double* __restrict__ sigma, const double* __restrict__ xl,
+                                  const double* __restrict__ xu, const double* __restrict__ ul,
+                                  const double* __restrict__ uu, double* __restrict__ Dx,
+                                  double* __restrict__ Du, int ns, int nu, int mx, int n) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < mx) {
+    const int i = p % ns;
+    Dx[p] = (isinf(xu[i]) ? 0.0 : sigma[p]) + (isinf(xl[i]) ? 0.0 : sigma[(long long)mx + p]);
+  } else if (p < mx + n) {
+    const int c = p - mx, k = c % nu;
+    Du[c] = (isinf(uu[k]) ? 0.0 : sigma[2LL * mx + c]) +
+            (isinf(ul[k]) ? 0.0 : sigma[2LL * mx + n + c]);
+  }
+}
+
+int launch_sigma_fold(Problem& p, const double* sigma) {
+  hipLaunchKernelGGL(sigma_fold_kernel, dim3(ceil_div((long long)p.mx + p.n, 256)), dim3(256), 0,
+                     p.stream, sigma, p.xl, p.xu, p.ul, p.uu, p.Dx, p.Du, p.ns, p.nu, p.mx, p.n);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// ---------------------------------------------------------------- one step from an iterate
+__global__ void set_step_state_kernel(IpmState* st, double mu, double tau) {
+  st->mu = mu;
+  st->tau = tau;
+  st->done = 0;
+  st->status = kRunning;
+  st->info = 0;
+}
+
+int launch_step_given(Problem& p, const double* v, const double* s, const double* lam,
+                      const double* z, double mu, double tau) {
+  const size_t m = p.m;
+  CMPC_HIP(hipMemcpyAsync(p.v, v, sizeof(double) * p.n, hipMemcpyDeviceToDevice, p.stream));
+  CMPC_HIP(hipMemcpyAsync(p.s, s, sizeof(double) * m, hipMemcpyDeviceToDevice, p.stream));
+  CMPC_HIP(hipMemcpyAsync(p.lam, lam, sizeof(double) * m, hipMemcpyDeviceToDevice, p.stream));
+  CMPC_HIP(hipMemcpyAsync(p.z, z, sizeof(double) * m, hipMemcpyDeviceToDevice, p.stream));
+  hipLaunchKernelGGL(set_step_state_kernel, dim3(1), dim3(1), 0, p.stream, p.st, mu, tau);
+  CMPC_LAUNCH_CHECK();
+  const int* done = &p.st->done;
+  if (launch_gamma_mv(p, p.v, p.gv, done)) return CMPC_ERR_HIP;
+  if (launch_prep(p)) return CMPC_ERR_HIP;
+  if (launch_gamma_t(p, p.wx, 3, p.gt, done)) return CMPC_ERR_HIP;
+  if (launch_hv(p, p.v, p.Hv, done)) return CMPC_ERR_HIP;
+  hipLaunchKernelGGL(mu_rhs_kernel, dim3(1), dim3(256), 0, p.stream, p.Hv, p.h, p.gt, p.wu,
+                     p.norm_part, p.n_prep_blocks, p.rhs, p.n, p.st, 1);
+  CMPC_LAUNCH_CHECK();
+  if (launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K)) return CMPC_ERR_HIP;
+  if (launch_potrf(p.stream, p.K, p.n, p.n, &p.st->done, &p.st->info, &p.st->status))
+    return CMPC_ERR_HIP;
+  if (launch_step(p)) return CMPC_ERR_HIP;
+  hipLaunchKernelGGL(update_kernel, dim3(1), dim3(256), 0, p.stream, p.d, p.s, p.lam, p.z, p.gv,
+                     p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part, p.n_step_blocks, p.mx,
+                     p.n, p.st, 0);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+}  // namespace cmpc

@@ -1,0 +1,354 @@
+// Formation of the condensed matrix K = Hbase + Gamma' diag(D) Gamma + diag(Ddiag)
+// (left-hand side of eqn. (cond_KKT) after folding the two-sided bound rows; the paper's
+// Section 4 names this condensation as the step whose cost grows with the row count of J).
+//
+// Design (gfx950):
+//  * Gamma is stored packed by row block t (ns x t nu), so only its structural nonzeros
+//    are read; tile (I, J) of K receives row block t only if t nu > 64 I.
+//  * Work = (64 x 64 output tile, row block, row range) segments, ordered block-major and
+//    cut into equal-cost pieces, one piece per workgroup (stream-K).  Workgroups that run
+//    on the same XCD get neighbouring pieces, so a row block is fetched from HBM once per
+//    XCD and re-read from that XCD's L2 by every tile that needs it.
+//  * Each of the 4 wavefronts of a workgroup accumulates the whole 64 x 64 tile over every
+//    4th group of 4 rows with v_mfma_f64_16x16x4f64 (or the f32 variant), operands loaded
+//    straight from memory in the MFMA lane layout and scaled by D on the fly; 16 x 16
+//    blocks that are structurally zero (columns >= t nu) or above the diagonal are skipped.
+//  * At the end of a tile's piece the 4 accumulators are summed in LDS and written to a
+//    partial slot; a second kernel adds the slots of each tile in a fixed order to Hbase
+//    (deterministic, no atomics).
+#include <algorithm>
+
+#include "problem.hpp"
+
+namespace cmpc {
+
+static int nblocks16(int I, int J, int len) {
+  const int a0 = 64 * I, b0 = 64 * J;
+  if (len <= a0) return 0;
+  const int nib = std::min(4, ceil_div(len - a0, 16));
+  const int njb = std::min(4, ceil_div(len - b0, 16));
+  if (I != J) return nib * njb;
+  int c = 0;
+  for (int ib = 0; ib < nib; ++ib)
+    for (int jb = 0; jb < njb; ++jb)
+      if (jb <= ib) ++c;
+  return c;
+}
+
+void syrk_free(SyrkPlan& sp) {
+  hipFree(sp.tiles);
+  hipFree(sp.jobs);
+  hipFree(sp.wg_begin);
+  hipFree(sp.slot_begin);
+  hipFree(sp.slots);
+  hipFree(sp.partials);
+  sp = SyrkPlan();
+}
+
+int syrk_plan(Problem& p) {
+  SyrkPlan& sp = p.syrk;
+  const int ns = p.ns, nu = p.nu, N = p.N, n = p.n;
+  sp.nt = ceil_div(n, 64);
+  std::vector<int2> tiles;
+  for (int I = 0; I < sp.nt; ++I)
+    for (int J = 0; J <= I; ++J) tiles.push_back(make_int2(I, J));
+  sp.ntiles = (int)tiles.size();
+  struct Seg {
+    int tile, t, cpr;
+  };
+  std::vector<Seg> segs;
+  double total = 0.0;
+  for (int t = N; t >= 1; --t)
+    for (int q = 0; q < sp.ntiles; ++q) {
+      const int c = nblocks16(tiles[q].x, tiles[q].y, t * nu);
+      if (c > 0) {
+        segs.push_back({q, t, c});
+        total += (double)c * ns;
+      }
+    }
+  sp.flops_structural = 0.0;
+  for (int t = 1; t <= N; ++t) {
+    const double len = (double)t * nu;
+    sp.flops_structural += (double)ns * len * (len + 1.0);
+  }
+  int nwg = (int)(total / 12000.0);
+  nwg = std::max(8, std::min(512, nwg));
+  nwg = (nwg + 7) / 8 * 8;
+  const double target = total / nwg;
+  std::vector<SyrkJob> jobs;
+  std::vector<int> job_wg;
+  int wg = 0;
+  double acc = 0.0;
+  for (const Seg& sg : segs) {
+    int r = 0;
+    while (r < ns) {
+      const double room = target * (wg + 1) - acc;
+      int take = ns - r;
+      if (wg < nwg - 1) {
+        int want = (int)std::ceil(std::max(room, 1.0) / sg.cpr);
+        want = (want + 15) / 16 * 16;
+        take = std::min(take, std::max(16, want));
+      }
+      jobs.push_back({sg.tile, sg.t, r, r + take, -1});
+      job_wg.push_back(wg);
+      acc += (double)take * sg.cpr;
+      r += take;
+      if (wg < nwg - 1 && acc >= target * (wg + 1) - 1e-9) ++wg;
+    }
+  }
+  // workgroup ranges (jobs are emitted in workgroup order) and flush points
+  std::vector<int> wg_begin(nwg + 1, (int)jobs.size());
+  for (int j = (int)jobs.size() - 1; j >= 0; --j) wg_begin[job_wg[j]] = j;
+  for (int w = nwg - 1; w >= 0; --w)
+    if (wg_begin[w] > wg_begin[w + 1]) wg_begin[w] = wg_begin[w + 1];
+  std::vector<int> slot_tile;
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    const bool last = (j + 1 == jobs.size()) || job_wg[j + 1] != job_wg[j] ||
+                      jobs[j + 1].tile != jobs[j].tile;
+    if (last) {
+      jobs[j].slot = (int)slot_tile.size();
+      slot_tile.push_back(jobs[j].tile);
+    }
+  }
+  sp.nslots = (int)slot_tile.size();
+  std::vector<int> slot_begin(sp.ntiles + 1, 0), slots(sp.nslots);
+  for (int s = 0; s < sp.nslots; ++s) slot_begin[slot_tile[s] + 1]++;
+  for (int q = 0; q < sp.ntiles; ++q) slot_begin[q + 1] += slot_begin[q];
+  {
+    std::vector<int> fill(slot_begin.begin(), slot_begin.end() - 1);
+    for (int s = 0; s < sp.nslots; ++s) slots[fill[slot_tile[s]]++] = s;
+  }
+  sp.nwg = nwg;
+  CMPC_HIP(hipMalloc(&sp.tiles, sizeof(int2) * tiles.size()));
+  CMPC_HIP(hipMalloc(&sp.jobs, sizeof(SyrkJob) * std::max<size_t>(1, jobs.size())));
+  CMPC_HIP(hipMalloc(&sp.wg_begin, sizeof(int) * (nwg + 1)));
+  CMPC_HIP(hipMalloc(&sp.slot_begin, sizeof(int) * (sp.ntiles + 1)));
+  CMPC_HIP(hipMalloc(&sp.slots, sizeof(int) * std::max(1, sp.nslots)));
+  CMPC_HIP(hipMalloc(&sp.partials, sizeof(double) * 4096 * (size_t)std::max(1, sp.nslots)));
+  CMPC_HIP(hipMemcpy(sp.tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice));
+  CMPC_HIP(hipMemcpy(sp.jobs, jobs.data(), sizeof(SyrkJob) * jobs.size(), hipMemcpyHostToDevice));
+  CMPC_HIP(hipMemcpy(sp.wg_begin, wg_begin.data(), sizeof(int) * (nwg + 1), hipMemcpyHostToDevice));
+  CMPC_HIP(hipMemcpy(sp.slot_begin, slot_begin.data(), sizeof(int) * (sp.ntiles + 1),
+                     hipMemcpyHostToDevice));
+  CMPC_HIP(hipMemcpy(sp.slots, slots.data(), sizeof(int) * sp.nslots, hipMemcpyHostToDevice));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------------------
+
+template <typename TIn>
+struct MfmaOps;
+
+template <>
+struct MfmaOps<double> {
+  typedef d4 acc_t;
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output element v of lane l sits at row l/16 + 4v, column l%16 of the 16 x 16 block
+  __device__ static inline int out_row(int lk, int v) { return lk + 4 * v; }
+};
+
+template <>
+struct MfmaOps<float> {
+  typedef f4 acc_t;
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output element v of lane l sits at row 4 (l/16) + v, column l%16
+  __device__ static inline int out_row(int lk, int v) { return 4 * lk + v; }
+};
+
+// Rows [r0, r1) of one row block against one tile: NIB active 16-column blocks of the
+// tile rows (columns >= t nu are structural zeros); off-diagonal tiles have all 4 column
+// blocks active, diagonal tiles skip the blocks above the diagonal.
+template <typename TIn, int NIB, bool DIAG>
+__device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4][4],
+                                          const TIn* __restrict__ base,
+                                          const double* __restrict__ Dt, int len, int a0, int b0,
+                                          int r0, int r1, int wave, int li, int lk) {
+  typedef MfmaOps<TIn> Ops;
+  constexpr int NJB = DIAG ? NIB : 4;
+  bool va[NIB], vb[NJB];
+#pragma unroll
+  for (int q = 0; q < NIB; ++q) va[q] = a0 + 16 * q + li < len;
+#pragma unroll
+  for (int q = 0; q < NJB; ++q) vb[q] = b0 + 16 * q + li < len;
+  const int nsteps = (r1 - r0 + 15) >> 4;
+  TIn ca[NIB], cb[NJB], cd;
+  auto load = [&](int step, TIn* xa, TIn* xb, TIn& xd) {
+    const int r = r0 + 16 * step + 4 * wave + lk;
+    const bool vr = r < r1;
+    const TIn* row = base + (long long)(vr ? r : r0) * len;
+    xd = vr ? (TIn)Dt[r] : (TIn)0;
+#pragma unroll
+    for (int q = 0; q < NIB; ++q) xa[q] = (vr && va[q]) ? row[a0 + 16 * q + li] : (TIn)0;
+    if (!DIAG) {
+#pragma unroll
+      for (int q = 0; q < NJB; ++q) xb[q] = (vr && vb[q]) ? row[b0 + 16 * q + li] : (TIn)0;
+    }
+  };
+  load(0, ca, cb, cd);
+  for (int step = 0; step < nsteps; ++step) {
+    TIn na[NIB], nb[NJB], nd = (TIn)0;
+#pragma unroll
+    for (int q = 0; q < NIB; ++q) na[q] = (TIn)0;
+#pragma unroll
+    for (int q = 0; q < NJB; ++q) nb[q] = (TIn)0;
+    if (step + 1 < nsteps) load(step + 1, na, nb, nd);
+    TIn sa[NIB];
+#pragma unroll
+    for (int q = 0; q < NIB; ++q) sa[q] = ca[q] * cd;
+#pragma unroll
+    for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < (DIAG ? ib + 1 : NJB); ++jb)
+        acc[ib][jb] = Ops::mma(sa[ib], DIAG ? ca[jb] : cb[jb], acc[ib][jb]);
+#pragma unroll
+    for (int q = 0; q < NIB; ++q) ca[q] = na[q];
+    if (!DIAG) {
+#pragma unroll
+      for (int q = 0; q < NJB; ++q) cb[q] = nb[q];
+    }
+    cd = nd;
+  }
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(256, 1) void syrk_streamk_kernel(
+    const TIn* __restrict__ Gam, const long long* __restrict__ off, const double* __restrict__ D,
+    const SyrkJob* __restrict__ jobs, const int* __restrict__ wg_begin,
+    const int2* __restrict__ tiles, double* __restrict__ partials, int ns, int nu, int nwg,
+    const int* __restrict__ done) {
+  typedef MfmaOps<TIn> Ops;
+  typedef typename Ops::acc_t acc_t;
+  __shared__ double red[64 * 64];
+  if (done != nullptr && *done) return;
+  const int per = nwg >> 3;
+  const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+  const int jend = wg_begin[wg + 1];
+  for (int jj = wg_begin[wg]; jj < jend; ++jj) {
+    const SyrkJob job = jobs[jj];
+    const int2 tl = tiles[job.tile];
+    const int a0 = tl.x * 64, b0 = tl.y * 64;
+    const int len = job.t * nu;
+    const TIn* __restrict__ base = Gam + off[job.t - 1];
+    const double* __restrict__ Dt = D + (long long)(job.t - 1) * ns;
+    const int nib = min(4, (len - a0 + 15) >> 4);
+    const int key = (tl.x == tl.y ? 4 : 0) + nib - 1;
+    switch (key) {
+      case 0: syrk_rows<TIn, 1, false>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
+      case 1: syrk_rows<TIn, 2, false>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
+      case 2: syrk_rows<TIn, 3, false>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
+      case 3: syrk_rows<TIn, 4, false>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
+      case 4: syrk_rows<TIn, 1, true>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
+      case 5: syrk_rows<TIn, 2, true>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
+      case 6: syrk_rows<TIn, 3, true>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
+      default: syrk_rows<TIn, 4, true>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
+    }
+    if (job.slot >= 0) {
+      __syncthreads();
+      for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+#pragma unroll
+          for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int idx = (16 * ib + Ops::out_row(lk, v)) * 64 + 16 * jb + li;
+                const double x = (double)acc[ib][jb][v];
+                red[idx] = (w == 0) ? x : red[idx] + x;
+              }
+        }
+        __syncthreads();
+      }
+      double* dst = partials + (long long)job.slot * 4096;
+      for (int e = threadIdx.x; e < 4096; e += 256) dst[e] = red[e];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    }
+  }
+}
+
+// K(lower) = Hb(lower) + sum of the tile's partial slots (fixed order) + diag(Ddiag).
+__global__ __launch_bounds__(256) void syrk_finish_kernel(
+    const double* __restrict__ partials, const int* __restrict__ slot_begin,
+    const int* __restrict__ slots, const int2* __restrict__ tiles, const double* __restrict__ Hb,
+    const double* __restrict__ Ddiag, double* __restrict__ K, int n, const int* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  const int2 tl = tiles[blockIdx.x];
+  const int a0 = tl.x * 64, b0 = tl.y * 64;
+  const int q0 = slot_begin[blockIdx.x], q1 = slot_begin[blockIdx.x + 1];
+  for (int e = threadIdx.x; e < 4096; e += 256) {
+    const int gi = a0 + (e >> 6), gj = b0 + (e & 63);
+    if (gi >= n || gj > gi) continue;
+    double sum = 0.0;
+    for (int q = q0; q < q1; ++q) sum += partials[(long long)slots[q] * 4096 + e];
+    double val = Hb[(long long)gi * n + gj] + sum;
+    if (gi == gj && Ddiag != nullptr) val += Ddiag[gi];
+    K[(long long)gi * n + gj] = val;
+  }
+}
+
+int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hbase,
+                const double* Ddiag, double* K) {
+  SyrkPlan& sp = p.syrk;
+  const int* done = p.st ? &p.st->done : nullptr;
+  if (precision == CMPC_FP32_SYRK) {
+    if (p.Gam32 == nullptr) {
+      set_error("FP32 copy of Gamma not allocated");
+      return CMPC_ERR_INVALID;
+    }
+    hipLaunchKernelGGL(syrk_streamk_kernel<float>, dim3(sp.nwg), dim3(256), 0, p.stream, p.Gam32,
+                       p.goff, Drow, sp.jobs, sp.wg_begin, sp.tiles, sp.partials, p.ns, p.nu,
+                       sp.nwg, done);
+  } else {
+    hipLaunchKernelGGL(syrk_streamk_kernel<double>, dim3(sp.nwg), dim3(256), 0, p.stream, p.Gam,
+                       p.goff, Drow, sp.jobs, sp.wg_begin, sp.tiles, sp.partials, p.ns, p.nu,
+                       sp.nwg, done);
+  }
+  CMPC_LAUNCH_CHECK();
+  hipLaunchKernelGGL(syrk_finish_kernel, dim3(sp.ntiles), dim3(256), 0, p.stream, sp.partials,
+                     sp.slot_begin, sp.slots, sp.tiles, Hbase, Ddiag, K, p.n, done);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+}  // namespace cmpc
+
+namespace cmpc {
+
+__global__ void convert_f32_kernel(const double* __restrict__ in, float* __restrict__ out,
+                                   long long len) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) out[i] = (float)in[i];
+}
+
+// Low-precision copy of the packed Gamma for the mixed-precision SYRK (made once).
+int launch_convert_gamma(Problem& p, int precision) {
+  const long long nnz = p.off[p.N];
+  if (precision == CMPC_FP32_SYRK && p.Gam32 == nullptr) {
+    if (hipMalloc(&p.Gam32, sizeof(float) * (size_t)nnz) != hipSuccess) {
+      p.Gam32 = nullptr;
+      set_error("out of device memory (FP32 Gamma)");
+      return CMPC_ERR_NOMEM;
+    }
+    hipLaunchKernelGGL(convert_f32_kernel, dim3(ceil_div(nnz, 256)), dim3(256), 0, p.stream, p.Gam,
+                       p.Gam32, nnz);
+    CMPC_LAUNCH_CHECK();
+  }
+  return 0;
+}
+
+}  // namespace cmpc

@@ -1,0 +1,117 @@
+// Device-resident problem, IPM workspace and the launchers of every kernel family.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+#include "condmpc.h"
+
+namespace cmpc {
+
+// Interior-point scalars kept on the device so that one iteration needs no host round trip.
+struct IpmState {
+  double mu, tau, alpha, alpha_z;
+  double nr1, nr3, nlz, szmax, szmin, err0;  // norms at the top of the current iteration
+  double tol, mu_min, h0, obj;
+  int iter;      // steps taken
+  int status;    // CMPC_* outcome once done
+  int done;      // nonzero: every later kernel of the solve returns at entry
+  int info;      // Cholesky: 1-based failing column
+  int max_iter;
+  int use_low;   // mixed modes: current SYRK is the low-precision one
+  int switch_iter;
+  int refine_steps;
+  int nonc;      // mixed modes: refinement failures so far
+  int pad_;
+};
+
+constexpr int kRunning = 100;
+
+// One stream-K job of the SYRK: rows [r0, r1) of row block t (1-based) contribute to
+// output tile `tile`; slot >= 0 means the accumulator is written to partial slot `slot`
+// after this job and cleared.
+struct SyrkJob {
+  int tile, t, r0, r1, slot;
+};
+
+struct SyrkPlan {
+  int nt = 0, ntiles = 0, nwg = 0, nslots = 0;
+  int2* tiles = nullptr;         // (I, J) tile coordinates, I >= J, 64 x 64 tiles
+  SyrkJob* jobs = nullptr;
+  int* wg_begin = nullptr;       // nwg + 1
+  int* slot_begin = nullptr;     // ntiles + 1 (CSR of partial slots per tile)
+  int* slots = nullptr;
+  double* partials = nullptr;    // nslots x 4096
+  double flops_structural = 0;   // algorithmic FLOPs of one SYRK (structural nonzeros)
+};
+
+struct Problem {
+  int ns = 0, nu = 0, N = 0, n = 0, mx = 0, m = 0;
+  hipStream_t stream = nullptr;
+  bool q_diag = false;
+  // problem data (device)
+  double *A = nullptr, *B = nullptr, *Q = nullptr, *Qf = nullptr, *R = nullptr;
+  double *xl = nullptr, *xu = nullptr, *ul = nullptr, *uu = nullptr;
+  double *qdiag = nullptr;       // diag(Qbar), length mx (diagonal weights only)
+  double *G = nullptr;           // G_k = A^k B, k = 0..N-1: N x ns x nu
+  double *Gam = nullptr;         // packed Gamma: block t (t = 1..N) is ns x (t nu) row-major
+  long long* goff = nullptr;     // device copy of off (N + 1)
+  std::vector<long long> off;    // off[t - 1] = start of block t; off[N] = nnz
+  float* Gam32 = nullptr;        // FP32 copy (mixed modes)
+  unsigned short* Gam16 = nullptr;  // BF16 copy (mixed modes)
+  double *H = nullptr;           // n x n, full symmetric
+  double *K = nullptr;           // n x n workspace (lower triangle = condensed matrix / factor)
+  double *x0 = nullptr, *c = nullptr, *qc = nullptr, *h = nullptr, *d = nullptr;
+  bool have_x0 = false;
+  // iterate
+  double *v = nullptr, *s = nullptr, *lam = nullptr, *z = nullptr, *gv = nullptr;
+  // step and work vectors
+  double *pv = nullptr, *ps = nullptr, *plam = nullptr, *pz = nullptr, *gpv = nullptr;
+  double *rhs = nullptr, *Dx = nullptr, *Du = nullptr, *wx = nullptr, *wu = nullptr;
+  double *gt = nullptr, *Hv = nullptr, *tmpn = nullptr, *tmpn2 = nullptr, *tmpmx = nullptr;
+  double *norm_part = nullptr, *alpha_part = nullptr, *gt_part = nullptr;
+  int n_prep_blocks = 0, n_step_blocks = 0, gt_chunks = 0, gt_rows = 0;
+  IpmState* st = nullptr;
+  SyrkPlan syrk;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+// ---- setup kernels (k_build.hip) ----
+int launch_gemm_f64(hipStream_t s, int M, int Nc, int Kd, double alpha, const double* A,
+                    long long a_i, long long a_k, const double* B, long long b_k, long long b_j,
+                    double beta, double* C, long long ldc);
+int launch_pack_gamma(Problem& p);
+int launch_gemv(hipStream_t s, const double* A, const double* x, double* y, int rows, int cols);
+int launch_block_diag_weight(Problem& p, const double* in, double* out);
+int launch_make_d(Problem& p);
+int launch_h0(Problem& p);
+int launch_rbar(Problem& p, double* Hb);
+int launch_mirror_lower(hipStream_t s, double* H, int n);
+int launch_dense_gamma(Problem& p, double* dense);
+
+// ---- SYRK (k_syrk.hip) ----
+int syrk_plan(Problem& p);
+void syrk_free(SyrkPlan& sp);
+// K(lower) = Hbase(lower) + Gamma' diag(Drow) Gamma + diag(Ddiag)   (Ddiag may be NULL)
+int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hbase,
+                const double* Ddiag, double* K);
+
+// ---- Cholesky (k_chol.hip) ----
+int launch_potrf(hipStream_t s, double* K, int n, int ld, int* done, int* info, int* status);
+int launch_potrs(hipStream_t s, const double* L, int n, int ld, double* b, const int* done);
+
+// ---- IPM vector kernels (k_ipm.hip) ----
+int ipm_alloc_work(Problem& p);
+int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int* done);
+int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done);
+int launch_ipm_init(Problem& p, const cmpc_options& o);
+int launch_prep(Problem& p);
+int launch_mu_rhs(Problem& p);
+int launch_step(Problem& p);
+int launch_update(Problem& p);
+int launch_finalize(Problem& p);
+int launch_sigma_fold(Problem& p, const double* sigma);
+int launch_step_given(Problem& p, const double* v, const double* s, const double* lam,
+                      const double* z, double mu, double tau);
+
+}  // namespace cmpc

@@ -1,0 +1,228 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, step by step.
+
+Tolerances (FP64 path): the reduction, the condensed matrix and the factorisation are
+compared element-wise at 1e-12 relative to the largest magnitude of the compared array
+(sums of up to ~5e4 products of O(1) numbers in a different order: ~1e-14 expected);
+Newton directions at 1e-9 relative (the solve amplifies rounding by cond(K), which the
+test points keep below ~1e6); converged solves by the objective within 1e-8 relative and
+the KKT residuals within 1e-8, with the same iteration count.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2209_13049_amd import condmpc
+from paper_2209_13049_amd import workloads as W
+from test_oracle_pins import random_stable
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def cases():
+    small = W.heat1d_config("small")
+    ragged = W.heat1d(37, 3, 23, seed=(9, 1))                      # n = 69: two tiles, ragged
+    tight = W.heat1d(60, 4, 20, seed=(0, 1), xu=0.05, x0_range=(-0.4, 0.04))
+    genq = random_stable(7, 3, 9, 5)                               # dense Q, Q_f
+    inf = W.heat1d(30, 2, 12, seed=(4, 4))
+    inf.xu[3] = np.inf
+    inf.xl[5] = -np.inf
+    inf.uu[1] = np.inf
+    wide = W.heat1d(50, 7, 21, seed=(8, 2))                       # n = 147: 3 tile rows
+    return {"small": small, "ragged": ragged, "tight": tight, "genq": genq, "inf": inf,
+            "wide": wide}
+
+
+CASES = cases()
+
+
+def rel_err(a, b):
+    scale = max(1.0, float(np.max(np.abs(b))))
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b)))) / scale
+
+
+@pytest.fixture(scope="module")
+def problems(lib):
+    out = {}
+    for name, p in CASES.items():
+        print(f"[parity] building {name}: ns={p.ns} nu={p.nu} N={p.N}", flush=True)
+        gp = condmpc.Problem(p)
+        gp.set_x0(p.x0)
+        out[name] = (p, gp, oracle.reduce_problem(p))
+    yield out
+    for _, gp, _ in out.values():
+        gp.close()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_reduction(problems, name):
+    """Gamma, c, H, h, h0, d of Section 2 against the oracle."""
+    p, gp, red = problems[name]
+    ex = gp.export_dense()
+    assert rel_err(ex["Gamma"], red.Gamma) <= 1e-13
+    assert rel_err(ex["c"], red.c) <= 1e-13
+    assert rel_err(ex["H"], red.H) <= 1e-12
+    assert np.array_equal(ex["H"], ex["H"].T)
+    assert rel_err(ex["h"], red.h) <= 1e-12
+    assert abs(ex["h0"] - red.h0) <= 1e-12 * max(1.0, abs(red.h0))
+    keep = np.isfinite(ex["d"])
+    assert keep.sum() == red.d.size
+    assert rel_err(ex["d"][keep], red.d) <= 1e-13
+
+
+def _sigma_full(gp, red, sig_kept):
+    d = gp.export_dense(gamma=False)["d"]
+    keep = np.isfinite(d)
+    full = np.zeros(gp.m)
+    full[keep] = sig_kept
+    return full, keep
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("scale", [1e-6, 1.0, 1e6])
+def test_condensed_matrix(problems, name, scale):
+    """K = H + J' Sigma J (eqn. (cond_KKT) left-hand side), lower triangle."""
+    p, gp, red = problems[name]
+    rng = np.random.default_rng(3)
+    sig = scale * rng.uniform(0.01, 10.0, red.d.size)
+    full, _ = _sigma_full(gp, red, sig)
+    K = torch.zeros(gp.n, gp.n, dtype=torch.float64, device=DEV)
+    gp.form_condensed(gpu(full), K)
+    K_ref = oracle.condensed_matrix(red, sig)
+    Kg = K.cpu().numpy()
+    lo = np.tril_indices(gp.n)
+    assert rel_err(Kg[lo], K_ref[lo]) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 130, 257, 500])
+def test_cholesky_and_solve(lib, n):
+    rng = np.random.default_rng(n)
+    M = rng.normal(size=(n, n))
+    A = M @ M.T + n * np.eye(n)
+    Kt = gpu(np.triu(np.full((n, n), 7.0), 1) + np.tril(A))     # junk above the diagonal
+    info = condmpc.potrf(Kt)
+    assert info == 0
+    L = np.tril(Kt.cpu().numpy())
+    L_ref = np.linalg.cholesky(A)
+    assert rel_err(L, L_ref) <= 1e-12
+    assert np.all(np.triu(Kt.cpu().numpy(), 1) == np.triu(np.full((n, n), 7.0), 1))
+    b = rng.normal(size=n)
+    bt = gpu(b)
+    condmpc.potrs(Kt, bt)
+    x_ref = np.linalg.solve(A, b)
+    assert rel_err(bt.cpu().numpy(), x_ref) <= 1e-11
+
+
+def test_cholesky_reports_indefinite(lib):
+    n = 100
+    A = np.eye(n)
+    A[70, 70] = -1.0
+    with pytest.raises(condmpc.CmpcError) as e:
+        condmpc.potrf(gpu(A))
+    assert e.value.code == condmpc.ERR_CHOLESKY
+    assert "71" in str(e.value)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_newton_step(problems, name):
+    """One condensed Newton direction and its step lengths from a random interior point."""
+    p, gp, red = problems[name]
+    rng = np.random.default_rng(11)
+    mk = red.d.size
+    v = rng.uniform(-0.2, 0.2, gp.n)
+    s = rng.uniform(0.05, 1.0, mk)
+    lam = rng.uniform(0.01, 2.0, mk)
+    z = rng.uniform(0.01, 2.0, mk)
+    mu, tau = 0.03, 0.99
+    ref = oracle.condensed_step(red, v, s, lam, z, mu)
+    d = gp.export_dense(gamma=False)["d"]
+    keep = np.isfinite(d)
+
+    def full(x, fill):
+        f = np.full(gp.m, fill)
+        f[keep] = x
+        return gpu(f)
+    out = gp.newton_step(gpu(v), full(s, 1.0), full(lam, 0.0), full(z, 0.0), mu, tau)
+    assert rel_err(out["pv"].cpu().numpy(), ref["pv"]) <= 1e-9
+    for k in ("ps", "plam", "pz"):
+        g = out[k].cpu().numpy()
+        assert rel_err(g[keep], ref[k]) <= 1e-9, k
+        assert np.all(g[~keep] == 0.0)
+    a_ref = oracle.fraction_to_boundary(s, ref["ps"], tau)
+    az_ref = oracle.fraction_to_boundary(z, ref["pz"], tau)
+    assert out["alpha"] == pytest.approx(a_ref, rel=1e-9)
+    assert out["alpha_z"] == pytest.approx(az_ref, rel=1e-9)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_full_solve(problems, name):
+    """Algorithm 1 end to end against the oracle: same status and iteration count,
+    objective within 1e-8 relative, KKT residuals within 1e-8."""
+    p, gp, red = problems[name]
+    ref = oracle.solve(p, red=red)
+    res = gp.solve()
+    print(f"[parity] {name}: gpu iters {res['iters']} obj {res['obj']:.12e} | "
+          f"oracle iters {ref.iters} obj {ref.obj:.12e}", flush=True)
+    assert res["status"] == condmpc.OK == ref.status
+    assert res["iters"] == ref.iters
+    assert abs(res["obj"] - ref.obj) <= 1e-8 * max(1.0, abs(ref.obj))
+    assert res["primal_res"] <= 1e-8 and res["dual_res"] <= 1e-8
+    assert res["compl_res"] <= 1e-8
+    u, x = gp.solution()
+    assert rel_err(u, ref.v) <= 1e-6
+    assert rel_err(x, ref.x) <= 1e-6
+    # the states returned are the simulated ones of the returned controls
+    assert rel_err(x, oracle.simulate(p, u)) <= 1e-12
+    # weak duality: objective within the final duality gap of the oracle's
+    assert abs(res["gap"] - ref.gap) <= 1e-6 * max(ref.gap, 1e-12) + 1e-12
+
+
+def test_repeat_solve_is_deterministic(problems):
+    p, gp, red = problems["wide"]
+    r1 = gp.solve()
+    u1, _ = gp.solution(with_x=False)
+    r2 = gp.solve()
+    u2, _ = gp.solution(with_x=False)
+    assert r1["iters"] == r2["iters"] and r1["obj"] == r2["obj"]
+    assert np.array_equal(u1, u2)
+
+
+def test_new_x0_reuses_problem(problems):
+    p, gp, red = problems["small"]
+    x0b = np.random.default_rng(77).uniform(-0.3, 0.3, p.ns)
+    pb = p.with_x0(x0b)
+    gp.set_x0(x0b)
+    res = gp.solve()
+    ref = oracle.solve(pb)
+    gp.set_x0(p.x0)
+    assert res["status"] == 0 and res["iters"] == ref.iters
+    assert abs(res["obj"] - ref.obj) <= 1e-8 * max(1.0, abs(ref.obj))
+
+
+def test_x0_outside_bounds_rejected(problems):
+    p, gp, red = problems["small"]
+    bad = p.x0.copy()
+    bad[3] = 0.9
+    with pytest.raises(condmpc.CmpcError) as e:
+        gp.set_x0(bad)
+    assert e.value.code == condmpc.ERR_X0_BOUNDS
+    bad[3] = np.nan
+    with pytest.raises(condmpc.CmpcError) as e:
+        gp.set_x0(bad)
+    assert e.value.code == condmpc.ERR_NONFINITE
+    gp.set_x0(p.x0)
+
+
+def test_iteration_limit(problems):
+    p, gp, red = problems["tight"]
+    res = gp.solve(max_iter=2)
+    assert res["status"] == condmpc.MAX_ITER and res["iters"] == 2
+    ref = oracle.solve(p, red=red, max_iter=2)
+    assert ref.status == oracle.STATUS_MAX_ITER
+    assert abs(res["obj"] - ref.obj) <= 1e-9 * max(1.0, abs(ref.obj))
