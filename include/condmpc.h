@@ -72,7 +72,11 @@ typedef struct {
   int precision;     /* CMPC_FP64 (default), CMPC_FP32_SYRK or CMPC_BF16_SYRK */
   int max_refine;    /* mixed modes: refinement steps per solve (default 5) */
   double mu_switch;  /* mixed modes: use the FP64 SYRK once mu < mu_switch (default 1e-6) */
-  int check_every;   /* read the convergence flag every this many iterations (default 1) */
+  int check_every;   /* iterations queued ahead of the convergence flag the host has seen
+                        (default 2); after convergence the queued ones exit at once */
+  int profile;       /* nonzero: time the formation and the Cholesky factorisation of K in
+                        every iteration with HIP events on the problem's stream (fills
+                        ms_syrk, ms_form, ms_potrf) */
 } cmpc_options;
 
 typedef struct {
@@ -87,7 +91,23 @@ typedef struct {
   double mu;           /* final barrier parameter */
   double gap;          /* s'z */
   double ms_total;     /* wall time of the solve on the stream, milliseconds */
+  double ms_syrk;      /* profile: time in the stream-K SYRK kernel over the iterations */
+  double ms_form;      /* profile: time forming K (SYRK + adding H, diag and partials) */
+  double ms_potrf;     /* profile: time in the Cholesky factorisation over the iterations */
 } cmpc_result;
+
+/* Sizes and per-iteration work of a problem. */
+typedef struct {
+  int n, mx, m;              /* as cmpc_problem_dims */
+  long long gamma_nnz;       /* stored entries of Gamma: ns nu N(N+1)/2 */
+  double syrk_flops;         /* algorithmic FLOPs of one formation of K: 2 per multiply-add
+                                over the structural nonzeros, lower triangle with diagonal,
+                                sum_t ns (t nu)(t nu + 1) */
+  double potrf_flops;        /* n^3 / 3 */
+  int syrk_workgroups;       /* launch size of the SYRK */
+  int syrk_partial_slots;    /* partial tiles written by one SYRK */
+  double device_bytes;       /* device memory held by the problem */
+} cmpc_info;
 
 /* Default options (values above). */
 void cmpc_default_options(cmpc_options* opts);
@@ -101,6 +121,9 @@ int cmpc_problem_create(const cmpc_lq_desc* desc, void* stream, cmpc_problem** o
 
 /* Release all device memory of the problem (NULL is ignored).  Synchronises its stream. */
 void cmpc_problem_destroy(cmpc_problem* p);
+
+/* Fill *info (host). */
+int cmpc_problem_info(const cmpc_problem* p, cmpc_info* info);
 
 /* n = nu N (size of K), mx = ns N (rows of Gamma), m = 2 mx + 2 n (inequality rows of
  * eqn. (dense) before rows with infinite bounds are dropped).  Any output may be NULL. */

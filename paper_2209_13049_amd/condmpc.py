@@ -21,7 +21,7 @@ FP64, FP32_SYRK, BF16_SYRK = 0, 1, 2
 # every function declared in include/condmpc.h
 EXPORTS = [
     "cmpc_default_options", "cmpc_problem_create", "cmpc_problem_destroy", "cmpc_problem_dims",
-    "cmpc_set_x0", "cmpc_solve", "cmpc_get_solution", "cmpc_get_iterate", "cmpc_export_dense",
+    "cmpc_problem_info", "cmpc_set_x0", "cmpc_solve", "cmpc_get_solution", "cmpc_get_iterate", "cmpc_export_dense",
     "cmpc_form_condensed", "cmpc_newton_step", "cmpc_potrf", "cmpc_potrs", "cmpc_last_error",
     "cmpc_status_str",
 ]
@@ -38,7 +38,8 @@ class LQDesc(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("max_refine", ctypes.c_int),
-                ("mu_switch", ctypes.c_double), ("check_every", ctypes.c_int)]
+                ("mu_switch", ctypes.c_double), ("check_every", ctypes.c_int),
+                ("profile", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -47,7 +48,18 @@ class Result(ctypes.Structure):
                 ("obj", ctypes.c_double), ("primal_res", ctypes.c_double),
                 ("dual_res", ctypes.c_double), ("compl_res", ctypes.c_double),
                 ("mu", ctypes.c_double), ("gap", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("ms_syrk", ctypes.c_double),
+                ("ms_form", ctypes.c_double), ("ms_potrf", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("mx", ctypes.c_int), ("m", ctypes.c_int),
+                ("gamma_nnz", ctypes.c_longlong), ("syrk_flops", ctypes.c_double),
+                ("potrf_flops", ctypes.c_double), ("syrk_workgroups", ctypes.c_int),
+                ("syrk_partial_slots", ctypes.c_int), ("device_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -70,6 +82,7 @@ def load(path: str = LIB_PATH):
         "cmpc_problem_create": (i, [ctypes.POINTER(LQDesc), vp, ctypes.POINTER(vp)]),
         "cmpc_problem_destroy": (None, [vp]),
         "cmpc_problem_dims": (i, [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]),
+        "cmpc_problem_info": (i, [vp, ctypes.POINTER(Info)]),
         "cmpc_set_x0": (i, [vp, vp, i]),
         "cmpc_solve": (i, [vp, ctypes.POINTER(Options), ctypes.POINTER(Result)]),
         "cmpc_get_solution": (i, [vp, vp, vp, i]),
@@ -151,6 +164,11 @@ class Problem:
         _check(lib.cmpc_problem_dims(self._h, ctypes.byref(n), ctypes.byref(mx), ctypes.byref(m)))
         self.n, self.mx, self.m = n.value, mx.value, m.value
         self.ns, self.nu, self.N = A.shape[0], B.shape[1], int(prob.N)
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(load().cmpc_problem_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
 
     def close(self):
         if self._h:

@@ -28,15 +28,21 @@ static void free_problem(Problem* p) {
                      &p->lam, &p->z,  &p->gv,   &p->pv,    &p->ps,   &p->plam, &p->pz,
                      &p->gpv, &p->rhs, &p->Dx,  &p->Du,    &p->wx,   &p->wu,   &p->gt,
                      &p->Hv, &p->tmpn, &p->tmpn2, &p->tmpmx, &p->norm_part, &p->alpha_part,
-                     &p->gt_part};
+                     &p->gt_part, &p->Wdiag};
   for (double** b : bufs) {
     if (*b) hipFree(*b);
     *b = nullptr;
   }
   if (p->goff) hipFree(p->goff);
+  if (p->a_rowptr) hipFree(p->a_rowptr);
+  if (p->a_col) hipFree(p->a_col);
+  if (p->a_val) hipFree(p->a_val);
+  if (p->red_part) hipFree(p->red_part);
   if (p->Gam32) hipFree(p->Gam32);
   if (p->Gam16) hipFree(p->Gam16);
   if (p->st) hipFree(p->st);
+  for (hipEvent_t e : p->prof_ev) hipEventDestroy(e);
+  if (p->hflags) hipHostFree(p->hflags);
   if (p->ev0) hipEventDestroy(p->ev0);
   if (p->ev1) hipEventDestroy(p->ev1);
   syrk_free(p->syrk);
@@ -147,6 +153,36 @@ static int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
   TRY(upload(&p->xu, desc->xu, ns, stream));
   TRY(upload(&p->ul, desc->ul, nu, stream));
   TRY(upload(&p->uu, desc->uu, nu, stream));
+  {  // sparse copy of A for the free response, when A is sparse enough
+    std::vector<int> rowptr(ns + 1, 0), col;
+    std::vector<double> val;
+    for (int i = 0; i < ns; ++i) {
+      for (int j = 0; j < ns; ++j) {
+        const double a = desc->A[(size_t)i * ns + j];
+        if (a != 0.0) {
+          col.push_back(j);
+          val.push_back(a);
+        }
+      }
+      rowptr[i + 1] = (int)col.size();
+    }
+    if ((double)col.size() <= 0.25 * (double)ns * ns && ns <= 4096 && !col.empty()) {
+      if (hipMalloc(&p->a_rowptr, sizeof(int) * (ns + 1)) != hipSuccess ||
+          hipMalloc(&p->a_col, sizeof(int) * col.size()) != hipSuccess) {
+        free_problem(p);
+        return CMPC_ERR_NOMEM;
+      }
+      TRY(upload(&p->a_val, val.data(), val.size(), stream));
+      if (hipMemcpyAsync(p->a_rowptr, rowptr.data(), sizeof(int) * (ns + 1), hipMemcpyHostToDevice,
+                         stream) != hipSuccess ||
+          hipMemcpyAsync(p->a_col, col.data(), sizeof(int) * col.size(), hipMemcpyHostToDevice,
+                         stream) != hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess) {
+        free_problem(p);
+        return CMPC_ERR_HIP;
+      }
+    }
+  }
   bool qd = true;
   for (int i = 0; i < ns && qd; ++i)
     for (int j = 0; j < ns; ++j)
@@ -243,38 +279,34 @@ static int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
 }
 
 static int set_x0(Problem& p, const double* x0, int on_device) {
-  std::vector<double> hx(p.ns);
-  if (on_device) {
-    CMPC_HIP(hipMemcpyAsync(hx.data(), x0, sizeof(double) * p.ns, hipMemcpyDeviceToHost, p.stream));
-    CMPC_HIP(hipStreamSynchronize(p.stream));
-  } else {
-    std::memcpy(hx.data(), x0, sizeof(double) * p.ns);
-  }
-  if (!all_finite(hx.data(), p.ns)) {
-    set_error("x0 has a non-finite entry");
-    return CMPC_ERR_NONFINITE;
-  }
-  std::vector<double> xl(p.ns), xu(p.ns);
-  CMPC_HIP(hipMemcpyAsync(xl.data(), p.xl, sizeof(double) * p.ns, hipMemcpyDeviceToHost, p.stream));
-  CMPC_HIP(hipMemcpyAsync(xu.data(), p.xu, sizeof(double) * p.ns, hipMemcpyDeviceToHost, p.stream));
-  CMPC_HIP(hipStreamSynchronize(p.stream));
-  for (int i = 0; i < p.ns; ++i)
-    if (hx[i] < xl[i] || hx[i] > xu[i]) {
-      set_error("x0 violates a state bound");
-      return CMPC_ERR_X0_BOUNDS;
+  if (!on_device) {
+    for (int i = 0; i < p.ns; ++i)
+      if (!std::isfinite(x0[i])) {
+        set_error("x0 has a non-finite entry");
+        return CMPC_ERR_NONFINITE;
+      }
+    if (p.xl_host.empty()) {
+      p.xl_host.resize(p.ns);
+      p.xu_host.resize(p.ns);
+      CMPC_HIP(hipMemcpy(p.xl_host.data(), p.xl, sizeof(double) * p.ns, hipMemcpyDeviceToHost));
+      CMPC_HIP(hipMemcpy(p.xu_host.data(), p.xu, sizeof(double) * p.ns, hipMemcpyDeviceToHost));
     }
+    for (int i = 0; i < p.ns; ++i)
+      if (x0[i] < p.xl_host[i] || x0[i] > p.xu_host[i]) {
+        set_error("x0 violates a state bound");
+        return CMPC_ERR_X0_BOUNDS;
+      }
+  }
   CMPC_HIP(hipMemcpyAsync(p.x0, x0, sizeof(double) * p.ns,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p.stream));
-  // c_t = A^t x0, t = 1..N
-  if (launch_gemv(p.stream, p.A, p.x0, p.c, p.ns, p.ns)) return CMPC_ERR_HIP;
-  for (int t = 2; t <= p.N; ++t)
-    if (launch_gemv(p.stream, p.A, p.c + (size_t)(t - 2) * p.ns, p.c + (size_t)(t - 1) * p.ns,
-                    p.ns, p.ns))
-      return CMPC_ERR_HIP;
+  // device x0: validated on the device; a bad x0 makes the next solve return the error
+  if (launch_check_x0(p)) return CMPC_ERR_HIP;
+  if (launch_free_response(p)) return CMPC_ERR_HIP;  // c_t = A^t x0
   if (launch_block_diag_weight(p, p.c, p.qc)) return CMPC_ERR_HIP;
   if (launch_gamma_t(p, p.qc, 1, p.h, nullptr)) return CMPC_ERR_HIP;
   if (launch_h0(p)) return CMPC_ERR_HIP;
   if (launch_make_d(p)) return CMPC_ERR_HIP;
+  if (!on_device) CMPC_HIP(hipStreamSynchronize(p.stream));  // host x0 buffer may be reused
   p.have_x0 = true;
   return 0;
 }
@@ -289,42 +321,89 @@ static int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
     return CMPC_ERR_INVALID;
   }
   const int check = std::max(1, o.check_every);
-  CMPC_HIP(hipEventRecord(p.ev0, p.stream));
-  if (launch_ipm_init(p, o)) return CMPC_ERR_HIP;
-  int* hflag = nullptr;
-  CMPC_HIP(hipHostMalloc((void**)&hflag, sizeof(int)));
-  *hflag = 0;
-  int rc = 0;
-  for (int it = 0; it <= o.max_iter && rc == 0; ++it) {
-    rc = launch_prep(p);
-    if (!rc) rc = launch_mu_rhs(p);
-    if (!rc) rc = launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K);
-    if (!rc) rc = launch_potrf(p.stream, p.K, p.n, p.n, &p.st->done, &p.st->info, &p.st->status);
-    if (!rc) rc = launch_step(p);
-    if (!rc) rc = launch_update(p);
-    if (rc) break;
-    if ((it + 1) % check == 0 || it == o.max_iter) {
-      if (hipMemcpyAsync(hflag, &p.st->done, sizeof(int), hipMemcpyDeviceToHost, p.stream) !=
-              hipSuccess ||
-          hipStreamSynchronize(p.stream) != hipSuccess) {
-        set_error(std::string("solve: ") + hipGetErrorString(hipGetLastError()));
-        rc = CMPC_ERR_HIP;
-        break;
-      }
-      if (*hflag) break;
+  const bool prof = o.profile != 0;
+  if (prof) {
+    const size_t need = 4 * (size_t)(o.max_iter + 1);
+    while (p.prof_ev.size() < need) {
+      hipEvent_t e;
+      CMPC_HIP(hipEventCreate(&e));
+      p.prof_ev.push_back(e);
     }
   }
-  hipHostFree(hflag);
+  CMPC_HIP(hipEventRecord(p.ev0, p.stream));
+  if (launch_ipm_init(p, o)) return CMPC_ERR_HIP;
+  // Convergence is read back without stalling the queue: the last kernel of iteration it
+  // stores 1 (running) or 2 (done) into slot it % R of a mapped pinned ring; before queueing
+  // iteration it + depth the host polls slot it only.
+  const int depth = std::max(1, check);
+  constexpr int R = 16;
+  if (p.hflags == nullptr) {
+    CMPC_HIP(hipHostMalloc((void**)&p.hflags, sizeof(int) * R, hipHostMallocMapped));
+    CMPC_HIP(hipHostGetDevicePointer((void**)&p.dflags, p.hflags, 0));
+  }
+  volatile int* hf = p.hflags;
+  int rc = 0;
+  for (int it = 0; it <= o.max_iter && rc == 0; ++it) {
+    if (it >= depth) {
+      const int slot = (it - depth) % R;
+      long long spins = 0;
+      while (hf[slot] == 0) {
+        if ((++spins & 1023) == 0) {
+          const hipError_t q = hipStreamQuery(p.stream);
+          if (q == hipSuccess && hf[slot] == 0) {  // queue drained but the flag never came
+            set_error("solve: iteration flag missing");
+            rc = CMPC_ERR_HIP;
+            break;
+          }
+          if (q != hipSuccess && q != hipErrorNotReady) {
+            set_error(std::string("solve: ") + hipGetErrorString(q));
+            rc = CMPC_ERR_HIP;
+            break;
+          }
+        }
+      }
+      if (rc) break;
+      if (hf[slot] == 2) break;
+    }
+    const int slot = it % R;
+    hf[slot] = 0;
+    if (prof) {
+      rc = launch_prep(p);
+      if (!rc) rc = launch_mu_rhs(p);
+      if (!rc) rc = launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K, p.prof_ev[4 * it],
+                                p.prof_ev[4 * it + 1]);
+      if (!rc) rc = launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info,
+                                 &p.st->status, p.prof_ev[4 * it + 2], p.prof_ev[4 * it + 3]);
+    } else {
+      rc = launch_prep(p);
+      if (!rc) rc = launch_mu_rhs(p);
+      if (!rc) rc = launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K);
+      if (!rc) rc = launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info,
+                                 &p.st->status);
+    }
+    if (!rc) rc = launch_step(p);
+    if (!rc) rc = launch_update(p);
+    if (!rc) rc = launch_publish(p, slot);
+  }
   if (rc) return rc;
-  if (launch_finalize(p)) return CMPC_ERR_HIP;
   CMPC_HIP(hipEventRecord(p.ev1, p.stream));
   IpmState hs;
-  double gap = 0;
   CMPC_HIP(hipMemcpyAsync(&hs, p.st, sizeof(IpmState), hipMemcpyDeviceToHost, p.stream));
-  CMPC_HIP(hipMemcpyAsync(&gap, p.tmpn, sizeof(double), hipMemcpyDeviceToHost, p.stream));
   CMPC_HIP(hipStreamSynchronize(p.stream));
+  const double gap = hs.gap;
   float ms = 0.f;
   hipEventElapsedTime(&ms, p.ev0, p.ev1);
+  double ms_syrk = 0.0, ms_form = 0.0, ms_potrf = 0.0;
+  if (prof)
+    for (int it = 0; it < hs.iter && 4 * it + 3 < (int)p.prof_ev.size(); ++it) {
+      float a = 0.f, b = 0.f, c = 0.f;
+      hipEventElapsedTime(&a, p.prof_ev[4 * it], p.prof_ev[4 * it + 1]);
+      hipEventElapsedTime(&b, p.prof_ev[4 * it], p.prof_ev[4 * it + 2]);
+      hipEventElapsedTime(&c, p.prof_ev[4 * it + 2], p.prof_ev[4 * it + 3]);
+      ms_syrk += a;
+      ms_form += b;
+      ms_potrf += c;
+    }
   const int status = hs.done ? hs.status : CMPC_MAX_ITER;
   if (res) {
     res->status = status;
@@ -338,6 +417,9 @@ static int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
     res->mu = hs.mu;
     res->gap = gap;
     res->ms_total = ms;
+    res->ms_syrk = ms_syrk;
+    res->ms_form = ms_form;
+    res->ms_potrf = ms_potrf;
   }
   if (status == CMPC_ERR_CHOLESKY) set_error("Cholesky breakdown at column " + std::to_string(hs.info));
   return status;
@@ -360,7 +442,31 @@ void cmpc_default_options(cmpc_options* o) {
   o->precision = CMPC_FP64;
   o->max_refine = 5;
   o->mu_switch = 1e-6;
-  o->check_every = 1;
+  o->check_every = 2;
+  o->profile = 0;
+}
+
+int cmpc_problem_info(const cmpc_problem* h, cmpc_info* info) {
+  if (!h || !info) {
+    set_error("NULL argument");
+    return CMPC_ERR_INVALID;
+  }
+  const Problem& p = *h->p;
+  info->n = p.n;
+  info->mx = p.mx;
+  info->m = p.m;
+  info->gamma_nnz = p.off[p.N];
+  info->syrk_flops = p.syrk.flops_structural;
+  info->potrf_flops = (double)p.n * p.n * p.n / 3.0;
+  info->syrk_workgroups = p.syrk.nwg;
+  info->syrk_partial_slots = p.syrk.nslots;
+  double b = 8.0 * (double)p.off[p.N];
+  if (p.Gam32) b += 4.0 * (double)p.off[p.N];
+  b += 8.0 * (2.0 * p.n * p.n + (double)p.N * p.ns * p.nu + 2.0 * p.ns * p.ns);
+  b += 8.0 * 4096.0 * p.syrk.nslots + 8.0 * 3.0 * p.n * (double)p.gt_chunks;
+  b += 8.0 * (7.0 * p.m + 12.0 * p.mx + 16.0 * p.n);
+  info->device_bytes = b;
+  return 0;
 }
 
 int cmpc_problem_create(const cmpc_lq_desc* desc, void* stream, cmpc_problem** out) {
@@ -544,15 +650,22 @@ int cmpc_potrf(double* K, int n, int ld, void* stream, int* info) {
   }
   hipStream_t s = (hipStream_t)stream;
   int* flags = nullptr;  // done, info, status
+  double* Wall = nullptr;
   CMPC_HIP(hipMalloc(&flags, 3 * sizeof(int)));
+  if (hipMalloc(&Wall, sizeof(double) * 4096 * (size_t)ceil_div(n, 64)) != hipSuccess) {
+    hipFree(flags);
+    set_error("out of device memory");
+    return CMPC_ERR_NOMEM;
+  }
   int rc = 0;
   if (hipMemsetAsync(flags, 0, 3 * sizeof(int), s) != hipSuccess) rc = CMPC_ERR_HIP;
-  if (!rc) rc = launch_potrf(s, K, n, ld, flags, flags + 1, flags + 2);
+  if (!rc) rc = launch_potrf(s, K, n, ld, Wall, flags, flags + 1, flags + 2);
   int hf[3] = {0, 0, 0};
   if (!rc && (hipMemcpyAsync(hf, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
               hipStreamSynchronize(s) != hipSuccess))
     rc = CMPC_ERR_HIP;
   hipFree(flags);
+  hipFree(Wall);
   if (rc) return rc;
   if (info) *info = hf[1];
   if (hf[0]) {
@@ -567,10 +680,18 @@ int cmpc_potrs(const double* L, int n, int ld, double* b, void* stream) {
     set_error("invalid argument");
     return CMPC_ERR_INVALID;
   }
+  if (n > 8192) {
+    set_error("n > 8192 is not supported");
+    return CMPC_ERR_INVALID;
+  }
   hipStream_t s = (hipStream_t)stream;
-  if (launch_potrs(s, L, n, ld, b, nullptr)) return CMPC_ERR_HIP;
-  CMPC_HIP(hipStreamSynchronize(s));
-  return 0;
+  double* Wall = nullptr;
+  CMPC_HIP(hipMalloc(&Wall, sizeof(double) * (4096 * (size_t)ceil_div(n, 64) + n)));
+  int rc = launch_tri_inv(s, L, n, ld, Wall);
+  if (!rc) rc = launch_potrs(s, L, n, ld, Wall, b, b, Wall + 4096 * (size_t)ceil_div(n, 64), nullptr);
+  if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = CMPC_ERR_HIP;
+  hipFree(Wall);
+  return rc;
 }
 
 const char* cmpc_last_error(void) { return g_error.c_str(); }

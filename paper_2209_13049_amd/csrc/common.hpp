@@ -1,6 +1,7 @@
 // Shared device helpers and launch utilities for the condensed-space IPM library (gfx950).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -1,6 +1,8 @@
 // Setup kernels: the state elimination of Section 2 (eqn. (x_def)) and the x0-dependent
 // data of eqn. (dense).  They run once per problem or once per initial state, not per
 // interior-point iteration.
+#include <algorithm>
+
 #include "problem.hpp"
 
 namespace cmpc {
@@ -148,26 +150,106 @@ int launch_make_d(Problem& p) {
   return 0;
 }
 
-// h0 = 1/2 x0' (Q x0) + 1/2 c' (Qbar c); Q x0 is in tmp (ns), Qbar c in qc (mx).
+// h0 = 1/2 x0' (Q x0) + 1/2 c' (Qbar c) in two stages: per-block partial sums of c' qc,
+// then one workgroup adds them (fixed order) to x0' (Q x0).
+__global__ __launch_bounds__(256) void dot_partial_kernel(const double* __restrict__ a,
+                                                          const double* __restrict__ b,
+                                                          long long len,
+                                                          double* __restrict__ part) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < len;
+       i += (long long)gridDim.x * 256)
+    acc = fma(a[i], b[i], acc);
+  acc = block_sum256(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
 __global__ __launch_bounds__(256) void h0_kernel(const double* __restrict__ x0,
                                                  const double* __restrict__ qx0,
-                                                 const double* __restrict__ c,
-                                                 const double* __restrict__ qc, int ns, int mx,
-                                                 IpmState* st) {
+                                                 const double* __restrict__ part, int nparts,
+                                                 int ns, IpmState* st) {
   __shared__ double sh[4];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < ns; i += 256) a = fma(x0[i], qx0[i], a);
-  for (int r = threadIdx.x; r < mx; r += 256) b = fma(c[r], qc[r], b);
+  for (int i = threadIdx.x; i < nparts; i += 256) b += part[i];
   a = block_sum256(a, sh);
   b = block_sum256(b, sh);
   if (threadIdx.x == 0) st->h0 = 0.5 * a + 0.5 * b;
 }
 
 int launch_h0(Problem& p) {
-  // tmpn2 has room for max(n, ns) doubles
+  // tmpn2 has room for max(n, ns) doubles; red_part for 1024
   if (launch_gemv(p.stream, p.Q, p.x0, p.tmpn2, p.ns, p.ns)) return CMPC_ERR_HIP;
-  hipLaunchKernelGGL(h0_kernel, dim3(1), dim3(256), 0, p.stream, p.x0, p.tmpn2, p.c, p.qc, p.ns,
-                     p.mx, p.st);
+  const int nparts = std::min(1024, ceil_div(p.mx, 256));
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(nparts), dim3(256), 0, p.stream, p.c, p.qc,
+                     (long long)p.mx, p.red_part);
+  CMPC_LAUNCH_CHECK();
+  hipLaunchKernelGGL(h0_kernel, dim3(1), dim3(256), 0, p.stream, p.x0, p.tmpn2, p.red_part, nparts,
+                     p.ns, p.st);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// Free response c_t = A^t x0, t = 1..N, for a sparse A (CSR): one workgroup keeps the
+// state in LDS and steps through the horizon.
+__global__ __launch_bounds__(1024) void free_response_csr_kernel(
+    const int* __restrict__ rowptr, const int* __restrict__ col, const double* __restrict__ val,
+    const double* __restrict__ x0, double* __restrict__ c, int ns, int N) {
+  extern __shared__ double buf[];  // 2 ns
+  double* cur = buf;
+  double* nxt = buf + ns;
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) cur[i] = x0[i];
+  __syncthreads();
+  for (int t = 1; t <= N; ++t) {
+    for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+      double acc = 0.0;
+      for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) acc = fma(val[e], cur[col[e]], acc);
+      nxt[i] = acc;
+      c[(long long)(t - 1) * ns + i] = acc;
+    }
+    __syncthreads();
+    double* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+}
+
+int launch_free_response(Problem& p) {
+  if (p.a_rowptr != nullptr) {
+    hipLaunchKernelGGL(free_response_csr_kernel, dim3(1), dim3(1024),
+                       sizeof(double) * 2 * (size_t)p.ns, p.stream, p.a_rowptr, p.a_col, p.a_val,
+                       p.x0, p.c, p.ns, p.N);
+    CMPC_LAUNCH_CHECK();
+    return 0;
+  }
+  if (launch_gemv(p.stream, p.A, p.x0, p.c, p.ns, p.ns)) return CMPC_ERR_HIP;
+  for (int t = 2; t <= p.N; ++t)
+    if (launch_gemv(p.stream, p.A, p.c + (size_t)(t - 2) * p.ns, p.c + (size_t)(t - 1) * p.ns,
+                    p.ns, p.ns))
+      return CMPC_ERR_HIP;
+  return 0;
+}
+
+// Validity of a device-resident x0: 1 = outside [xl, xu], 2 = not finite.
+__global__ void check_x0_kernel(const double* __restrict__ x0, const double* __restrict__ xl,
+                                const double* __restrict__ xu, int ns, IpmState* st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) st->x0_flag = 0;
+  __syncthreads();
+  if (blockIdx.x != 0) return;
+  int flag = 0;
+  for (int j = threadIdx.x; j < ns; j += blockDim.x) {
+    const double x = x0[j];
+    if (!isfinite(x)) flag = max(flag, 2);
+    else if (x < xl[j] || x > xu[j]) flag = max(flag, 1);
+  }
+  if (flag) atomicMax(&st->x0_flag, flag);
+}
+
+int launch_check_x0(Problem& p) {
+  hipLaunchKernelGGL(check_x0_kernel, dim3(1), dim3(256), 0, p.stream, p.x0, p.xl, p.xu, p.ns,
+                     p.st);
   CMPC_LAUNCH_CHECK();
   return 0;
 }

@@ -2,106 +2,45 @@
 // condensed matrix is positive definite, so it is factored by Cholesky and p_v follows by
 // triangular solves).  Row-major, lower triangle, leading dimension ld.
 //
-// Blocked right-looking factorisation with 64-column panels:
-//   potrf_diag   one workgroup factors the 64 x 64 diagonal block in LDS;
-//   trsm_panel   the rows below solve X L_kk' = A_ik, one row per thread, L_kk in LDS;
-//   syrk_update  every 64 x 64 tile of the trailing lower triangle subtracts L_ik L_jk'
-//                with v_mfma_f64_16x16x4f64 from LDS-staged panels.
-// The triangular solves run in one workgroup: 64-row blocks, wavefront-wide dot products
-// for the off-diagonal part, a shuffle-broadcast substitution inside each diagonal block.
+// Right-looking blocked factorisation with 64 x 64 tiles and one launch per block column:
+//   chol_first  factors the first diagonal tile and forms its inverse W_0 = L_00^-1;
+//   chol_step k every workgroup owns one tile (i, j), i > k, k <= j <= i:
+//                 X_i = A_ik W_k'  (the panel block L_ik, v_mfma_f64_16x16x4f64 from LDS);
+//                 j == k : writes L_ik;
+//                 j > k  : A_ij -= X_i X_j'  (also MFMA);
+//                 (k+1, k+1) additionally factors its updated tile at once and forms W_{k+1},
+//                 so the next launch finds the next pivot block ready (look-ahead).
+// A diagonal tile is factored by 4 wavefronts (wavefront w owns columns 16w..16w+15, lane
+// = row) with one barrier per column, and inverted by forward substitution with 4 lanes per
+// column (no barriers).  The inverses W_k are kept (nt x 64 x 64) so that the triangular
+// solves become block matrix-vector products.
 #include "problem.hpp"
 
 namespace cmpc {
 
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ K, int ld, int k0,
-                                                         int nb, int* done, int* info,
-                                                         int* status) {
-  __shared__ double a[64][65];
-  if (*done) return;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < 4096; e += 256) {
+typedef double Tile[64][65];
+
+// 1/x from the hardware estimate refined by two Newton-Raphson steps (quadratic convergence
+// from the estimate's ~2^-26 relative error to full double precision).
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ inline void load_tile(const double* __restrict__ K, int ld, int n, int r0, int c0,
+                                 Tile& T) {
+  for (int e = threadIdx.x; e < 4096; e += 256) {
     const int i = e >> 6, j = e & 63;
-    a[i][j] = (i < nb && j <= i) ? K[(long long)(k0 + i) * ld + k0 + j] : (i == j ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    const double piv = a[j][j];
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      if (tid == 0) {
-        *info = k0 + j + 1;
-        *status = CMPC_ERR_CHOLESKY;
-        *done = 1;
-      }
-      return;
-    }
-    const double inv = 1.0 / piv;
-    for (int e = tid; e < 4096; e += 256) {
-      const int i = e >> 6, k = e & 63;
-      if (k > j && k <= i && i < nb) a[i][k] -= a[i][j] * a[k][j] * inv;
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < 4096; e += 256) {
-    const int i = e >> 6, j = e & 63;
-    if (i < nb && j <= i) {
-      const double r = sqrt(a[j][j]);
-      K[(long long)(k0 + i) * ld + k0 + j] = (i == j) ? r : a[i][j] / r;
-    }
+    T[i][j] = (r0 + i < n && c0 + j < n) ? K[(long long)(r0 + i) * ld + c0 + j] : 0.0;
   }
 }
 
-__global__ __launch_bounds__(256) void trsm_panel_kernel(double* __restrict__ K, int ld, int k0,
-                                                         int nb, int n, const int* done) {
-  __shared__ double L[64][65];
-  if (*done) return;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < 4096; e += 256) {
-    const int i = e >> 6, j = e & 63;
-    L[i][j] = (i < nb && j <= i) ? K[(long long)(k0 + i) * ld + k0 + j] : (i == j ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  const int row = k0 + nb + blockIdx.x * 256 + tid;
-  if (row >= n) return;
-  double* rp = K + (long long)row * ld + k0;
-  double x[64];
-#pragma unroll
-  for (int j = 0; j < 64; ++j) x[j] = (j < nb) ? rp[j] : 0.0;
-#pragma unroll
-  for (int j = 0; j < 64; ++j) {
-    double sum = x[j];
-#pragma unroll
-    for (int k = 0; k < j; ++k) sum = fma(-x[k], L[j][k], sum);
-    x[j] = sum / L[j][j];
-  }
-#pragma unroll
-  for (int j = 0; j < 64; ++j)
-    if (j < nb) rp[j] = x[j];
-}
-
-__global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ K, int ld, int k0,
-                                                          int nb, int n, const int* done) {
-  __shared__ double PI[64][65];
-  __shared__ double PJ[64][65];
-  if (*done) return;
-  const int k1 = k0 + nb;
-  // lower-triangular tile index -> (I, J), I >= J
-  const int b = blockIdx.x;
-  int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
-  while ((I + 1) * (I + 2) / 2 <= b) ++I;
-  while (I * (I + 1) / 2 > b) --I;
-  const int J = b - I * (I + 1) / 2;
-  const int r0 = k1 + 64 * I, c0 = k1 + 64 * J;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < 4096; e += 256) {
-    const int i = e >> 6, k = e & 63;
-    PI[i][k] = (r0 + i < n && k < nb) ? K[(long long)(r0 + i) * ld + k0 + k] : 0.0;
-    PJ[i][k] = (c0 + i < n && k < nb) ? K[(long long)(c0 + i) * ld + k0 + k] : 0.0;
-  }
-  __syncthreads();
-  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
-  const int wr = wave >> 1, wc = wave & 1;
-  if (I == J && wc > wr) return;
-  d4 acc[2][2];
+// acc (per wavefront: its 32 x 32 quadrant, 2 x 2 blocks of 16 x 16) = A B'
+__device__ inline void mma_abt(const Tile& A, const Tile& B, d4 (&acc)[2][2], int wr, int wc,
+                               int li, int lk) {
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -110,8 +49,8 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ K
     double xa[2], xb[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      xa[q] = PI[32 * wr + 16 * q + li][4 * ks + lk];
-      xb[q] = PJ[32 * wc + 16 * q + li][4 * ks + lk];
+      xa[q] = A[32 * wr + 16 * q + li][4 * ks + lk];
+      xb[q] = B[32 * wc + 16 * q + li][4 * ks + lk];
     }
 #pragma unroll
     for (int ib = 0; ib < 2; ++ib)
@@ -119,101 +58,453 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double* __restrict__ K
       for (int jb = 0; jb < 2; ++jb)
         acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ib], xb[jb], acc[ib][jb], 0, 0, 0);
   }
+}
+
+// Store a quadrant accumulator into an LDS tile (row = 32 wr + 16 ib + lk + 4 v).
+__device__ inline void store_acc(Tile& T, const d4 (&acc)[2][2], int wr, int wc, int li, int lk) {
 #pragma unroll
   for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int gi = r0 + 32 * wr + 16 * ib + lk + 4 * v;
-        const int gj = c0 + 32 * wc + 16 * jb + li;
-        if (gi < n && gj <= gi) K[(long long)gi * ld + gj] -= acc[ib][jb][v];
-      }
+      for (int v = 0; v < 4; ++v)
+        T[32 * wr + 16 * ib + lk + 4 * v][32 * wc + 16 * jb + li] = acc[ib][jb][v];
 }
 
-int launch_potrf(hipStream_t s, double* K, int n, int ld, int* done, int* info, int* status) {
-  for (int k0 = 0; k0 < n; k0 += 64) {
-    const int nb = n - k0 < 64 ? n - k0 : 64;
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, K, ld, k0, nb, done, info,
-                       status);
-    CMPC_LAUNCH_CHECK();
-    const int rest = n - k0 - nb;
-    if (rest > 0) {
-      hipLaunchKernelGGL(trsm_panel_kernel, dim3(ceil_div(rest, 256)), dim3(256), 0, s, K, ld, k0,
-                         nb, n, done);
-      CMPC_LAUNCH_CHECK();
-      const int nt = ceil_div(rest, 64);
-      hipLaunchKernelGGL(syrk_update_kernel, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, K, ld, k0,
-                         nb, n, done);
-      CMPC_LAUNCH_CHECK();
+// 16 x 16 product C = A B of LDS blocks (row-major, padded stride 65) on one wavefront with
+// v_mfma_f64_16x16x4f64; returns the accumulator (element v of lane l is C[l/16 + 4v][l%16]).
+__device__ inline d4 mma16(const double* A, const double* B, d4 c, int li, int lk) {
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks)
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(A[li * 65 + 4 * ks + lk], B[(4 * ks + lk) * 65 + li],
+                                             c, 0, 0, 0);
+  return c;
+}
+
+// Inverse W = L^-1 of the lower-triangular tile T.  Wavefront b inverts the diagonal 16 x 16
+// block b by forward substitution (4 lanes per column); the blocks below the diagonal follow
+// by block diagonals d = 1, 2, 3:  W_ij = -W_ii (sum_{k=j}^{i-1} L_ik W_kj), as MFMA products.
+__device__ void inv64(const Tile& T, Tile& W, double* rdiag) {
+  __shared__ double S[4][16 * 65];  // per-wavefront 16 x 16 scratch
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  if (t < 64) rdiag[t] = recip(T[t][t]);
+  for (int e = t; e < 4096; e += 256) W[e >> 6][e & 63] = 0.0;
+  __syncthreads();
+  {  // diagonal block w
+    const int c = lane >> 2, p = lane & 3, o = 16 * w;
+    double wv[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) {
+      double part = 0.0;
+#pragma unroll
+      for (int kk = 0; kk <= (ii >> 2); ++kk) {
+        const int k = 4 * kk + p;
+        const double lk = T[o + ii][o + (k < 16 ? k : 15)];
+        part = fma(k < ii ? lk : 0.0, wv[kk], part);
+      }
+      part += __shfl_xor(part, 1, 64);
+      part += __shfl_xor(part, 2, 64);
+      const double val = (ii >= c) ? (((ii == c) ? 1.0 : 0.0) - part) * rdiag[o + ii] : 0.0;
+      if (p == (ii & 3)) wv[ii >> 2] = val;
     }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) W[o + 4 * kk + p][o + c] = wv[kk];
+  }
+  __syncthreads();
+  const int li = lane & 15, lk = lane >> 4;
+  double* Sw = S[w];
+  for (int d = 1; d < 4; ++d) {
+    const int j = w, ii = w + d;  // block (ii, j) handled by wavefront w
+    if (ii < 4) {
+      d4 acc = d4{0, 0, 0, 0};
+      for (int k = j; k < ii; ++k) acc = mma16(&T[16 * ii][16 * k], &W[16 * k][16 * j], acc, li, lk);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Sw[(lk + 4 * v) * 65 + li] = acc[v];
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+      acc = mma16(&W[16 * ii][16 * ii], Sw, d4{0, 0, 0, 0}, li, lk);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) W[16 * ii + lk + 4 * v][16 * j + li] = -acc[v];
+    }
+    __syncthreads();
+  }
+}
+
+__device__ inline double readlane_f64(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Right-looking factorisation of the tile, 4 columns per barrier, for the wavefront holding
+// columns 16 W .. 16 W + 15 of row i (lane i).  The wavefront owning a 4-column panel
+// eliminates it in registers (pivots and panel entries broadcast by readlane), publishes
+// the 4 unscaled columns and pivot reciprocals in LDS, and every wavefront applies the
+// rank-4 update to its later columns.  Entries above the diagonal are updated too (they
+// never feed an entry on or below it and are discarded), so the only tests are static.
+template <int W>
+__device__ __forceinline__ void chol_panels(double (&r)[16], double* pan /* 2 x 64 x 4 */,
+                                            double* pinv /* 2 x 4 */, double* piv, int i,
+                                            int t) {
+#pragma unroll
+  for (int P = 0; P < 16; ++P) {
+    double* pb = pan + (P & 1) * 256;
+    double* ib = pinv + (P & 1) * 4;
+    if (W == (P >> 2)) {
+      const int c0 = 4 * (P & 3);
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int j = 4 * P + jj;
+        const double p = readlane_f64(r[c0 + jj], j);
+        const double ip = recip(p);
+        const double lij = r[c0 + jj] * ip;
+#pragma unroll
+        for (int kk = jj + 1; kk < 4; ++kk)
+          r[c0 + kk] = fma(-lij, readlane_f64(r[c0 + jj], 4 * P + kk), r[c0 + kk]);
+        if (t == 64 * W) {
+          piv[j] = p;
+          ib[jj] = ip;
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) pb[4 * i + jj] = r[c0 + jj];
+    }
+    __syncthreads();
+    if (16 * W + 15 > 4 * P + 3) {
+      double li[4], ipv[4];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        li[jj] = pb[4 * i + jj];
+        ipv[jj] = ib[jj];
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) li[jj] *= ipv[jj];
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        if (16 * W + kk > 4 * P + 3) {
+          const double* pk = pb + 4 * (16 * W + kk);
+          double acc = r[kk];
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) acc = fma(-li[jj], pk[jj], acc);
+          r[kk] = acc;
+        }
+      }
+    }
+  }
+}
+
+// Factor the SPD tile T in place (lower triangle -> L, strict upper -> 0) and write its
+// inverse to W.  Rows >= nvalid are identity padding.  Returns false (uniformly) and the
+// 0-based failing column in *bad if a pivot is not positive and finite.
+__device__ __forceinline__ bool chol_inv64(Tile& T, Tile& W, double* colb, double* piv, int nvalid,
+                                           int* bad) {
+  __shared__ double pan[512], pinv[8];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  // ---- factorisation: wavefront w holds columns 16w..16w+15 of row `lane` in registers
+  const int i = lane;
+  double r[16];
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = 16 * w + kk;
+    double x = (k <= i) ? T[i][k] : 0.0;
+    if (i >= nvalid) x = (k == i) ? 1.0 : 0.0;
+    r[kk] = x;
+  }
+  __syncthreads();
+  switch (w) {  // wavefront-uniform: column indices become compile-time constants
+    case 0: chol_panels<0>(r, pan, pinv, piv, i, t); break;
+    case 1: chol_panels<1>(r, pan, pinv, piv, i, t); break;
+    case 2: chol_panels<2>(r, pan, pinv, piv, i, t); break;
+    default: chol_panels<3>(r, pan, pinv, piv, i, t); break;
+  }
+  __syncthreads();
+  // A pivot that is not positive and finite leaves garbage behind it; it is reported here
+  // (the first such column), after the loop, so the loop itself carries no test.
+  if (t == 0) *bad = 64;
+  __syncthreads();
+  if (t < 64) {
+    const double pj = piv[t];
+    if (!(pj > 0.0) || !isfinite(pj)) atomicMin(bad, t);
+    colb[t] = recip(sqrt(pj));  // 1 / L_jj
+  }
+  __syncthreads();
+  if (*bad < 64) return false;
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = 16 * w + kk;
+    T[i][k] = (k <= i) ? r[kk] * colb[k] : 0.0;
+  }
+  __syncthreads();
+  inv64(T, W, piv);
+  return true;
+}
+
+__device__ inline void write_tile_lower(double* __restrict__ K, int ld, int n, int r0, int c0,
+                                        const Tile& T, bool diag) {
+  for (int e = threadIdx.x; e < 4096; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    if (r0 + i < n && c0 + j < n && (!diag || j <= i)) K[(long long)(r0 + i) * ld + c0 + j] = T[i][j];
+  }
+}
+
+__device__ inline void write_w(double* __restrict__ Wk, const Tile& W) {
+  for (int e = threadIdx.x; e < 4096; e += 256) Wk[e] = W[e >> 6][e & 63];
+}
+
+__device__ inline void load_w(const double* __restrict__ Wk, Tile& W) {
+  for (int e = threadIdx.x; e < 4096; e += 256) W[e >> 6][e & 63] = Wk[e];
+}
+
+__global__ __launch_bounds__(256) void chol_first_kernel(double* __restrict__ K, int ld, int n,
+                                                         double* __restrict__ Wall, int* done,
+                                                         int* info, int* status) {
+  __shared__ Tile T, W;
+  __shared__ double colb[128], piv[64];
+  __shared__ int bad;
+  if (*done) return;
+  load_tile(K, ld, n, 0, 0, T);
+  __syncthreads();
+  const int nvalid = n < 64 ? n : 64;
+  if (!chol_inv64(T, W, colb, piv, nvalid, &bad)) {
+    if (threadIdx.x == 0) {
+      *info = bad + 1;
+      *status = CMPC_ERR_CHOLESKY;
+      *done = 1;
+    }
+    return;
+  }
+  write_tile_lower(K, ld, n, 0, 0, T, true);
+  write_w(Wall, W);
+}
+
+// Launch k: (A) the panel of block column k-1, L_i,k-1 = A_i,k-1 W_k-1' for i >= k, written
+// now because launch k-1 still read A_i,k-1 while forming its updates; (B) for k <= nt-2 the
+// trailing update with block column k, and the factorisation of the next pivot tile.
+__global__ __launch_bounds__(256) void chol_step_kernel(double* __restrict__ K, int ld, int n,
+                                                        int k, int nt, double* __restrict__ Wall,
+                                                        int* done, int* info, int* status) {
+  __shared__ Tile Wt, Xi, Xj;
+  __shared__ double colb[128], piv[64];
+  __shared__ int bad;
+  if (*done) return;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const int wr = wave >> 1, wc = wave & 1;
+  int b = blockIdx.x;
+  d4 acc[2][2];
+  const int npanel = k >= 1 ? nt - k : 0;
+  if (b < npanel) {  // (A) panel tile (k + b, k - 1)
+    const int r0 = 64 * (k + b), c0 = 64 * (k - 1);
+    load_w(Wall + (long long)(k - 1) * 4096, Wt);
+    load_tile(K, ld, n, r0, c0, Xi);
+    __syncthreads();
+    mma_abt(Xi, Wt, acc, wr, wc, li, lk);
+    __syncthreads();
+    store_acc(Xi, acc, wr, wc, li, lk);
+    __syncthreads();
+    write_tile_lower(K, ld, n, r0, c0, Xi, false);
+    return;
+  }
+  b -= npanel;
+  // (B) update tile (ti, tj), k+1 <= tj <= ti: lower-triangular index b
+  int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= b) ++I;
+  while (I > 0 && I * (I + 1) / 2 > b) --I;
+  const int J = b - I * (I + 1) / 2;
+  const int ti = k + 1 + I, tj = k + 1 + J;
+  const int r0 = 64 * ti, c0 = 64 * tj, k0 = 64 * k;
+  const bool diag = ti == tj;
+  load_w(Wall + (long long)k * 4096, Wt);
+  load_tile(K, ld, n, r0, k0, Xi);
+  if (!diag) load_tile(K, ld, n, c0, k0, Xj);
+  __syncthreads();
+  mma_abt(Xi, Wt, acc, wr, wc, li, lk);  // X_i = A_ik W_k'
+  d4 accj[2][2];
+  if (!diag) mma_abt(Xj, Wt, accj, wr, wc, li, lk);  // X_j
+  __syncthreads();
+  store_acc(Xi, acc, wr, wc, li, lk);
+  if (!diag) store_acc(Xj, accj, wr, wc, li, lk);
+  __syncthreads();
+  mma_abt(Xi, diag ? Xi : Xj, acc, wr, wc, li, lk);  // X_i X_j'
+  __syncthreads();
+  if (!(diag && ti == k + 1)) {
+    if (diag && wc > wr) return;
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gi = r0 + 32 * wr + 16 * ib + lk + 4 * v;
+          const int gj = c0 + 32 * wc + 16 * jb + li;
+          if (gi < n && gj <= gi) K[(long long)gi * ld + gj] -= acc[ib][jb][v];
+        }
+    return;
+  }
+  // the next pivot tile: update in LDS, factor, invert, publish
+  load_tile(K, ld, n, r0, c0, Xj);
+  __syncthreads();
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Xj[32 * wr + 16 * ib + lk + 4 * v][32 * wc + 16 * jb + li] -= acc[ib][jb][v];
+  __syncthreads();
+  const int nvalid = n - r0 < 64 ? n - r0 : 64;
+  if (!chol_inv64(Xj, Xi, colb, piv, nvalid, &bad)) {
+    if (threadIdx.x == 0) {
+      *info = r0 + bad + 1;
+      *status = CMPC_ERR_CHOLESKY;
+      *done = 1;
+    }
+    return;
+  }
+  write_tile_lower(K, ld, n, r0, c0, Xj, true);
+  write_w(Wall + (long long)(k + 1) * 4096, Xi);
+}
+
+int launch_potrf(hipStream_t s, double* K, int n, int ld, double* Wall, int* done, int* info,
+                 int* status, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  const int nt = ceil_div(n, 64);
+  hipExtLaunchKernelGGL(chol_first_kernel, dim3(1), dim3(256), 0, s, ev_start,
+                        nt == 1 ? ev_stop : nullptr, 0, K, ld, n, Wall, done, info, status);
+  CMPC_LAUNCH_CHECK();
+  for (int k = 0; k < nt && nt > 1; ++k) {
+    const int npanel = k >= 1 ? nt - k : 0;
+    const int rows = nt - 1 - k;
+    const int tiles = npanel + rows * (rows + 1) / 2;
+    hipExtLaunchKernelGGL(chol_step_kernel, dim3(tiles), dim3(256), 0, s, (hipEvent_t) nullptr,
+                          k == nt - 1 ? ev_stop : nullptr, 0, K, ld, n, k, nt, Wall, done, info,
+                          status);
+    CMPC_LAUNCH_CHECK();
   }
   return 0;
 }
 
-// Solve L L' x = b in place, one workgroup, n <= 8192.
-__global__ __launch_bounds__(256) void potrs_kernel(const double* __restrict__ L, int n, int ld,
-                                                    double* __restrict__ b, const int* done) {
-  __shared__ double y[8192];
-  if (done != nullptr && *done) return;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int i = tid; i < n; i += 256) y[i] = b[i];
+// Inverses of the diagonal tiles of an existing factor (for a standalone solve).
+__global__ __launch_bounds__(256) void tri_inv_kernel(const double* __restrict__ L, int ld, int n,
+                                                      double* __restrict__ Wall) {
+  __shared__ Tile T, W;
+  const int r0 = 64 * blockIdx.x;
+  const int nvalid = n - r0 < 64 ? n - r0 : 64;
+  load_tile(L, ld, n, r0, r0, T);
   __syncthreads();
-  // forward: L y = b, blocks of 64 rows, left-looking
-  for (int k0 = 0; k0 < n; k0 += 64) {
-    const int nb = n - k0 < 64 ? n - k0 : 64;
-    for (int q = wave; q < nb; q += 4) {
-      const double* rp = L + (long long)(k0 + q) * ld;
-      double acc = 0.0;
-      for (int j = lane; j < k0; j += 64) acc = fma(rp[j], y[j], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) y[k0 + q] -= acc;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      double yr = lane < nb ? y[k0 + lane] : 0.0;
-      for (int j = 0; j < nb; ++j) {
-        const double ljj = L[(long long)(k0 + j) * ld + k0 + j];
-        const double yj = __shfl(yr, j, 64) / ljj;
-        if (lane == j) yr = yj;
-        else if (lane > j && lane < nb) yr = fma(-L[(long long)(k0 + lane) * ld + k0 + j], yj, yr);
-      }
-      if (lane < nb) y[k0 + lane] = yr;
-    }
-    __syncthreads();
+  for (int e = threadIdx.x; e < 4096; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    if (j > i) T[i][j] = 0.0;
+    if (i >= nvalid) T[i][j] = (i == j) ? 1.0 : 0.0;
   }
-  // backward: L' x = y, blocks from the bottom, right-looking updates of the rows above
-  const int last0 = ((n - 1) / 64) * 64;
-  for (int k0 = last0; k0 >= 0; k0 -= 64) {
-    const int nb = n - k0 < 64 ? n - k0 : 64;
-    if (wave == 0) {
-      double xr = lane < nb ? y[k0 + lane] : 0.0;
-      for (int j = nb - 1; j >= 0; --j) {
-        const double ljj = L[(long long)(k0 + j) * ld + k0 + j];
-        const double xj = __shfl(xr, j, 64) / ljj;
-        if (lane == j) xr = xj;
-        else if (lane < j) xr = fma(-L[(long long)(k0 + j) * ld + k0 + lane], xj, xr);
-      }
-      if (lane < nb) y[k0 + lane] = xr;
-    }
-    __syncthreads();
-    for (int i = tid; i < k0; i += 256) {
-      double acc = 0.0;
-      for (int j = 0; j < nb; ++j) acc = fma(L[(long long)(k0 + j) * ld + i], y[k0 + j], acc);
-      y[i] -= acc;
-    }
-    __syncthreads();
-  }
-  for (int i = tid; i < n; i += 256) b[i] = y[i];
+  __syncthreads();
+  __shared__ double rdiag[64];
+  inv64(T, W, rdiag);
+  write_w(Wall + (long long)blockIdx.x * 4096, W);
 }
 
-int launch_potrs(hipStream_t s, const double* L, int n, int ld, double* b, const int* done) {
-  if (n > 8192) {
-    set_error("potrs: n > 8192 not supported");
-    return CMPC_ERR_INVALID;
-  }
-  hipLaunchKernelGGL(potrs_kernel, dim3(1), dim3(256), 0, s, L, n, ld, b, done);
+int launch_tri_inv(hipStream_t s, const double* L, int n, int ld, double* Wall) {
+  hipLaunchKernelGGL(tri_inv_kernel, dim3(ceil_div(n, 64)), dim3(256), 0, s, L, ld, n, Wall);
   CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// Triangular solves with the factor L and the diagonal-tile inverses W_k, one launch per
+// 64-row block, many workgroups per launch.
+//   forward step k:  y_k = W_k b_k  (b_k already holds b_k - sum_{j<k} L_kj y_j), and the
+//                    workgroup for block i > k applies b_i -= L_ik y_k;
+//   backward step k: x_k = W_k' y_k  (y_k already reduced by the blocks below), and the
+//                    workgroup for block j < k applies y_j -= L_kj' x_k.
+// Every workgroup recomputes the 64-long block solution (a 64 x 64 product) itself, so the
+// launch needs no inter-workgroup synchronisation; workgroup 0 stores it.
+
+// v = M u (trans = false) or M' u (trans = true) for the 64 x 64 tile M (row-major, ld 64);
+// u, v in LDS.  4 lanes per output entry.
+__device__ inline void tile_mv64(const double* __restrict__ M, const double* u, double* v,
+                                 bool trans) {
+  const int r = threadIdx.x >> 2, p = threadIdx.x & 3;
+  double acc = 0.0;
+  if (!trans) {
+    for (int m = p; m < 64; m += 4) acc = fma(M[r * 64 + m], u[m], acc);
+  } else {
+    for (int m = p; m < 64; m += 4) acc = fma(M[m * 64 + r], u[m], acc);
+  }
+  acc += __shfl_xor(acc, 1, 64);
+  acc += __shfl_xor(acc, 2, 64);
+  if (p == 0) v[r] = acc;
+}
+
+__global__ __launch_bounds__(256) void trsv_fwd_step_kernel(const double* __restrict__ L, int ld,
+                                                           int n, const double* __restrict__ Wall,
+                                                           double* __restrict__ b,
+                                                           double* __restrict__ y, int k,
+                                                           const int* __restrict__ done) {
+  __shared__ double bk[64], yk[64];
+  if (done != nullptr && *done) return;
+  const int k0 = 64 * k, t = threadIdx.x;
+  if (t < 64) bk[t] = (k0 + t < n) ? b[k0 + t] : 0.0;
+  __syncthreads();
+  tile_mv64(Wall + (long long)k * 4096, bk, yk, false);
+  __syncthreads();
+  if (blockIdx.x == 0 && t < 64 && k0 + t < n) y[k0 + t] = yk[t];
+  const int i0 = k0 + 64 * (1 + (int)blockIdx.x);
+  if (i0 >= n) return;
+  // b_i -= L_ik y_k: 4 lanes per row of block i
+  const int r = t >> 2, p = t & 3;
+  double acc = 0.0;
+  if (i0 + r < n) {
+    const double* rp = L + (long long)(i0 + r) * ld + k0;
+    for (int m = p; m < 64; m += 4) acc = fma(rp[m], yk[m], acc);
+  }
+  acc += __shfl_xor(acc, 1, 64);
+  acc += __shfl_xor(acc, 2, 64);
+  if (p == 0 && i0 + r < n) b[i0 + r] -= acc;
+}
+
+__global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const double* __restrict__ L, int ld,
+                                                           int n, const double* __restrict__ Wall,
+                                                           double* __restrict__ y,
+                                                           double* __restrict__ x, int k,
+                                                           const int* __restrict__ done) {
+  __shared__ double ykk[64], xk[64];
+  if (done != nullptr && *done) return;
+  const int k0 = 64 * k, t = threadIdx.x;
+  if (t < 64) ykk[t] = (k0 + t < n) ? y[k0 + t] : 0.0;
+  __syncthreads();
+  tile_mv64(Wall + (long long)k * 4096, ykk, xk, true);
+  __syncthreads();
+  if (blockIdx.x == 0 && t < 64 && k0 + t < n) x[k0 + t] = xk[t];
+  const int j = blockIdx.x;
+  if (j >= k) return;
+  // y_j -= L_kj' x_k: column c of block j gets sum_r L[k0 + r][64 j + c] x_k[r]
+  const int c = t & 63, g = t >> 6;
+  double acc = 0.0;
+  for (int r = g; r < 64; r += 4)
+    if (k0 + r < n) acc = fma(L[(long long)(k0 + r) * ld + 64 * j + c], xk[r], acc);
+  __shared__ double red[4][64];
+  red[g][c] = acc;
+  __syncthreads();
+  if (g == 0) y[64 * j + c] -= (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+}
+
+// x = (L L')^-1 b.  work: n doubles of scratch (the reduced right-hand side); x may alias b
+// only if work differs from both.
+int launch_potrs(hipStream_t s, const double* L, int n, int ld, const double* Wall,
+                 const double* b, double* x, double* work, const int* done) {
+  const int nt = ceil_div(n, 64);
+  if (work != b) {
+    CMPC_HIP(hipMemcpyAsync(work, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  }
+  for (int k = 0; k < nt; ++k) {  // forward: y (into x) from work
+    hipLaunchKernelGGL(trsv_fwd_step_kernel, dim3(nt - k - 1 > 0 ? nt - k - 1 : 1), dim3(256), 0,
+                       s, L, ld, n, Wall, work, x, k, done);
+    CMPC_LAUNCH_CHECK();
+  }
+  for (int k = nt - 1; k >= 0; --k) {  // backward: x from y (x reduced in place)
+    hipLaunchKernelGGL(trsv_bwd_step_kernel, dim3(k > 0 ? k : 1), dim3(256), 0, s, L, ld, n, Wall,
+                       x, work, k, done);
+    CMPC_LAUNCH_CHECK();
+  }
+  CMPC_HIP(hipMemcpyAsync(x, work, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   return 0;
 }
 

@@ -33,13 +33,15 @@ int ipm_alloc_work(Problem& p) {
   CMPC_HIP(hipMalloc(&p.gt, sizeof(double) * 3 * n));
   p.n_prep_blocks = ceil_div((long long)mx + n, 256);
   p.n_step_blocks = p.n_prep_blocks;
-  CMPC_HIP(hipMalloc(&p.norm_part, sizeof(double) * 4 * p.n_prep_blocks));
+  CMPC_HIP(hipMalloc(&p.norm_part, sizeof(double) * 5 * p.n_prep_blocks));
   CMPC_HIP(hipMalloc(&p.alpha_part, sizeof(double) * 2 * p.n_step_blocks));
   int rc = 128;
   while ((long long)ceil_div(p.ns, rc) * p.N > 2048 && rc < 4096) rc *= 2;
   p.gt_rows = rc;
   p.gt_chunks = ceil_div(p.ns, rc) * p.N;
   CMPC_HIP(hipMalloc(&p.gt_part, sizeof(double) * 3 * n * (size_t)p.gt_chunks));
+  CMPC_HIP(hipMalloc(&p.red_part, sizeof(double) * 1024));
+  CMPC_HIP(hipMalloc(&p.Wdiag, sizeof(double) * 4096 * (size_t)ceil_div(p.n, 64)));
   CMPC_HIP(hipMalloc(&p.st, sizeof(IpmState)));
   CMPC_HIP(hipMemset(p.st, 0, sizeof(IpmState)));
   return 0;
@@ -47,85 +49,81 @@ int ipm_alloc_work(Problem& p) {
 
 // ---------------------------------------------------------------- Gamma' W  (NV vectors)
 // Partial sums of chunk (t, q): rows [q rc, (q+1) rc) of row block t, columns a < t nu.
+// Threads form TPC columns x RG row groups (TPC = 64, 128 or 256 by the row length), so
+// short rows of early blocks still keep every lane busy; row groups are summed in LDS.
 template <int NV>
 __global__ __launch_bounds__(256) void gamma_t_partial_kernel(
     const double* __restrict__ Gam, const long long* __restrict__ off,
     const double* __restrict__ W, long long wstride, double* __restrict__ part, int ns, int nu,
     int n, int rc, int cpb, const int* __restrict__ done) {
-  __shared__ double wsh[NV][512];
+  __shared__ double red[NV][256];
   if (done != nullptr && *done) return;
   const int chunk = blockIdx.x;
   const int t = chunk / cpb + 1, q = chunk - (t - 1) * cpb;
   const int len = t * nu;
   const int r0 = q * rc, r1 = min(ns, r0 + rc);
-  double acc[NV][8];
-  const int ncol_iter = (len + 255) / 256;  // <= 8 handled per pass
-  for (int cbase = 0; cbase < ncol_iter; cbase += 8) {
+  const int tpc = len <= 64 ? 64 : (len <= 128 ? 128 : 256);
+  const int rgs = 256 / tpc;
+  const int rg = threadIdx.x / tpc, cc = threadIdx.x - rg * tpc;
+  const double* __restrict__ base = Gam + off[t - 1];
+  const double* __restrict__ wb = W + (long long)(t - 1) * ns;
+  for (int cbase = 0; cbase < len; cbase += tpc) {
+    const int a = cbase + cc;
+    const bool va = a < len;
+    double acc[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+#pragma unroll 4
+    for (int r = r0 + rg; r < r1; r += rgs) {
+      const double g = va ? base[(long long)r * len + a] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[k][u] = 0.0;
-    for (int rr = r0; rr < r1; rr += 512) {
-      const int rend = min(r1, rr + 512);
-      __syncthreads();
-      for (int r = rr + threadIdx.x; r < rend; r += 256)
+      for (int k = 0; k < NV; ++k) acc[k] = fma(g, wb[k * wstride + r], acc[k]);
+    }
 #pragma unroll
-        for (int k = 0; k < NV; ++k) wsh[k][r - rr] = W[k * wstride + (long long)(t - 1) * ns + r];
-      __syncthreads();
-      for (int r = rr; r < rend; ++r) {
-        const double* row = Gam + off[t - 1] + (long long)r * len;
-        double wv[NV];
+    for (int k = 0; k < NV; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    if (rg == 0 && va) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) wv[k] = wsh[k][r - rr];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int a = (cbase + u) * 256 + threadIdx.x;
-          if (cbase + u < ncol_iter && a < len) {
-            const double g = row[a];
-#pragma unroll
-            for (int k = 0; k < NV; ++k) acc[k][u] = fma(g, wv[k], acc[k][u]);
-          }
-        }
+      for (int k = 0; k < NV; ++k) {
+        double sum = red[k][cc];
+        for (int g2 = 1; g2 < rgs; ++g2) sum += red[k][g2 * tpc + cc];
+        part[((long long)chunk * NV + k) * n + a] = sum;
       }
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int a = (cbase + u) * 256 + threadIdx.x;
-      if (cbase + u < ncol_iter && a < len)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) part[((long long)chunk * NV + k) * n + a] = acc[k][u];
-    }
+    __syncthreads();
   }
 }
 
-// out[k][a] = sum over chunks whose block covers column a (fixed order).
+// out[k][a] = sum over chunks whose block covers column a (fixed order): 16 columns x 16
+// chunk groups per workgroup.
 template <int NV>
 __global__ __launch_bounds__(256) void gamma_t_reduce_kernel(const double* __restrict__ part,
                                                              double* __restrict__ out, int n,
                                                              int nu, int cpb, int nchunks,
                                                              const int* __restrict__ done) {
-  __shared__ double sh[4][NV][64];
+  __shared__ double sh[16][NV][16];
   if (done != nullptr && *done) return;
-  const int a = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int g = threadIdx.x >> 6;
+  const int l = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int a = blockIdx.x * 16 + l;
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
   if (a < n) {
     const int tmin = a / nu + 1;  // first block with t nu > a
     const int c0 = (tmin - 1) * cpb;
-    for (int ch = c0 + g; ch < nchunks; ch += 4)
+    for (int ch = c0 + g; ch < nchunks; ch += 16)
 #pragma unroll
       for (int k = 0; k < NV; ++k) acc[k] += part[((long long)ch * NV + k) * n + a];
   }
 #pragma unroll
-  for (int k = 0; k < NV; ++k) sh[g][k][threadIdx.x & 63] = acc[k];
+  for (int k = 0; k < NV; ++k) sh[g][k][l] = acc[k];
   __syncthreads();
   if (g == 0 && a < n) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-      const int l = threadIdx.x & 63;
-      out[(long long)k * n + a] = (sh[0][k][l] + sh[1][k][l]) + (sh[2][k][l] + sh[3][k][l]);
+      double sum = 0.0;
+      for (int g2 = 0; g2 < 16; ++g2) sum += sh[g2][k][l];
+      out[(long long)k * n + a] = sum;
     }
   }
 }
@@ -137,14 +135,14 @@ int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int
                        p.Gam, p.goff, w, (long long)p.mx, p.gt_part, p.ns, p.nu, p.n, p.gt_rows,
                        cpb, done);
     CMPC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(gamma_t_reduce_kernel<3>, dim3(ceil_div(p.n, 64)), dim3(256), 0, p.stream,
+    hipLaunchKernelGGL(gamma_t_reduce_kernel<3>, dim3(ceil_div(p.n, 16)), dim3(256), 0, p.stream,
                        p.gt_part, out, p.n, p.nu, cpb, p.gt_chunks, done);
   } else {
     hipLaunchKernelGGL(gamma_t_partial_kernel<1>, dim3(p.gt_chunks), dim3(256), 0, p.stream,
                        p.Gam, p.goff, w, (long long)p.mx, p.gt_part, p.ns, p.nu, p.n, p.gt_rows,
                        cpb, done);
     CMPC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(gamma_t_reduce_kernel<1>, dim3(ceil_div(p.n, 64)), dim3(256), 0, p.stream,
+    hipLaunchKernelGGL(gamma_t_reduce_kernel<1>, dim3(ceil_div(p.n, 16)), dim3(256), 0, p.stream,
                        p.gt_part, out, p.n, p.nu, cpb, p.gt_chunks, done);
   }
   CMPC_LAUNCH_CHECK();
@@ -178,27 +176,24 @@ int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done) {
 }
 
 // ---------------------------------------------------------------- y = H x (H symmetric)
+// One wavefront per row, lanes stride the (contiguous) row.
 __global__ __launch_bounds__(256) void hv_kernel(const double* __restrict__ H,
                                                  const double* __restrict__ x,
                                                  double* __restrict__ y, int n,
                                                  const int* __restrict__ done) {
-  __shared__ double sh[4][64];
   if (done != nullptr && *done) return;
-  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int g = threadIdx.x >> 6;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= n) return;
+  const double* row = H + (long long)c * n;
   double acc = 0.0;
-  if (c < n)
-    for (int j = g; j < n; j += 4) acc = fma(H[(long long)j * n + c], x[j], acc);
-  sh[g][threadIdx.x & 63] = acc;
-  __syncthreads();
-  if (g == 0 && c < n) {
-    const int l = threadIdx.x & 63;
-    y[c] = (sh[0][l] + sh[1][l]) + (sh[2][l] + sh[3][l]);
-  }
+  for (int j = lane; j < n; j += 64) acc = fma(row[j], x[j], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) y[c] = acc;
 }
 
 static int launch_hv(Problem& p, const double* x, double* y, const int* done) {
-  hipLaunchKernelGGL(hv_kernel, dim3(ceil_div(p.n, 64)), dim3(256), 0, p.stream, p.H, x, y, p.n,
+  hipLaunchKernelGGL(hv_kernel, dim3(ceil_div(p.n, 4)), dim3(256), 0, p.stream, p.H, x, y, p.n,
                      done);
   CMPC_LAUNCH_CHECK();
   return 0;
@@ -226,14 +221,15 @@ __global__ void ipm_init_kernel(const double* __restrict__ d, double* __restrict
   if (i < n) v[i] = 0.0;
   if (i < mx) gv[i] = 0.0;
   if (i == 0) {
+    const int xf = st->x0_flag;
     st->mu = kMuInit;
     st->tau = fmax(kTauMin, 1.0 - kMuInit);
     st->alpha = st->alpha_z = 0.0;
     st->tol = tol;
     st->mu_min = tol / 10.0;
     st->iter = 0;
-    st->status = kRunning;
-    st->done = 0;
+    st->status = xf == 2 ? CMPC_ERR_NONFINITE : (xf == 1 ? CMPC_ERR_X0_BOUNDS : kRunning);
+    st->done = xf != 0;
     st->info = 0;
     st->max_iter = max_iter;
     st->switch_iter = -1;
@@ -281,7 +277,7 @@ __global__ __launch_bounds__(256) void prep_kernel(
   __shared__ double sh[4];
   if (*done) return;
   const int p = blockIdx.x * 256 + threadIdx.x;
-  double nr3 = 0.0, nlz = 0.0, szmax = 0.0, szmin = INFINITY;
+  double nr3 = 0.0, nlz = 0.0, szmax = 0.0, szmin = INFINITY, gap = 0.0;
   if (p < mx + n) {
     const PairRows pr = pair_rows(p, mx, n, gv, v);
     double sig[2] = {0.0, 0.0}, dl[2] = {0.0, 0.0}, inv[2] = {0.0, 0.0}, y3[2] = {0.0, 0.0};
@@ -303,6 +299,7 @@ __global__ __launch_bounds__(256) void prep_kernel(
         const double sz = sr * zr;
         szmax = fmax(szmax, sz);
         szmin = fmin(szmin, sz);
+        gap += sz;
       }
     }
     const double D = sig[0] + sig[1];
@@ -323,12 +320,14 @@ __global__ __launch_bounds__(256) void prep_kernel(
   nlz = block_max256(nlz, sh);
   szmax = block_max256(szmax, sh);
   szmin = block_min256(szmin, sh);
+  gap = block_sum256(gap, sh);
   if (threadIdx.x == 0) {
-    double* np = norm_part + 4LL * blockIdx.x;
+    double* np = norm_part + 5LL * blockIdx.x;
     np[0] = nr3;
     np[1] = nlz;
     np[2] = szmax;
     np[3] = szmin;
+    np[4] = gap;
   }
 }
 
@@ -347,22 +346,26 @@ int launch_prep(Problem& p) {
 __global__ __launch_bounds__(256) void mu_rhs_kernel(
     const double* __restrict__ Hv, const double* __restrict__ h, const double* __restrict__ gt,
     const double* __restrict__ wu, const double* __restrict__ norm_part, int nparts,
-    double* __restrict__ rhs, int n, IpmState* st, int fixed_mu) {
+    const double* __restrict__ v, double* __restrict__ rhs, int n, IpmState* st, int fixed_mu) {
   __shared__ double sh[4];
   if (st->done) return;
-  double nr1 = 0.0;
+  double nr1 = 0.0, f = 0.0;
   for (int c = threadIdx.x; c < n; c += 256) {
     const double r1 = Hv[c] + h[c] + (gt[c] + wu[c]);
     nr1 = fmax(nr1, fabs(r1));
+    f += v[c] * (0.5 * Hv[c] + h[c]);
   }
   nr1 = block_max256(nr1, sh);
-  double nr3 = 0.0, nlz = 0.0, szmax = 0.0, szmin = INFINITY;
+  f = block_sum256(f, sh);
+  double nr3 = 0.0, nlz = 0.0, szmax = 0.0, szmin = INFINITY, gap = 0.0;
   for (int b = threadIdx.x; b < nparts; b += 256) {
-    nr3 = fmax(nr3, norm_part[4LL * b]);
-    nlz = fmax(nlz, norm_part[4LL * b + 1]);
-    szmax = fmax(szmax, norm_part[4LL * b + 2]);
-    szmin = fmin(szmin, norm_part[4LL * b + 3]);
+    nr3 = fmax(nr3, norm_part[5LL * b]);
+    nlz = fmax(nlz, norm_part[5LL * b + 1]);
+    szmax = fmax(szmax, norm_part[5LL * b + 2]);
+    szmin = fmin(szmin, norm_part[5LL * b + 3]);
+    gap += norm_part[5LL * b + 4];
   }
+  gap = block_sum256(gap, sh);
   nr3 = block_max256(nr3, sh);
   nlz = block_max256(nlz, sh);
   szmax = block_max256(szmax, sh);
@@ -378,6 +381,8 @@ __global__ __launch_bounds__(256) void mu_rhs_kernel(
       st->szmax = szmax;
       st->szmin = szmin;
       st->err0 = e0;
+      st->obj = f + st->h0;
+      st->gap = gap;
     }
     if (e0 <= st->tol) {
       if (threadIdx.x == 0) {
@@ -414,7 +419,7 @@ int launch_mu_rhs(Problem& p) {
   if (launch_gamma_t(p, p.wx, 3, p.gt, done)) return CMPC_ERR_HIP;
   if (launch_hv(p, p.v, p.Hv, done)) return CMPC_ERR_HIP;
   hipLaunchKernelGGL(mu_rhs_kernel, dim3(1), dim3(256), 0, p.stream, p.Hv, p.h, p.gt, p.wu,
-                     p.norm_part, p.n_prep_blocks, p.rhs, p.n, p.st, 0);
+                     p.norm_part, p.n_prep_blocks, p.v, p.rhs, p.n, p.st, 0);
   CMPC_LAUNCH_CHECK();
   return 0;
 }
@@ -470,8 +475,8 @@ __global__ __launch_bounds__(256) void step_kernel(
 
 int launch_step(Problem& p) {
   const int* done = &p.st->done;
-  hipMemcpyAsync(p.pv, p.rhs, sizeof(double) * p.n, hipMemcpyDeviceToDevice, p.stream);
-  if (launch_potrs(p.stream, p.K, p.n, p.n, p.pv, done)) return CMPC_ERR_HIP;
+  if (launch_potrs(p.stream, p.K, p.n, p.n, p.Wdiag, p.rhs, p.pv, p.tmpn, done))
+    return CMPC_ERR_HIP;
   if (launch_gamma_mv(p, p.pv, p.gpv, done)) return CMPC_ERR_HIP;
   hipLaunchKernelGGL(step_kernel, dim3(p.n_step_blocks), dim3(256), 0, p.stream, p.d, p.s, p.lam,
                      p.z, p.gv, p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part, p.mx, p.n,
@@ -541,40 +546,23 @@ __global__ __launch_bounds__(256) void update_kernel(
   if (blockIdx.x == 0 && threadIdx.x == 0) st->iter += 1;
 }
 
-int launch_update(Problem& p) {
-  hipLaunchKernelGGL(update_kernel, dim3(p.n_step_blocks), dim3(256), 0, p.stream, p.d, p.s,
-                     p.lam, p.z, p.gv, p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part,
-                     p.n_step_blocks, p.mx, p.n, p.st, 1);
+// End-of-iteration flag for the host: 1 = still running, 2 = done, written with a
+// system-scope release into mapped pinned memory (the host polls it; no copy, no event).
+__global__ void publish_kernel(const IpmState* st, int* flag) {
+  const int v = st->done ? 2 : 1;
+  __hip_atomic_store(flag, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+int launch_publish(Problem& p, int slot) {
+  hipLaunchKernelGGL(publish_kernel, dim3(1), dim3(1), 0, p.stream, p.st, p.dflags + slot);
   CMPC_LAUNCH_CHECK();
   return 0;
 }
 
-// ---------------------------------------------------------------- final objective, gap
-__global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict__ Hv,
-                                                       const double* __restrict__ h,
-                                                       const double* __restrict__ v,
-                                                       const double* __restrict__ s,
-                                                       const double* __restrict__ z,
-                                                       const double* __restrict__ d, int n,
-                                                       long long m, IpmState* st,
-                                                       double* __restrict__ gap_out) {
-  __shared__ double sh[4];
-  double f = 0.0, g = 0.0;
-  for (int c = threadIdx.x; c < n; c += 256) f += v[c] * (0.5 * Hv[c] + h[c]);
-  for (long long r = threadIdx.x; r < m; r += 256)
-    if (!isinf(d[r])) g = fma(s[r], z[r], g);
-  f = block_sum256(f, sh);
-  g = block_sum256(g, sh);
-  if (threadIdx.x == 0) {
-    st->obj = f + st->h0;
-    *gap_out = g;
-  }
-}
-
-int launch_finalize(Problem& p) {
-  if (launch_hv(p, p.v, p.Hv, nullptr)) return CMPC_ERR_HIP;
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, p.stream, p.Hv, p.h, p.v, p.s, p.z,
-                     p.d, p.n, (long long)p.m, p.st, p.tmpn);
+int launch_update(Problem& p) {
+  hipLaunchKernelGGL(update_kernel, dim3(p.n_step_blocks), dim3(256), 0, p.stream, p.d, p.s,
+                     p.lam, p.z, p.gv, p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part,
+                     p.n_step_blocks, p.mx, p.n, p.st, 1);
   CMPC_LAUNCH_CHECK();
   return 0;
 }
@@ -626,10 +614,10 @@ int launch_step_given(Problem& p, const double* v, const double* s, const double
   if (launch_gamma_t(p, p.wx, 3, p.gt, done)) return CMPC_ERR_HIP;
   if (launch_hv(p, p.v, p.Hv, done)) return CMPC_ERR_HIP;
   hipLaunchKernelGGL(mu_rhs_kernel, dim3(1), dim3(256), 0, p.stream, p.Hv, p.h, p.gt, p.wu,
-                     p.norm_part, p.n_prep_blocks, p.rhs, p.n, p.st, 1);
+                     p.norm_part, p.n_prep_blocks, p.v, p.rhs, p.n, p.st, 1);
   CMPC_LAUNCH_CHECK();
   if (launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K)) return CMPC_ERR_HIP;
-  if (launch_potrf(p.stream, p.K, p.n, p.n, &p.st->done, &p.st->info, &p.st->status))
+  if (launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info, &p.st->status))
     return CMPC_ERR_HIP;
   if (launch_step(p)) return CMPC_ERR_HIP;
   hipLaunchKernelGGL(update_kernel, dim3(1), dim3(256), 0, p.stream, p.d, p.s, p.lam, p.z, p.gv,

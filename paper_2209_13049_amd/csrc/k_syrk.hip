@@ -11,8 +11,8 @@
 //    XCD and re-read from that XCD's L2 by every tile that needs it.
 //  * Each of the 4 wavefronts of a workgroup accumulates the whole 64 x 64 tile over every
 //    4th group of 4 rows with v_mfma_f64_16x16x4f64 (or the f32 variant), operands loaded
-//    straight from memory in the MFMA lane layout and scaled by D on the fly; 16 x 16
-//    blocks that are structurally zero (columns >= t nu) or above the diagonal are skipped.
+//    straight from memory in the MFMA lane layout through a register prefetch ring and
+//    scaled by D on the fly; structurally zero columns (>= t nu) load as zeros.
 //  * At the end of a tile's piece the 4 accumulators are summed in LDS and written to a
 //    partial slot; a second kernel adds the slots of each tile in a fixed order to Hbase
 //    (deterministic, no atomics).
@@ -60,10 +60,11 @@ int syrk_plan(Problem& p) {
   double total = 0.0;
   for (int t = N; t >= 1; --t)
     for (int q = 0; q < sp.ntiles; ++q) {
-      const int c = nblocks16(tiles[q].x, tiles[q].y, t * nu);
-      if (c > 0) {
-        segs.push_back({q, t, c});
-        total += (double)c * ns;
+      // a segment exists when the block reaches the tile's rows; the kernel always runs the
+      // full 4 x 4 set of 16 x 16 blocks, so every row costs the same
+      if (nblocks16(tiles[q].x, tiles[q].y, t * nu) > 0) {
+        segs.push_back({q, t, 16});
+        total += 16.0 * ns;
       }
     }
   sp.flops_structural = 0.0;
@@ -159,63 +160,57 @@ struct MfmaOps<float> {
   __device__ static inline int out_row(int lk, int v) { return 4 * lk + v; }
 };
 
-// Rows [r0, r1) of one row block against one tile: NIB active 16-column blocks of the
-// tile rows (columns >= t nu are structural zeros); off-diagonal tiles have all 4 column
-// blocks active, diagonal tiles skip the blocks above the diagonal.
-template <typename TIn, int NIB, bool DIAG>
+// Rows [r0, r1) of one row block against one tile.  Every wavefront takes every 4th group
+// of 4 rows; operands are loaded straight into the MFMA lane layout (lane l: column l%16 of
+// a 16-column block, row l/16 of the 4-row group) through a PF-deep register ring, so PF-1
+// groups of loads are in flight behind the MFMAs of the current group.  Columns >= t nu
+// (structural zeros) and rows >= r1 load as 0 without touching memory; all 16 output blocks
+// are always computed (one code path keeps the accumulators in registers at 2 waves/SIMD).
+template <typename TIn>
 __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4][4],
                                           const TIn* __restrict__ base,
                                           const double* __restrict__ Dt, int len, int a0, int b0,
                                           int r0, int r1, int wave, int li, int lk) {
   typedef MfmaOps<TIn> Ops;
-  constexpr int NJB = DIAG ? NIB : 4;
-  bool va[NIB], vb[NJB];
+  constexpr int PF = 3;
+  bool va[4], vb[4];
 #pragma unroll
-  for (int q = 0; q < NIB; ++q) va[q] = a0 + 16 * q + li < len;
-#pragma unroll
-  for (int q = 0; q < NJB; ++q) vb[q] = b0 + 16 * q + li < len;
+  for (int q = 0; q < 4; ++q) {
+    va[q] = a0 + 16 * q + li < len;
+    vb[q] = b0 + 16 * q + li < len;
+  }
   const int nsteps = (r1 - r0 + 15) >> 4;
-  TIn ca[NIB], cb[NJB], cd;
-  auto load = [&](int step, TIn* xa, TIn* xb, TIn& xd) {
+  TIn ra[PF][4], rb[PF][4], rd[PF];
+  auto load = [&](int step, TIn (&xa)[4], TIn (&xb)[4], TIn& xd) {
     const int r = r0 + 16 * step + 4 * wave + lk;
     const bool vr = r < r1;
     const TIn* row = base + (long long)(vr ? r : r0) * len;
     xd = vr ? (TIn)Dt[r] : (TIn)0;
 #pragma unroll
-    for (int q = 0; q < NIB; ++q) xa[q] = (vr && va[q]) ? row[a0 + 16 * q + li] : (TIn)0;
-    if (!DIAG) {
-#pragma unroll
-      for (int q = 0; q < NJB; ++q) xb[q] = (vr && vb[q]) ? row[b0 + 16 * q + li] : (TIn)0;
+    for (int q = 0; q < 4; ++q) {
+      xa[q] = (vr && va[q]) ? row[a0 + 16 * q + li] : (TIn)0;
+      xb[q] = (vr && vb[q]) ? row[b0 + 16 * q + li] : (TIn)0;
     }
   };
-  load(0, ca, cb, cd);
-  for (int step = 0; step < nsteps; ++step) {
-    TIn na[NIB], nb[NJB], nd = (TIn)0;
 #pragma unroll
-    for (int q = 0; q < NIB; ++q) na[q] = (TIn)0;
+  for (int u = 0; u < PF; ++u) load(u, ra[u], rb[u], rd[u]);
+  for (int step = 0; step < nsteps; step += PF) {
 #pragma unroll
-    for (int q = 0; q < NJB; ++q) nb[q] = (TIn)0;
-    if (step + 1 < nsteps) load(step + 1, na, nb, nd);
-    TIn sa[NIB];
+    for (int u = 0; u < PF; ++u) {
+      TIn sa[4];
 #pragma unroll
-    for (int q = 0; q < NIB; ++q) sa[q] = ca[q] * cd;
+      for (int q = 0; q < 4; ++q) sa[q] = ra[u][q] * rd[u];
 #pragma unroll
-    for (int ib = 0; ib < NIB; ++ib)
+      for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
-      for (int jb = 0; jb < (DIAG ? ib + 1 : NJB); ++jb)
-        acc[ib][jb] = Ops::mma(sa[ib], DIAG ? ca[jb] : cb[jb], acc[ib][jb]);
-#pragma unroll
-    for (int q = 0; q < NIB; ++q) ca[q] = na[q];
-    if (!DIAG) {
-#pragma unroll
-      for (int q = 0; q < NJB; ++q) cb[q] = nb[q];
+        for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = Ops::mma(sa[ib], rb[u][jb], acc[ib][jb]);
+      load(step + u + PF, ra[u], rb[u], rd[u]);
     }
-    cd = nd;
   }
 }
 
 template <typename TIn>
-__global__ __launch_bounds__(256, 1) void syrk_streamk_kernel(
+__global__ __launch_bounds__(256, 2) void syrk_streamk_kernel(
     const TIn* __restrict__ Gam, const long long* __restrict__ off, const double* __restrict__ D,
     const SyrkJob* __restrict__ jobs, const int* __restrict__ wg_begin,
     const int2* __restrict__ tiles, double* __restrict__ partials, int ns, int nu, int nwg,
@@ -242,18 +237,7 @@ __global__ __launch_bounds__(256, 1) void syrk_streamk_kernel(
     const int len = job.t * nu;
     const TIn* __restrict__ base = Gam + off[job.t - 1];
     const double* __restrict__ Dt = D + (long long)(job.t - 1) * ns;
-    const int nib = min(4, (len - a0 + 15) >> 4);
-    const int key = (tl.x == tl.y ? 4 : 0) + nib - 1;
-    switch (key) {
-      case 0: syrk_rows<TIn, 1, false>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
-      case 1: syrk_rows<TIn, 2, false>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
-      case 2: syrk_rows<TIn, 3, false>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
-      case 3: syrk_rows<TIn, 4, false>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
-      case 4: syrk_rows<TIn, 1, true>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
-      case 5: syrk_rows<TIn, 2, true>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
-      case 6: syrk_rows<TIn, 3, true>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
-      default: syrk_rows<TIn, 4, true>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk); break;
-    }
+    syrk_rows<TIn>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
     if (job.slot >= 0) {
       __syncthreads();
       for (int w = 0; w < 4; ++w) {
@@ -282,27 +266,27 @@ __global__ __launch_bounds__(256, 1) void syrk_streamk_kernel(
 }
 
 // K(lower) = Hb(lower) + sum of the tile's partial slots (fixed order) + diag(Ddiag).
+// 16 workgroups per tile, one element per thread.
 __global__ __launch_bounds__(256) void syrk_finish_kernel(
     const double* __restrict__ partials, const int* __restrict__ slot_begin,
     const int* __restrict__ slots, const int2* __restrict__ tiles, const double* __restrict__ Hb,
     const double* __restrict__ Ddiag, double* __restrict__ K, int n, const int* __restrict__ done) {
   if (done != nullptr && *done) return;
-  const int2 tl = tiles[blockIdx.x];
-  const int a0 = tl.x * 64, b0 = tl.y * 64;
-  const int q0 = slot_begin[blockIdx.x], q1 = slot_begin[blockIdx.x + 1];
-  for (int e = threadIdx.x; e < 4096; e += 256) {
-    const int gi = a0 + (e >> 6), gj = b0 + (e & 63);
-    if (gi >= n || gj > gi) continue;
-    double sum = 0.0;
-    for (int q = q0; q < q1; ++q) sum += partials[(long long)slots[q] * 4096 + e];
-    double val = Hb[(long long)gi * n + gj] + sum;
-    if (gi == gj && Ddiag != nullptr) val += Ddiag[gi];
-    K[(long long)gi * n + gj] = val;
-  }
+  const int tile = blockIdx.x >> 4;
+  const int e = ((blockIdx.x & 15) << 8) + threadIdx.x;
+  const int2 tl = tiles[tile];
+  const int gi = tl.x * 64 + (e >> 6), gj = tl.y * 64 + (e & 63);
+  if (gi >= n || gj > gi) return;
+  const int q0 = slot_begin[tile], q1 = slot_begin[tile + 1];
+  double sum = 0.0;
+  for (int q = q0; q < q1; ++q) sum += partials[(long long)slots[q] * 4096 + e];
+  double val = Hb[(long long)gi * n + gj] + sum;
+  if (gi == gj && Ddiag != nullptr) val += Ddiag[gi];
+  K[(long long)gi * n + gj] = val;
 }
 
 int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hbase,
-                const double* Ddiag, double* K) {
+                const double* Ddiag, double* K, hipEvent_t ev_start, hipEvent_t ev_stop) {
   SyrkPlan& sp = p.syrk;
   const int* done = p.st ? &p.st->done : nullptr;
   if (precision == CMPC_FP32_SYRK) {
@@ -310,16 +294,18 @@ int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hba
       set_error("FP32 copy of Gamma not allocated");
       return CMPC_ERR_INVALID;
     }
-    hipLaunchKernelGGL(syrk_streamk_kernel<float>, dim3(sp.nwg), dim3(256), 0, p.stream, p.Gam32,
-                       p.goff, Drow, sp.jobs, sp.wg_begin, sp.tiles, sp.partials, p.ns, p.nu,
-                       sp.nwg, done);
+    hipExtLaunchKernelGGL(syrk_streamk_kernel<float>, dim3(sp.nwg), dim3(256), 0, p.stream,
+                          ev_start, ev_stop, 0, (const float*)p.Gam32, (const long long*)p.goff,
+                          Drow, (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
+                          (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done);
   } else {
-    hipLaunchKernelGGL(syrk_streamk_kernel<double>, dim3(sp.nwg), dim3(256), 0, p.stream, p.Gam,
-                       p.goff, Drow, sp.jobs, sp.wg_begin, sp.tiles, sp.partials, p.ns, p.nu,
-                       sp.nwg, done);
+    hipExtLaunchKernelGGL(syrk_streamk_kernel<double>, dim3(sp.nwg), dim3(256), 0, p.stream,
+                          ev_start, ev_stop, 0, (const double*)p.Gam, (const long long*)p.goff,
+                          Drow, (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
+                          (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done);
   }
   CMPC_LAUNCH_CHECK();
-  hipLaunchKernelGGL(syrk_finish_kernel, dim3(sp.ntiles), dim3(256), 0, p.stream, sp.partials,
+  hipLaunchKernelGGL(syrk_finish_kernel, dim3(sp.ntiles * 16), dim3(256), 0, p.stream, sp.partials,
                      sp.slot_begin, sp.slots, sp.tiles, Hbase, Ddiag, K, p.n, done);
   CMPC_LAUNCH_CHECK();
   return 0;

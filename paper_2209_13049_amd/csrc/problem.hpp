@@ -12,7 +12,7 @@ namespace cmpc {
 struct IpmState {
   double mu, tau, alpha, alpha_z;
   double nr1, nr3, nlz, szmax, szmin, err0;  // norms at the top of the current iteration
-  double tol, mu_min, h0, obj;
+  double tol, mu_min, h0, obj, gap;
   int iter;      // steps taken
   int status;    // CMPC_* outcome once done
   int done;      // nonzero: every later kernel of the solve returns at entry
@@ -22,7 +22,7 @@ struct IpmState {
   int switch_iter;
   int refine_steps;
   int nonc;      // mixed modes: refinement failures so far
-  int pad_;
+  int x0_flag;   // device x0 check: 1 = outside the bounds, 2 = not finite
 };
 
 constexpr int kRunning = 100;
@@ -60,7 +60,11 @@ struct Problem {
   float* Gam32 = nullptr;        // FP32 copy (mixed modes)
   unsigned short* Gam16 = nullptr;  // BF16 copy (mixed modes)
   double *H = nullptr;           // n x n, full symmetric
+  double *Wdiag = nullptr;       // inverses of the diagonal 64 x 64 factor tiles
   double *K = nullptr;           // n x n workspace (lower triangle = condensed matrix / factor)
+  int *a_rowptr = nullptr, *a_col = nullptr;  // CSR copy of A when it is sparse
+  double* a_val = nullptr;
+  double *red_part = nullptr;    // 1024 partial sums
   double *x0 = nullptr, *c = nullptr, *qc = nullptr, *h = nullptr, *d = nullptr;
   bool have_x0 = false;
   // iterate
@@ -74,6 +78,10 @@ struct Problem {
   IpmState* st = nullptr;
   SyrkPlan syrk;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> prof_ev;  // per iteration: SYRK begin/end, Cholesky begin/end
+  int* hflags = nullptr;            // mapped pinned ring: 0 pending, 1 running, 2 done
+  int* dflags = nullptr;            // device alias of hflags
+  std::vector<double> xl_host, xu_host;
 };
 
 // ---- setup kernels (k_build.hip) ----
@@ -85,6 +93,8 @@ int launch_gemv(hipStream_t s, const double* A, const double* x, double* y, int 
 int launch_block_diag_weight(Problem& p, const double* in, double* out);
 int launch_make_d(Problem& p);
 int launch_h0(Problem& p);
+int launch_free_response(Problem& p);
+int launch_check_x0(Problem& p);
 int launch_rbar(Problem& p, double* Hb);
 int launch_mirror_lower(hipStream_t s, double* H, int n);
 int launch_dense_gamma(Problem& p, double* dense);
@@ -93,12 +103,20 @@ int launch_dense_gamma(Problem& p, double* dense);
 int syrk_plan(Problem& p);
 void syrk_free(SyrkPlan& sp);
 // K(lower) = Hbase(lower) + Gamma' diag(Drow) Gamma + diag(Ddiag)   (Ddiag may be NULL)
+// ev_start / ev_stop (optional): timing events attached to the stream-K kernel's dispatch
 int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hbase,
-                const double* Ddiag, double* K);
+                const double* Ddiag, double* K, hipEvent_t ev_start = nullptr,
+                hipEvent_t ev_stop = nullptr);
 
 // ---- Cholesky (k_chol.hip) ----
-int launch_potrf(hipStream_t s, double* K, int n, int ld, int* done, int* info, int* status);
-int launch_potrs(hipStream_t s, const double* L, int n, int ld, double* b, const int* done);
+// Wall: ceil(n/64) x 64 x 64 doubles receiving the inverses of the diagonal factor tiles
+// ev_start / ev_stop (optional): timing events attached to the first and last dispatch
+int launch_potrf(hipStream_t s, double* K, int n, int ld, double* Wall, int* done, int* info,
+                 int* status, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// x = (L L')^-1 b with n doubles of scratch `work` (distinct from b and x); x may alias b
+int launch_potrs(hipStream_t s, const double* L, int n, int ld, const double* Wall,
+                 const double* b, double* x, double* work, const int* done);
+int launch_tri_inv(hipStream_t s, const double* L, int n, int ld, double* Wall);
 
 // ---- IPM vector kernels (k_ipm.hip) ----
 int ipm_alloc_work(Problem& p);
@@ -109,7 +127,7 @@ int launch_prep(Problem& p);
 int launch_mu_rhs(Problem& p);
 int launch_step(Problem& p);
 int launch_update(Problem& p);
-int launch_finalize(Problem& p);
+int launch_publish(Problem& p, int slot);
 int launch_sigma_fold(Problem& p, const double* sigma);
 int launch_step_given(Problem& p, const double* v, const double* s, const double* lam,
                       const double* z, double mu, double tau);

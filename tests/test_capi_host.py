@@ -46,6 +46,7 @@ def test_library_loads_and_binds(built):
     # pure host functions can be called without a GPU
     o = condmpc.default_options()
     assert o.tol == 1e-8 and o.max_iter == 200 and o.precision == condmpc.FP64
+    assert o.check_every == 2 and o.profile == 0
     assert condmpc.status_str(condmpc.ERR_CHOLESKY) == "Cholesky breakdown"
     assert condmpc.status_str(condmpc.OK) == "converged"
 
@@ -68,6 +69,7 @@ def test_struct_layouts_match_header():
     assert fields("cmpc_lq_desc") == [f for f, _ in condmpc.LQDesc._fields_]
     assert fields("cmpc_options") == [f for f, _ in condmpc.Options._fields_]
     assert fields("cmpc_result") == [f for f, _ in condmpc.Result._fields_]
+    assert fields("cmpc_info") == [f for f, _ in condmpc.Info._fields_]
 
 
 def test_null_arguments_are_rejected_without_gpu(built):

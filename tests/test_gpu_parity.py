@@ -100,7 +100,7 @@ def test_condensed_matrix(problems, name, scale):
     assert rel_err(Kg[lo], K_ref[lo]) <= 1e-12
 
 
-@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 130, 257, 500])
+@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 127, 128, 129, 130, 257, 500])
 def test_cholesky_and_solve(lib, n):
     rng = np.random.default_rng(n)
     M = rng.normal(size=(n, n))
@@ -226,3 +226,34 @@ def test_iteration_limit(problems):
     ref = oracle.solve(p, red=red, max_iter=2)
     assert ref.status == oracle.STATUS_MAX_ITER
     assert abs(res["obj"] - ref.obj) <= 1e-9 * max(1.0, abs(ref.obj))
+
+
+def test_device_x0_checked_on_device(problems):
+    """A device-resident x0 is validated on the GPU; the next solve reports the error."""
+    p, gp, red = problems["small"]
+    bad = p.x0.copy()
+    bad[7] = 0.75
+    gp.set_x0(gpu(bad))
+    with pytest.raises(condmpc.CmpcError) as e:
+        gp.solve()
+    assert e.value.code == condmpc.ERR_X0_BOUNDS
+    bad[7] = np.inf
+    gp.set_x0(gpu(bad))
+    with pytest.raises(condmpc.CmpcError) as e:
+        gp.solve()
+    assert e.value.code == condmpc.ERR_NONFINITE
+    gp.set_x0(gpu(p.x0))
+    res = gp.solve()
+    ref = oracle.solve(p, red=red)
+    assert res["status"] == 0 and res["iters"] == ref.iters
+
+
+@pytest.mark.parametrize("n", [1000, 1111])
+def test_cholesky_large(lib, n):
+    rng = np.random.default_rng(n)
+    M = rng.normal(size=(n, n)) / np.sqrt(n)
+    A = M @ M.T + np.diag(rng.uniform(0.5, 2.0, n))
+    Kt = gpu(np.tril(A))
+    condmpc.potrf(Kt)
+    L = np.tril(Kt.cpu().numpy())
+    assert rel_err(L, np.linalg.cholesky(A)) <= 1e-11
