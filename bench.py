@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-solves", type=int, default=1)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the timed run at the other precision")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "
@@ -100,42 +102,54 @@ def main():
     total = args.warmup + args.steps
     x0s = [torch.from_numpy(W.heat1d_config("1d", instance=k).x0).to("cuda:0")
            for k in range(total)]
-    opts = condmpc.default_options(precision=PRECISIONS[args.precision], profile=1)
-    res = condmpc.Result()
 
-    def step(k):
-        prob.set_x0(x0s[k])
-        rc = prob.solve_raw(opts, res)
-        if rc != condmpc.OK:
-            raise RuntimeError(f"solve {k} returned {rc}: {condmpc.load().cmpc_last_error()}")
-        return res.iters, res.ms_syrk, res.ms_form, res.ms_potrf
+    def run(precision):
+        """Warm up, then time `steps` solves (each: set x0, solve) at one precision."""
+        opts = condmpc.default_options(precision=PRECISIONS[precision], profile=1)
+        res = condmpc.Result()
+        objs = []
 
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = syrk_ms = form_ms = potrf_ms = 0.0
-    for k in range(args.warmup, total):
-        it, a, b, c = step(k)
-        iters += it
-        syrk_ms += a
-        form_ms += b
-        potrf_ms += c
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+        def step(k):
+            prob.set_x0(x0s[k])
+            rc = prob.solve_raw(opts, res)
+            if rc != condmpc.OK:
+                raise RuntimeError(f"solve {k} returned {rc}: {condmpc.load().cmpc_last_error()}")
+            return res.iters, res.ms_syrk, res.ms_form, res.ms_potrf, res.obj
 
-    solves_per_s = args.steps / elapsed
-    syrk_avg_s = syrk_ms / 1e3 / max(1, iters)
-    achieved = info["syrk_flops"] / syrk_avg_s / 1e12
+        for k in range(args.warmup):
+            step(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        acc = np.zeros(4)
+        for k in range(args.warmup, total):
+            it, a, b, c, f = step(k)
+            acc += (it, a, b, c)
+            objs.append(f)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        iters = max(1.0, acc[0])
+        syrk_avg_s = acc[1] / 1e3 / iters
+        achieved = info["syrk_flops"] / syrk_avg_s / 1e12
+        return {"solves_per_s": args.steps / elapsed, "ms_per_step": elapsed * 1e3 / args.steps,
+                "iters_per_solve": acc[0] / args.steps, "ms_per_iter": elapsed * 1e3 / iters,
+                "ms_per_iter_syrk_potrf": (acc[2] + acc[3]) / iters,
+                "ms_per_iter_syrk_kernel": acc[1] / iters, "ms_per_iter_potrf": acc[3] / iters,
+                "syrk_achieved_tflops": achieved, "syrk_avg_launch_us": syrk_avg_s * 1e6,
+                "objs": objs}
+
+    main_run = run(args.precision)
+    other = "fp32" if args.precision == "fp64" else "fp64"
+    other_run = run(other) if not args.no_compare else None
     peak = PEAK[args.precision]
+    achieved = main_run["syrk_achieved_tflops"]
     out = {
         "metric": METRIC,
-        "value": solves_per_s,
+        "value": main_run["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -145,19 +159,33 @@ def main():
                    "ns": cfg["ns"], "nu": cfg["nu"], "N": cfg["N"], "n": info["n"],
                    "state_rows": info["mx"], "tol": 1e-8, "precision": args.precision,
                    "x0": "U(-0.4, 0.4) per state, seed [1, step]"},
-        "iters_per_solve": iters / args.steps,
-        "ms_per_iter": elapsed * 1e3 / max(1, iters),
-        "ms_per_iter_syrk_potrf": (form_ms + potrf_ms) / max(1, iters),
-        "ms_per_iter_syrk_kernel": syrk_ms / max(1, iters),
-        "ms_per_iter_potrf": potrf_ms / max(1, iters),
+        "iters_per_solve": main_run["iters_per_solve"],
+        "ms_per_iter": main_run["ms_per_iter"],
+        "ms_per_iter_syrk_potrf": main_run["ms_per_iter_syrk_potrf"],
+        "ms_per_iter_syrk_kernel": main_run["ms_per_iter_syrk_kernel"],
+        "ms_per_iter_potrf": main_run["ms_per_iter_potrf"],
         "roofline": {"bound": "mfma", "kernel": "syrk_streamk_kernel<double>" if
                      args.precision == "fp64" else "syrk_streamk_kernel<float>",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic() if
                      args.precision == "fp64" else None,
                      "flops_per_launch": info["syrk_flops"],
-                     "avg_launch_us": syrk_avg_s * 1e6},
+                     "avg_launch_us": main_run["syrk_avg_launch_us"]},
     }
+    if other_run is not None:
+        rel = [abs(a - b) / max(1.0, abs(b)) for a, b in zip(other_run["objs"], main_run["objs"])]
+        out["compare"] = {
+            "precision": other,
+            "solves_per_s": other_run["solves_per_s"],
+            "speedup_vs_" + args.precision: other_run["solves_per_s"] / main_run["solves_per_s"],
+            "iters_per_solve": other_run["iters_per_solve"],
+            "ms_per_iter": other_run["ms_per_iter"],
+            "ms_per_iter_syrk_potrf": other_run["ms_per_iter_syrk_potrf"],
+            "syrk_kernel_us": other_run["syrk_avg_launch_us"],
+            "syrk_achieved_tflops_structural": other_run["syrk_achieved_tflops"],
+            "syrk_peak_tflops": PEAK[other],
+            "max_obj_rel_diff": max(rel) if rel else None,
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(base, args.cpu_solves)
     prob.close()

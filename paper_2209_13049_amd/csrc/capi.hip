@@ -28,7 +28,7 @@ static void free_problem(Problem* p) {
                      &p->lam, &p->z,  &p->gv,   &p->pv,    &p->ps,   &p->plam, &p->pz,
                      &p->gpv, &p->rhs, &p->Dx,  &p->Du,    &p->wx,   &p->wu,   &p->gt,
                      &p->Hv, &p->tmpn, &p->tmpn2, &p->tmpmx, &p->norm_part, &p->alpha_part,
-                     &p->gt_part, &p->Wdiag};
+                     &p->gt_part, &p->Wdiag, &p->ref_res, &p->ref_dlt, &p->ref_gt};
   for (double** b : bufs) {
     if (*b) hipFree(*b);
     *b = nullptr;
@@ -322,6 +322,8 @@ static int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
   }
   const int check = std::max(1, o.check_every);
   const bool prof = o.profile != 0;
+  const int mixed = o.precision == CMPC_FP32_SYRK ? 1 : 0;
+  if (mixed && launch_convert_gamma(p, CMPC_FP32_SYRK)) return CMPC_ERR_HIP;
   if (prof) {
     const size_t need = 4 * (size_t)(o.max_iter + 1);
     while (p.prof_ev.size() < need) {
@@ -367,21 +369,14 @@ static int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
     }
     const int slot = it % R;
     hf[slot] = 0;
-    if (prof) {
-      rc = launch_prep(p);
-      if (!rc) rc = launch_mu_rhs(p);
-      if (!rc) rc = launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K, p.prof_ev[4 * it],
-                                p.prof_ev[4 * it + 1]);
-      if (!rc) rc = launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info,
-                                 &p.st->status, p.prof_ev[4 * it + 2], p.prof_ev[4 * it + 3]);
-    } else {
-      rc = launch_prep(p);
-      if (!rc) rc = launch_mu_rhs(p);
-      if (!rc) rc = launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K);
-      if (!rc) rc = launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info,
-                                 &p.st->status);
-    }
-    if (!rc) rc = launch_step(p);
+    hipEvent_t e0 = prof ? p.prof_ev[4 * it] : nullptr, e1 = prof ? p.prof_ev[4 * it + 1] : nullptr;
+    hipEvent_t e2 = prof ? p.prof_ev[4 * it + 2] : nullptr, e3 = prof ? p.prof_ev[4 * it + 3] : nullptr;
+    rc = launch_prep(p);
+    if (!rc) rc = launch_mu_rhs(p);
+    if (!rc) rc = launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K, e0, e1, mixed);
+    if (!rc) rc = launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info,
+                               &p.st->status, e2, e3, mixed ? &p.st->use_low : nullptr);
+    if (!rc) rc = launch_step(p, mixed ? o.max_refine : 0);
     if (!rc) rc = launch_update(p);
     if (!rc) rc = launch_publish(p, slot);
   }
@@ -515,8 +510,12 @@ int cmpc_solve(cmpc_problem* h, const cmpc_options* opts, cmpc_result* res) {
   cmpc_options o;
   cmpc_default_options(&o);
   if (opts) o = *opts;
-  if (o.precision != CMPC_FP64) {
-    set_error("mixed-precision modes are not available in this build");
+  if (o.precision != CMPC_FP64 && o.precision != CMPC_FP32_SYRK) {
+    set_error("unsupported precision mode");
+    return CMPC_ERR_INVALID;
+  }
+  if (o.max_refine < 0 || o.max_refine > 20) {
+    set_error("max_refine must lie in [0, 20]");
     return CMPC_ERR_INVALID;
   }
   return solve(*h->p, o, res);

@@ -256,9 +256,22 @@ __device__ inline void load_w(const double* __restrict__ Wk, Tile& W) {
   for (int e = threadIdx.x; e < 4096; e += 256) W[e >> 6][e & 63] = Wk[e];
 }
 
+// Pivot failure: a low-precision K (mixed modes) is retried in FP64 (done = 2 skips the
+// rest of the iteration); otherwise the breakdown is reported.
+__device__ inline void chol_fail(int col, int* done, int* info, int* status, int* lowflag) {
+  if (lowflag != nullptr && *lowflag) {
+    *lowflag = 0;
+    *done = 2;
+    return;
+  }
+  *info = col;
+  *status = CMPC_ERR_CHOLESKY;
+  *done = 1;
+}
+
 __global__ __launch_bounds__(256) void chol_first_kernel(double* __restrict__ K, int ld, int n,
                                                          double* __restrict__ Wall, int* done,
-                                                         int* info, int* status) {
+                                                         int* info, int* status, int* lowflag) {
   __shared__ Tile T, W;
   __shared__ double colb[128], piv[64];
   __shared__ int bad;
@@ -267,11 +280,7 @@ __global__ __launch_bounds__(256) void chol_first_kernel(double* __restrict__ K,
   __syncthreads();
   const int nvalid = n < 64 ? n : 64;
   if (!chol_inv64(T, W, colb, piv, nvalid, &bad)) {
-    if (threadIdx.x == 0) {
-      *info = bad + 1;
-      *status = CMPC_ERR_CHOLESKY;
-      *done = 1;
-    }
+    if (threadIdx.x == 0) chol_fail(bad + 1, done, info, status, lowflag);
     return;
   }
   write_tile_lower(K, ld, n, 0, 0, T, true);
@@ -283,7 +292,8 @@ __global__ __launch_bounds__(256) void chol_first_kernel(double* __restrict__ K,
 // trailing update with block column k, and the factorisation of the next pivot tile.
 __global__ __launch_bounds__(256) void chol_step_kernel(double* __restrict__ K, int ld, int n,
                                                         int k, int nt, double* __restrict__ Wall,
-                                                        int* done, int* info, int* status) {
+                                                        int* done, int* info, int* status,
+                                                        int* lowflag) {
   __shared__ Tile Wt, Xi, Xj;
   __shared__ double colb[128], piv[64];
   __shared__ int bad;
@@ -354,11 +364,7 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double* __restrict__ K, 
   __syncthreads();
   const int nvalid = n - r0 < 64 ? n - r0 : 64;
   if (!chol_inv64(Xj, Xi, colb, piv, nvalid, &bad)) {
-    if (threadIdx.x == 0) {
-      *info = r0 + bad + 1;
-      *status = CMPC_ERR_CHOLESKY;
-      *done = 1;
-    }
+    if (threadIdx.x == 0) chol_fail(r0 + bad + 1, done, info, status, lowflag);
     return;
   }
   write_tile_lower(K, ld, n, r0, c0, Xj, true);
@@ -366,10 +372,11 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double* __restrict__ K, 
 }
 
 int launch_potrf(hipStream_t s, double* K, int n, int ld, double* Wall, int* done, int* info,
-                 int* status, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                 int* status, hipEvent_t ev_start, hipEvent_t ev_stop, int* lowflag) {
   const int nt = ceil_div(n, 64);
   hipExtLaunchKernelGGL(chol_first_kernel, dim3(1), dim3(256), 0, s, ev_start,
-                        nt == 1 ? ev_stop : nullptr, 0, K, ld, n, Wall, done, info, status);
+                        nt == 1 ? ev_stop : nullptr, 0, K, ld, n, Wall, done, info, status,
+                        lowflag);
   CMPC_LAUNCH_CHECK();
   for (int k = 0; k < nt && nt > 1; ++k) {
     const int npanel = k >= 1 ? nt - k : 0;
@@ -377,7 +384,7 @@ int launch_potrf(hipStream_t s, double* K, int n, int ld, double* Wall, int* don
     const int tiles = npanel + rows * (rows + 1) / 2;
     hipExtLaunchKernelGGL(chol_step_kernel, dim3(tiles), dim3(256), 0, s, (hipEvent_t) nullptr,
                           k == nt - 1 ? ev_stop : nullptr, 0, K, ld, n, k, nt, Wall, done, info,
-                          status);
+                          status, lowflag);
     CMPC_LAUNCH_CHECK();
   }
   return 0;

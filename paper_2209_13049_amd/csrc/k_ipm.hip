@@ -23,6 +23,8 @@ int ipm_alloc_work(Problem& p) {
   double** vecs_n[] = {&p.v, &p.pv, &p.rhs, &p.Du, &p.Hv, &p.h, &p.tmpn};
   for (double** q : vecs_n) CMPC_HIP(hipMalloc(q, sizeof(double) * n));
   CMPC_HIP(hipMalloc(&p.tmpn2, sizeof(double) * nmax));
+  double** vecs_r[] = {&p.ref_res, &p.ref_dlt, &p.ref_gt};
+  for (double** q : vecs_r) CMPC_HIP(hipMalloc(q, sizeof(double) * n));
   double** vecs_m[] = {&p.s, &p.lam, &p.z, &p.ps, &p.plam, &p.pz, &p.d};
   for (double** q : vecs_m) CMPC_HIP(hipMalloc(q, sizeof(double) * m));
   double** vecs_mx[] = {&p.gv, &p.gpv, &p.c, &p.qc, &p.Dx, &p.tmpmx};
@@ -203,7 +205,8 @@ static int launch_hv(Problem& p, const double* x, double* y, const int* done) {
 __global__ void ipm_init_kernel(const double* __restrict__ d, double* __restrict__ s,
                                 double* __restrict__ lam, double* __restrict__ z,
                                 double* __restrict__ v, double* __restrict__ gv, int m, int n,
-                                int mx, IpmState* st, double tol, int max_iter) {
+                                int mx, IpmState* st, double tol, int max_iter, int low,
+                                double mu_switch) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
     const double di = d[i];
@@ -235,13 +238,20 @@ __global__ void ipm_init_kernel(const double* __restrict__ d, double* __restrict
     st->switch_iter = -1;
     st->refine_steps = 0;
     st->nonc = 0;
+    st->use_low = low;
+    st->mixed = low;
+    st->mu_switch = mu_switch;
+    st->ref_skip = 1;
+    st->res_prev = INFINITY;
   }
 }
 
 int launch_ipm_init(Problem& p, const cmpc_options& o) {
   const long long len = p.m;
+  const int low = o.precision != CMPC_FP64 ? 1 : 0;
   hipLaunchKernelGGL(ipm_init_kernel, dim3(ceil_div(len, 256)), dim3(256), 0, p.stream, p.d, p.s,
-                     p.lam, p.z, p.v, p.gv, p.m, p.n, p.mx, p.st, o.tol, o.max_iter);
+                     p.lam, p.z, p.v, p.gv, p.m, p.n, p.mx, p.st, o.tol, o.max_iter, low,
+                     o.mu_switch);
   CMPC_LAUNCH_CHECK();
   return 0;
 }
@@ -411,6 +421,10 @@ __global__ __launch_bounds__(256) void mu_rhs_kernel(
   if (threadIdx.x == 0 && !fixed_mu) {
     st->mu = mu;
     st->tau = fmax(kTauMin, 1.0 - mu);
+    if (st->use_low && mu < st->mu_switch) st->use_low = 0;  // late iterations: FP64 SYRK
+    if (st->mixed && !st->use_low && st->switch_iter < 0) st->switch_iter = st->iter;
+    st->ref_skip = st->use_low ? 0 : 1;
+    st->res_prev = INFINITY;
   }
 }
 
@@ -473,10 +487,12 @@ __global__ __launch_bounds__(256) void step_kernel(
   }
 }
 
-int launch_step(Problem& p) {
+int launch_step(Problem& p, int refine) {
   const int* done = &p.st->done;
   if (launch_potrs(p.stream, p.K, p.n, p.n, p.Wdiag, p.rhs, p.pv, p.tmpn, done))
     return CMPC_ERR_HIP;
+  for (int r = 0; r < refine; ++r)
+    if (launch_refine_step(p)) return CMPC_ERR_HIP;
   if (launch_gamma_mv(p, p.pv, p.gpv, done)) return CMPC_ERR_HIP;
   hipLaunchKernelGGL(step_kernel, dim3(p.n_step_blocks), dim3(256), 0, p.stream, p.d, p.s, p.lam,
                      p.z, p.gv, p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part, p.mx, p.n,
@@ -548,8 +564,10 @@ __global__ __launch_bounds__(256) void update_kernel(
 
 // End-of-iteration flag for the host: 1 = still running, 2 = done, written with a
 // system-scope release into mapped pinned memory (the host polls it; no copy, no event).
-__global__ void publish_kernel(const IpmState* st, int* flag) {
-  const int v = st->done ? 2 : 1;
+__global__ void publish_kernel(IpmState* st, int* flag) {
+  const int d = st->done;
+  if (d == 2) st->done = 0;  // the iteration was skipped for a retry in FP64
+  const int v = d == 1 ? 2 : 1;
   __hip_atomic_store(flag, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -590,6 +608,74 @@ int launch_sigma_fold(Problem& p, const double* sigma) {
   return 0;
 }
 
+// ---------------------------------------------------------------- iterative refinement
+// Mixed modes: p_v solved with the factor of the low-precision K is corrected against the
+// exact FP64 operator  K p = H p + Gamma'(D_x o Gamma p) + D_u o p:
+//   res = rhs - K p;  stop when |res| <= 1e-12 |rhs|;  else p += (L L')^-1 res.
+// A step that does not shrink |res| by 10x counts as not contracting; after two the SYRK
+// switches to FP64 from the next iteration on.  Every kernel is gated by st->ref_skip.
+__global__ void scale_by_kernel(double* __restrict__ x, const double* __restrict__ w, int len,
+                                const int* __restrict__ skip) {
+  if (*skip) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) x[i] *= w[i];
+}
+
+__global__ void axpy_gated_kernel(double* __restrict__ y, const double* __restrict__ x, int len,
+                                  const int* __restrict__ skip) {
+  if (*skip) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) y[i] += x[i];
+}
+
+__global__ __launch_bounds__(256) void refine_check_kernel(
+    const double* __restrict__ rhs, const double* __restrict__ Hp, const double* __restrict__ gtp,
+    const double* __restrict__ Du, const double* __restrict__ p, double* __restrict__ res, int n,
+    IpmState* st) {
+  __shared__ double sh[4];
+  if (st->ref_skip || st->done) return;
+  double nr = 0.0, nb = 0.0;
+  for (int c = threadIdx.x; c < n; c += 256) {
+    const double r = rhs[c] - (Hp[c] + gtp[c] + Du[c] * p[c]);
+    res[c] = r;
+    nr = fmax(nr, fabs(r));
+    nb = fmax(nb, fabs(rhs[c]));
+  }
+  nr = block_max256(nr, sh);
+  nb = block_max256(nb, sh);
+  if (threadIdx.x == 0) {
+    if (nr <= 1e-12 * nb) {
+      st->ref_skip = 1;
+    } else {
+      if (nr > 0.1 * st->res_prev) {
+        st->nonc += 1;
+        if (st->nonc >= 2) st->use_low = 0;
+      }
+      st->res_prev = nr;
+      st->refine_steps += 1;
+    }
+  }
+}
+
+int launch_refine_step(Problem& p) {
+  const int* skip = &p.st->ref_skip;
+  if (launch_gamma_mv(p, p.pv, p.gpv, skip)) return CMPC_ERR_HIP;
+  hipLaunchKernelGGL(scale_by_kernel, dim3(ceil_div(p.mx, 256)), dim3(256), 0, p.stream, p.gpv,
+                     p.Dx, p.mx, skip);
+  CMPC_LAUNCH_CHECK();
+  if (launch_gamma_t(p, p.gpv, 1, p.ref_gt, skip)) return CMPC_ERR_HIP;
+  if (launch_hv(p, p.pv, p.Hv, skip)) return CMPC_ERR_HIP;
+  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(256), 0, p.stream, p.rhs, p.Hv, p.ref_gt,
+                     p.Du, p.pv, p.ref_res, p.n, p.st);
+  CMPC_LAUNCH_CHECK();
+  if (launch_potrs(p.stream, p.K, p.n, p.n, p.Wdiag, p.ref_res, p.ref_dlt, p.tmpn, skip))
+    return CMPC_ERR_HIP;
+  hipLaunchKernelGGL(axpy_gated_kernel, dim3(ceil_div(p.n, 256)), dim3(256), 0, p.stream, p.pv,
+                     p.ref_dlt, p.n, skip);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
 // ---------------------------------------------------------------- one step from an iterate
 __global__ void set_step_state_kernel(IpmState* st, double mu, double tau) {
   st->mu = mu;
@@ -619,7 +705,7 @@ int launch_step_given(Problem& p, const double* v, const double* s, const double
   if (launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K)) return CMPC_ERR_HIP;
   if (launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info, &p.st->status))
     return CMPC_ERR_HIP;
-  if (launch_step(p)) return CMPC_ERR_HIP;
+  if (launch_step(p, 0)) return CMPC_ERR_HIP;
   hipLaunchKernelGGL(update_kernel, dim3(1), dim3(256), 0, p.stream, p.d, p.s, p.lam, p.z, p.gv,
                      p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part, p.n_step_blocks, p.mx,
                      p.n, p.st, 0);

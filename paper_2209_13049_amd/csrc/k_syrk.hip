@@ -214,11 +214,12 @@ __global__ __launch_bounds__(256, 2) void syrk_streamk_kernel(
     const TIn* __restrict__ Gam, const long long* __restrict__ off, const double* __restrict__ D,
     const SyrkJob* __restrict__ jobs, const int* __restrict__ wg_begin,
     const int2* __restrict__ tiles, double* __restrict__ partials, int ns, int nu, int nwg,
-    const int* __restrict__ done) {
+    const int* __restrict__ done, const int* __restrict__ lowflag, int want_low) {
   typedef MfmaOps<TIn> Ops;
   typedef typename Ops::acc_t acc_t;
   __shared__ double red[64 * 64];
   if (done != nullptr && *done) return;
+  if (lowflag != nullptr && (*lowflag != 0) != (want_low != 0)) return;
   const int per = nwg >> 3;
   const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -286,25 +287,33 @@ __global__ __launch_bounds__(256) void syrk_finish_kernel(
 }
 
 int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hbase,
-                const double* Ddiag, double* K, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                const double* Ddiag, double* K, hipEvent_t ev_start, hipEvent_t ev_stop,
+                int mixed) {
   SyrkPlan& sp = p.syrk;
   const int* done = p.st ? &p.st->done : nullptr;
-  if (precision == CMPC_FP32_SYRK) {
+  const int* low = mixed ? &p.st->use_low : nullptr;
+  const bool want32 = mixed || precision == CMPC_FP32_SYRK;
+  const bool want64 = mixed || precision != CMPC_FP32_SYRK;
+  if (want32) {
     if (p.Gam32 == nullptr) {
       set_error("FP32 copy of Gamma not allocated");
       return CMPC_ERR_INVALID;
     }
     hipExtLaunchKernelGGL(syrk_streamk_kernel<float>, dim3(sp.nwg), dim3(256), 0, p.stream,
-                          ev_start, ev_stop, 0, (const float*)p.Gam32, (const long long*)p.goff,
-                          Drow, (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
-                          (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done);
-  } else {
-    hipExtLaunchKernelGGL(syrk_streamk_kernel<double>, dim3(sp.nwg), dim3(256), 0, p.stream,
-                          ev_start, ev_stop, 0, (const double*)p.Gam, (const long long*)p.goff,
-                          Drow, (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
-                          (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done);
+                          ev_start, want64 ? nullptr : ev_stop, 0, (const float*)p.Gam32,
+                          (const long long*)p.goff, Drow, (const SyrkJob*)sp.jobs,
+                          (const int*)sp.wg_begin, (const int2*)sp.tiles, sp.partials, p.ns, p.nu,
+                          sp.nwg, done, low, 1);
+    CMPC_LAUNCH_CHECK();
   }
-  CMPC_LAUNCH_CHECK();
+  if (want64) {
+    hipExtLaunchKernelGGL(syrk_streamk_kernel<double>, dim3(sp.nwg), dim3(256), 0, p.stream,
+                          want32 ? nullptr : ev_start, ev_stop, 0, (const double*)p.Gam,
+                          (const long long*)p.goff, Drow, (const SyrkJob*)sp.jobs,
+                          (const int*)sp.wg_begin, (const int2*)sp.tiles, sp.partials, p.ns, p.nu,
+                          sp.nwg, done, low, 0);
+    CMPC_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(syrk_finish_kernel, dim3(sp.ntiles * 16), dim3(256), 0, p.stream, sp.partials,
                      sp.slot_begin, sp.slots, sp.tiles, Hbase, Ddiag, K, p.n, done);
   CMPC_LAUNCH_CHECK();

@@ -23,6 +23,9 @@ struct IpmState {
   int refine_steps;
   int nonc;      // mixed modes: refinement failures so far
   int x0_flag;   // device x0 check: 1 = outside the bounds, 2 = not finite
+  int ref_skip;  // mixed modes: nonzero = no (more) refinement in this iteration
+  int mixed;     // the solve started with a low-precision SYRK
+  double mu_switch, res_prev;
 };
 
 constexpr int kRunning = 100;
@@ -73,6 +76,7 @@ struct Problem {
   double *pv = nullptr, *ps = nullptr, *plam = nullptr, *pz = nullptr, *gpv = nullptr;
   double *rhs = nullptr, *Dx = nullptr, *Du = nullptr, *wx = nullptr, *wu = nullptr;
   double *gt = nullptr, *Hv = nullptr, *tmpn = nullptr, *tmpn2 = nullptr, *tmpmx = nullptr;
+  double *ref_res = nullptr, *ref_dlt = nullptr, *ref_gt = nullptr;  // refinement vectors (n)
   double *norm_part = nullptr, *alpha_part = nullptr, *gt_part = nullptr;
   int n_prep_blocks = 0, n_step_blocks = 0, gt_chunks = 0, gt_rows = 0;
   IpmState* st = nullptr;
@@ -103,16 +107,22 @@ int launch_dense_gamma(Problem& p, double* dense);
 int syrk_plan(Problem& p);
 void syrk_free(SyrkPlan& sp);
 // K(lower) = Hbase(lower) + Gamma' diag(Drow) Gamma + diag(Ddiag)   (Ddiag may be NULL)
-// ev_start / ev_stop (optional): timing events attached to the stream-K kernel's dispatch
+// ev_start / ev_stop (optional): timing events attached to the stream-K kernel's dispatch.
+// precision CMPC_FP64 or CMPC_FP32_SYRK; mixed != 0 queues both variants, each running only
+// when the device flag st->use_low selects it.
 int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hbase,
                 const double* Ddiag, double* K, hipEvent_t ev_start = nullptr,
-                hipEvent_t ev_stop = nullptr);
+                hipEvent_t ev_stop = nullptr, int mixed = 0);
+int launch_convert_gamma(Problem& p, int precision);
 
 // ---- Cholesky (k_chol.hip) ----
 // Wall: ceil(n/64) x 64 x 64 doubles receiving the inverses of the diagonal factor tiles
-// ev_start / ev_stop (optional): timing events attached to the first and last dispatch
+// ev_start / ev_stop (optional): timing events attached to the first and last dispatch.
+// lowflag (optional): if it is set when a pivot fails, it is cleared and *done = 2 (redo the
+// iteration in FP64) instead of reporting the breakdown.
 int launch_potrf(hipStream_t s, double* K, int n, int ld, double* Wall, int* done, int* info,
-                 int* status, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                 int* status, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
+                 int* lowflag = nullptr);
 // x = (L L')^-1 b with n doubles of scratch `work` (distinct from b and x); x may alias b
 int launch_potrs(hipStream_t s, const double* L, int n, int ld, const double* Wall,
                  const double* b, double* x, double* work, const int* done);
@@ -125,9 +135,10 @@ int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done);
 int launch_ipm_init(Problem& p, const cmpc_options& o);
 int launch_prep(Problem& p);
 int launch_mu_rhs(Problem& p);
-int launch_step(Problem& p);
+int launch_step(Problem& p, int refine);  // refine: refinement steps queued (mixed modes)
 int launch_update(Problem& p);
 int launch_publish(Problem& p, int slot);
+int launch_refine_step(Problem& p);
 int launch_sigma_fold(Problem& p, const double* sigma);
 int launch_step_given(Problem& p, const double* v, const double* s, const double* lam,
                       const double* z, double mu, double tau);

@@ -257,3 +257,39 @@ def test_cholesky_large(lib, n):
     condmpc.potrf(Kt)
     L = np.tril(Kt.cpu().numpy())
     assert rel_err(L, np.linalg.cholesky(A)) <= 1e-11
+
+
+# ----------------------------------------------------------------- mixed precision (FP32 SYRK)
+
+@pytest.mark.parametrize("name", ["small", "ragged", "wide", "tight"])
+def test_condensed_matrix_fp32(problems, name):
+    """The FP32-MFMA SYRK (FP64 H and diagonal) against the FP64 oracle: products rounded to
+    FP32 (u = 6e-8) summed over <= 1e4 terms in blocks -> within 1e-5 of the largest entry."""
+    p, gp, red = problems[name]
+    rng = np.random.default_rng(5)
+    sig = rng.uniform(0.01, 10.0, red.d.size)
+    full, _ = _sigma_full(gp, red, sig)
+    K = torch.zeros(gp.n, gp.n, dtype=torch.float64, device=DEV)
+    gp.form_condensed(gpu(full), K, precision=condmpc.FP32_SYRK)
+    K_ref = oracle.condensed_matrix(red, sig)
+    lo = np.tril_indices(gp.n)
+    err = rel_err(K.cpu().numpy()[lo], K_ref[lo])
+    assert 0 < err <= 1e-5   # nonzero: the low-precision kernel really ran
+
+
+@pytest.mark.parametrize("name", ["small", "ragged", "wide", "tight", "inf", "genq"])
+def test_mixed_precision_solve(problems, name):
+    """FP32 SYRK + FP64 Cholesky + FP64 iterative refinement meets the FP64 bar: objective
+    within 1e-8 relative of the oracle, KKT residuals within 1e-8."""
+    p, gp, red = problems[name]
+    ref = oracle.solve(p, red=red)
+    res = gp.solve(precision=condmpc.FP32_SYRK)
+    print(f"[mixed] {name}: iters {res['iters']} (oracle {ref.iters}) switch "
+          f"{res['precision_switch_iter']} refine {res['refine_steps']} obj rel "
+          f"{abs(res['obj'] - ref.obj) / max(1, abs(ref.obj)):.2e}", flush=True)
+    assert res["status"] == condmpc.OK
+    assert abs(res["obj"] - ref.obj) <= 1e-8 * max(1.0, abs(ref.obj))
+    assert res["primal_res"] <= 1e-8 and res["dual_res"] <= 1e-8 and res["compl_res"] <= 1e-8
+    assert abs(res["iters"] - ref.iters) <= 2
+    u, _ = gp.solution(with_x=False)
+    assert rel_err(u, ref.v) <= 1e-6
