@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--cpu-solves", type=int, default=1)
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the timed run at the other precision")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain elementwise copy of 256 MiB (reference for the "
+                         "hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU "
@@ -95,6 +98,12 @@ def main():
     from paper_2209_13049_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        a = torch.ones(32 * 2**20, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
     cfg = W.CONFIG_1D
     base = W.heat1d_config("1d", instance=0)
     prob = condmpc.Problem(base)
