@@ -72,6 +72,125 @@ def cpu_baseline(p, solves: int = 1):
             "s_per_iter": total / max(1, iters)}
 
 
+def batch_leg(steps: int, count: int = 512):
+    """Ragged batch of `count` 1-D heat instances (ns in [100, 2000], nu in [2, 16], N in
+    [16, 64]): FP32 SYRK + FP64 Cholesky, autotuned plans, graph-replayed iterations.
+    Returns the batched throughput, the same batch in FP64, and the instances solved one by
+    one with the single-instance path."""
+    import torch
+    from paper_2209_13049_amd import condmpc
+    from paper_2209_13049_amd import workloads as W
+    t0 = time.perf_counter()
+    probs = W.batch_instances(count, seed=3)
+    b = condmpc.Batch(probs)
+    t_create = time.perf_counter() - t0
+    tune = b.tune(condmpc.FP32_SYRK)
+    out = {"workload": f"heat1d_batch{count}_ns100-2000_nu2-16_N16-64",
+           "instances": count, "create_s": t_create, "tune": tune}
+    for prec, name in ((condmpc.FP32_SYRK, "fp32_syrk"), (condmpc.FP64, "fp64")):
+        rc, res = b.solve(precision=prec)                     # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = 0
+        for _ in range(steps):
+            rc, res = b.solve(precision=prec)
+            iters += max(r["iters"] for r in res)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"instances_per_s": count * steps / el, "ms_per_batch": el * 1e3 / steps,
+                     "ms_per_batch_iter": el * 1e3 / max(1, iters),
+                     "converged": sum(r["status"] == 0 for r in res),
+                     "max_iters": max(r["iters"] for r in res),
+                     "mean_iters": sum(r["iters"] for r in res) / count}
+    # the same instances one at a time through the single-instance path (FP32 SYRK)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(count):
+        b[i].solve(precision=condmpc.FP32_SYRK)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["one_by_one_fp32_syrk"] = {"instances_per_s": count / el}
+    out["batched_speedup_vs_one_by_one"] = out["fp32_syrk"]["instances_per_s"] / (count / el)
+    # objective of the two smallest instances against the oracle
+    import oracle
+    small = sorted(range(count), key=lambda i: b[i].mx * b[i].n)[:2]
+    rc, res = b.solve(precision=condmpc.FP32_SYRK)
+    errs = []
+    for i in small:
+        ref = oracle.solve(probs[i])
+        errs.append(abs(res[i]["obj"] - ref.obj) / max(1.0, abs(ref.obj)))
+    out["oracle_check"] = {"instances": small, "max_obj_rel_err": max(errs)}
+    b.close()
+    return out
+
+
+def surrogate_leg(ntrain: int, nquery: int, epochs: int, replicas: int = 64):
+    """Config-2 problem (ns = 1000, nu N = 500) with smooth random x0 fields: the batched IPM
+    generates (x0, u*) pairs, the BF16 network (1000 -> 4 x 1024 GELU -> 500) trains on the
+    GPU, and `nquery` held-out queries are answered by network + FP64 judge + fallback."""
+    import numpy as np
+    import torch
+    from paper_2209_13049_amd import condmpc
+    from paper_2209_13049_amd import workloads as W
+    base = W.heat1d_config("1d", instance=0)
+    X = W.smooth_x0(base.A.shape[0], ntrain + nquery, seed=4)
+    b = condmpc.Batch([base] * replicas, with_x0=False)
+    U = np.empty((X.shape[0], base.B.shape[1] * base.N))
+    fstar = np.empty(X.shape[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k0 in range(0, X.shape[0], replicas):
+        k1 = min(X.shape[0], k0 + replicas)
+        for i in range(replicas):
+            b[i].set_x0(X[min(k0 + i, k1 - 1)])
+        rc, res = b.solve()
+        for i in range(k1 - k0):
+            if res[i]["status"] != 0:
+                raise RuntimeError(f"IPM data generation: status {res[i]['status']}")
+            U[k0 + i] = b[i].solution(with_x=False)[0]
+            fstar[k0 + i] = res[i]["obj"]
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    b.close()
+    gp = condmpc.Problem(base)
+    gp.set_x0(base.x0)
+    widths = W.mlp_widths(base.A.shape[0], U.shape[1])
+    net = condmpc.Mlp(gp, W.mlp_init(widths, seed=5), 1024, 4, condmpc.MLP_BF16)
+    Xd = torch.from_numpy(X).to("cuda:0")
+    Ud = torch.from_numpy(U).to("cuda:0")
+    order = W.shuffle_order(ntrain, epochs, seed=6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = net.train(Xd[:ntrain].contiguous(), Ud[:ntrain].contiguous(), order=order,
+                       batch=512, epochs=epochs, lr=1e-3, lr_final=1e-6)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    Xq = Xd[ntrain:].contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, acc, rep = net.solve(Xq)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    _, vio, f, lb = net.judge(Xq, u)
+    true_gap = (f - fstar[ntrain:]) / np.abs(fstar[ntrain:])
+    ipm_rate = X.shape[0] / t_data
+    out = {"workload": "heat1d_ns1000_nu10_N50_smooth_x0", "train_pairs": ntrain,
+           "queries": nquery, "params": net.nparams, "epochs": epochs,
+           "data_gen_s": t_data, "ipm_batch_solves_per_s": ipm_rate,
+           "train_s": t_train, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+           "accepted": int(acc.sum()), "accept_rate": float(acc.mean()),
+           "ms_infer": rep["ms_infer"], "ms_judge": rep["ms_judge"],
+           "ms_fallback": rep["ms_fallback"], "solve_s": t_solve,
+           "accepted_answers_per_s": int(acc.sum()) / ((rep["ms_infer"] + rep["ms_judge"]) / 1e3),
+           "answers_per_s_with_fallback": nquery / t_solve,
+           "max_true_gap_accepted": float(np.max(true_gap[acc])) if acc.any() else None,
+           "max_violation_accepted": rep["max_violation_accepted"],
+           "max_certified_gap_accepted": rep["max_gap_accepted"]}
+    net.close()
+    gp.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +201,12 @@ def main():
     ap.add_argument("--cpu-solves", type=int, default=1)
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the timed run at the other precision")
+    ap.add_argument("--batch-steps", type=int, default=2,
+                    help="timed solves of the 512-instance batch (0 = skip the batch leg)")
+    ap.add_argument("--surrogate-train", type=int, default=16384,
+                    help="IPM-generated training pairs of the surrogate (0 = skip the leg)")
+    ap.add_argument("--surrogate-queries", type=int, default=4096)
+    ap.add_argument("--surrogate-epochs", type=int, default=60)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB (reference for the "
                          "hardware byte counters)")
@@ -195,9 +320,14 @@ def main():
             "syrk_peak_tflops": PEAK[other],
             "max_obj_rel_diff": max(rel) if rel else None,
         }
+    prob.close()
+    if args.batch_steps > 0:
+        out["batch"] = batch_leg(args.batch_steps)
+    if args.surrogate_train > 0:
+        out["surrogate"] = surrogate_leg(args.surrogate_train, args.surrogate_queries,
+                                         args.surrogate_epochs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(base, args.cpu_solves)
-    prob.close()
     print(json.dumps(out))
 
 

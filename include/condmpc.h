@@ -18,7 +18,8 @@
  *   - Work is issued on the HIP stream given at creation (NULL = the default stream).
  *   - Return value: 0 on success, a positive solver outcome, or a negative error code
  *     (below).  cmpc_last_error() gives a message for the calling thread's last error.
- *   - The library has no global state besides per-thread error messages.
+ *   - The library has no global state besides per-thread error messages and the SYRK
+ *     tuning table (cmpc_batch_tune).
  *
  * Readings of the paper that the library implements (Algorithm 1 leaves them open):
  *   objective with 1/2 on every quadratic term; Q_f = Q when NULL; state bounds for
@@ -49,7 +50,10 @@ extern "C" {
 
 /* ---- precision of the SYRK that forms K (Section 3 forms K in one precision; the
  *      mixed modes are this library's extension, with FP64 Cholesky and FP64 iterative
- *      refinement against the exact K) ---- */
+ *      refinement against the exact K).  A mixed solve starts at the given level and moves
+ *      up (BF16 -> FP32 -> FP64) after two refinement steps that fail to shrink the
+ *      residual 10x, after a Cholesky breakdown (the iteration is redone), and straight to
+ *      FP64 once mu < mu_switch. ---- */
 #define CMPC_FP64 0
 #define CMPC_FP32_SYRK 1
 #define CMPC_BF16_SYRK 2
@@ -69,7 +73,7 @@ typedef struct {
 typedef struct {
   double tol;        /* KKT tolerance of the stopping test (default 1e-8) */
   int max_iter;      /* iteration limit (default 200) */
-  int precision;     /* CMPC_FP64 (default), CMPC_FP32_SYRK or CMPC_BF16_SYRK */
+  int precision;     /* CMPC_FP64 (default), CMPC_FP32_SYRK or CMPC_BF16_SYRK (start level) */
   int max_refine;    /* mixed modes: refinement steps per solve (default 5) */
   double mu_switch;  /* mixed modes: use the FP64 SYRK once mu < mu_switch (default 1e-6) */
   int check_every;   /* iterations queued ahead of the convergence flag the host has seen
@@ -77,6 +81,8 @@ typedef struct {
   int profile;       /* nonzero: time the formation and the Cholesky factorisation of K in
                         every iteration with HIP events on the problem's stream (fills
                         ms_syrk, ms_form, ms_potrf) */
+  int equilibrate;   /* factor S K S with S = diag(K)^-1/2 instead of K: 1 on, 0 off,
+                        -1 (default) on in the mixed modes only */
 } cmpc_options;
 
 typedef struct {
@@ -180,6 +186,139 @@ int cmpc_potrf(double* K, int n, int ld, void* stream, int* info);
 
 /* Solve L L' x = b in place (b: n, device) with the factor from cmpc_potrf. */
 int cmpc_potrs(const double* L, int n, int ld, double* b, void* stream);
+
+/* ---- ragged batches (library extension: many independent instances of eqn. (sparse),
+ *      each reduced as in Section 2 and solved by Algorithm 1, advanced together) ---- */
+typedef struct cmpc_batch cmpc_batch;
+
+/* Result of cmpc_batch_tune. */
+typedef struct {
+  int quantum;        /* chosen SYRK work quantum (target work per stream-K workgroup) */
+  int persistent;     /* chosen grid policy: 1 = persistent workgroups loop over each work
+                         list, 0 = one workgroup per work item */
+  int candidates;     /* settings timed */
+  double syrk_us;     /* time of one batched formation of K with the chosen setting */
+  double default_us;  /* the same with the default setting (quantum 12000, persistent) */
+} cmpc_tune_report;
+
+/* Create `count` problems from descs[0..count) as cmpc_problem_create does, and set
+ * instance i's initial state from the host array x0s[i] (length ns of that instance) when
+ * x0s != NULL and x0s[i] != NULL.  Instances may differ in ns, nu and N.  stream is used
+ * for the set-up work and for calls on the instance handles; solves run on a stream of
+ * the batch's own.  Errors as cmpc_problem_create and cmpc_set_x0 (the message names the
+ * instance); on error nothing is kept. */
+int cmpc_batch_create(int count, const cmpc_lq_desc* descs, const double* const* x0s,
+                      void* stream, cmpc_batch** out);
+
+/* Release the batch and all of its instances (NULL is ignored). */
+void cmpc_batch_destroy(cmpc_batch* b);
+
+/* Number of instances (0 for NULL). */
+int cmpc_batch_size(const cmpc_batch* b);
+
+/* Borrowed handle of instance i (0 <= i < size), valid until cmpc_batch_destroy: use it with
+ * cmpc_set_x0, cmpc_get_solution, cmpc_get_iterate, cmpc_problem_info and the other
+ * per-problem calls.  cmpc_problem_destroy on it does nothing.  NULL if i is out of range. */
+cmpc_problem* cmpc_batch_instance(cmpc_batch* b, int i);
+
+/* Run Algorithm 1 on every instance at once: each stage of an iteration is one launch over
+ * a work list of (instance, block) items, one iteration is a captured HIP graph, and
+ * instances that have stopped are skipped until all have.  opts as cmpc_solve (NULL =
+ * defaults; tol, max_iter, precision, max_refine, mu_switch, check_every; profile is
+ * ignored).  results[i] (may be NULL) receives instance i's outcome; ms_total is the time of
+ * the whole batch.  Every instance needs an x0.  In FP64 every instance's iterates equal
+ * bit for bit those of cmpc_solve on that instance (same tuning-table entry).  Returns 0 if
+ * all converged, else a negative error of some instance or its positive outcome. */
+int cmpc_batch_solve(cmpc_batch* b, const cmpc_options* opts, cmpc_result* results);
+
+/* Autotuner: time the batched formation of K at the start point of the method for each
+ * candidate SYRK work quantum (3000 ... 96000) and grid policy, keep the fastest for this
+ * batch and record it in the process-wide tuning table under (n, mx, precision) of every
+ * instance.  Later solves (batched or single) of a problem with such a key build their
+ * SYRK plan from the table.  precision: CMPC_FP64, CMPC_FP32_SYRK or CMPC_BF16_SYRK.  rep
+ * may be NULL.
+ * Every instance needs an x0; their iterates are overwritten. */
+int cmpc_batch_tune(cmpc_batch* b, int precision, cmpc_tune_report* rep);
+
+/* Tuning-table entry for (n, mx, precision): returns 0 and fills the outputs (may be NULL)
+ * if present, 1 if not. */
+int cmpc_tune_lookup(int n, int mx, int precision, int* quantum, int* persistent);
+
+/* Empty the tuning table (plans are rebuilt with the defaults at the next solve). */
+void cmpc_tune_clear(void);
+
+/* ---- surrogate policy (library extension): a multilayer perceptron x0 -> u trained on
+ *      the solutions of Algorithm 1, whose answers Algorithm 1 judges and replaces ---- */
+#define CMPC_MLP_BF16 0       /* bfloat16 weights and activations, float32 accumulation */
+#define CMPC_MLP_FP32 1       /* float32 throughout (test mode) */
+#define CMPC_JUDGE_VIOLATION 1e-4  /* largest accepted bound violation of the states */
+#define CMPC_JUDGE_GAP 1e-3        /* largest accepted (f(u) - LB) / |LB| */
+
+typedef struct cmpc_mlp cmpc_mlp;
+
+typedef struct {
+  int batch;           /* minibatch rows, 1..4096 (default 512) */
+  int epochs;          /* passes over the data (default 20) */
+  float lr, lr_final;  /* AdamW step size, cosine-decayed from lr to lr_final (1e-3, 1e-5) */
+  float beta1, beta2, eps;  /* AdamW moments (0.9, 0.999, 1e-8) */
+  float weight_decay;  /* decoupled decay of the weight matrices, not the biases (1e-4) */
+} cmpc_train_opts;
+
+typedef struct {
+  int count, accepted;            /* queries, answers the judge certified */
+  int fallback_solved;            /* rejected answers replaced by a converged solve */
+  int fallback_failed;            /* rejected answers whose solve did not converge */
+  double max_violation_accepted;  /* largest state-bound violation among accepted answers */
+  double max_gap_accepted;        /* largest certified relative gap among accepted answers */
+  double ms_infer, ms_judge;      /* device time of the network and of the judge */
+  double ms_fallback, ms_total;   /* host wall time of the fallback solves and of the call */
+} cmpc_surrogate_report;
+
+void cmpc_default_train_opts(cmpc_train_opts* opts);
+
+/* Network for problem p (it must outlive the network): widths ns -> hidden (depth times,
+ * GELU) -> nu N, initial parameters `init` (host float32, packed W_1, b_1, ..., W_L+1,
+ * b_L+1, each W_l row-major d_l x d_(l-1)).  hidden % 64 == 0, 1 <= depth <= 16.  The judge
+ * needs diagonal Q and Q_f, nu <= 64 and ns <= 3500; creation also forms the unconstrained
+ * cost-to-go P_0 of the Riccati recursion (FP64) for the judge's lower bound. */
+int cmpc_mlp_create(cmpc_problem* p, int hidden, int depth, int precision, const float* init,
+                    cmpc_mlp** out);
+void cmpc_mlp_destroy(cmpc_mlp* m);
+long long cmpc_mlp_param_count(const cmpc_mlp* m);
+/* Packed float32 master parameters (layout as `init`), host. */
+int cmpc_mlp_get_params(const cmpc_mlp* m, float* params);
+/* Replace the parameters and reset the AdamW state. */
+int cmpc_mlp_set_params(cmpc_mlp* m, const float* params);
+
+/* One forward and backward pass without an update: gradients of the mean squared error
+ * between the network output and ustars over `count` rows (x0s: count x ns, ustars:
+ * count x nu N, device float64; count <= 4096).  grads (host, packed like the parameters),
+ * loss (host) and y (host, count x nu N unclipped outputs) may be NULL. */
+int cmpc_mlp_gradients(cmpc_mlp* m, const double* x0s, const double* ustars, int count,
+                       float* grads, double* loss, float* y);
+
+/* AdamW training: epoch e visits rows order[e count + i] (host; NULL = 0..count-1) in
+ * minibatches of opts->batch.  epoch_loss (host, epochs entries, may be NULL) receives the
+ * mean loss of each epoch.  x0s, ustars: device float64. */
+int cmpc_mlp_train(cmpc_mlp* m, const double* x0s, const double* ustars, int count,
+                   const cmpc_train_opts* opts, const int* order, double* epoch_loss);
+
+/* u (device, count x nu N) = network output clipped to the control bounds. */
+int cmpc_mlp_predict(cmpc_mlp* m, const double* x0s, int count, double* u);
+
+/* FP64 judge of answers u for initial states x0s (device): simulate eqn. (dyn), take the
+ * largest bound violation of x_1..x_N, the objective f(u) and LB = 1/2 x0'P_0 x0 (the
+ * unconstrained minimum h0 - 1/2 h'H^-1 h); accept iff violation <= CMPC_JUDGE_VIOLATION
+ * and (f - LB)/|LB| <= CMPC_JUDGE_GAP.  Host outputs, each may be NULL. */
+int cmpc_judge(cmpc_mlp* m, const double* x0s, const double* u, int count, int* accepted,
+               double* violation, double* f, double* lb);
+
+/* Answer `count` queries: predict, judge, and replace every rejected answer by the FP64
+ * solve of Algorithm 1 from that x0 (on the network's problem, whose x0 is overwritten).
+ * u: device (count x nu N); accepted: host (may be NULL); rep may be NULL.  Returns 0, or
+ * CMPC_MAX_ITER if a fallback solve did not converge. */
+int cmpc_surrogate_solve(cmpc_mlp* m, const double* x0s, int count, double* u, int* accepted,
+                         cmpc_surrogate_report* rep);
 
 /* Message of the calling thread's last error ("" if none). */
 const char* cmpc_last_error(void);

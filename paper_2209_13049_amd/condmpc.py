@@ -17,13 +17,18 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcondmpc.
 OK, MAX_ITER, SMALL_STEP = 0, 1, 2
 ERR_INVALID, ERR_NONFINITE, ERR_X0_BOUNDS, ERR_CHOLESKY, ERR_HIP, ERR_NOMEM = -1, -2, -3, -4, -5, -6
 FP64, FP32_SYRK, BF16_SYRK = 0, 1, 2
+MLP_BF16, MLP_FP32 = 0, 1
 
 # every function declared in include/condmpc.h
 EXPORTS = [
     "cmpc_default_options", "cmpc_problem_create", "cmpc_problem_destroy", "cmpc_problem_dims",
     "cmpc_problem_info", "cmpc_set_x0", "cmpc_solve", "cmpc_get_solution", "cmpc_get_iterate", "cmpc_export_dense",
-    "cmpc_form_condensed", "cmpc_newton_step", "cmpc_potrf", "cmpc_potrs", "cmpc_last_error",
-    "cmpc_status_str",
+    "cmpc_form_condensed", "cmpc_newton_step", "cmpc_potrf", "cmpc_potrs", "cmpc_batch_create",
+    "cmpc_batch_destroy", "cmpc_batch_size", "cmpc_batch_instance", "cmpc_batch_solve",
+    "cmpc_batch_tune", "cmpc_tune_lookup", "cmpc_tune_clear", "cmpc_default_train_opts",
+    "cmpc_mlp_create", "cmpc_mlp_destroy", "cmpc_mlp_param_count", "cmpc_mlp_get_params",
+    "cmpc_mlp_set_params", "cmpc_mlp_gradients", "cmpc_mlp_train", "cmpc_mlp_predict",
+    "cmpc_judge", "cmpc_surrogate_solve", "cmpc_last_error", "cmpc_status_str",
 ]
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -39,7 +44,7 @@ class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("max_refine", ctypes.c_int),
                 ("mu_switch", ctypes.c_double), ("check_every", ctypes.c_int),
-                ("profile", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("equilibrate", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -60,6 +65,34 @@ class Info(ctypes.Structure):
                 ("gamma_nnz", ctypes.c_longlong), ("syrk_flops", ctypes.c_double),
                 ("potrf_flops", ctypes.c_double), ("syrk_workgroups", ctypes.c_int),
                 ("syrk_partial_slots", ctypes.c_int), ("device_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("quantum", ctypes.c_int), ("persistent", ctypes.c_int),
+                ("candidates", ctypes.c_int), ("syrk_us", ctypes.c_double),
+                ("default_us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int), ("epochs", ctypes.c_int), ("lr", ctypes.c_float),
+                ("lr_final", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("weight_decay", ctypes.c_float)]
+
+
+class SurrogateReport(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int), ("accepted", ctypes.c_int),
+                ("fallback_solved", ctypes.c_int), ("fallback_failed", ctypes.c_int),
+                ("max_violation_accepted", ctypes.c_double),
+                ("max_gap_accepted", ctypes.c_double), ("ms_infer", ctypes.c_double),
+                ("ms_judge", ctypes.c_double), ("ms_fallback", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -93,6 +126,26 @@ def load(path: str = LIB_PATH):
                                  vp, vp, vp]),
         "cmpc_potrf": (i, [vp, i, i, vp, ctypes.POINTER(i)]),
         "cmpc_potrs": (i, [vp, i, i, vp, vp]),
+        "cmpc_batch_create": (i, [i, ctypes.POINTER(LQDesc), ctypes.POINTER(_dp), vp,
+                                  ctypes.POINTER(vp)]),
+        "cmpc_batch_destroy": (None, [vp]),
+        "cmpc_batch_size": (i, [vp]),
+        "cmpc_batch_instance": (vp, [vp, i]),
+        "cmpc_batch_solve": (i, [vp, ctypes.POINTER(Options), ctypes.POINTER(Result)]),
+        "cmpc_batch_tune": (i, [vp, i, ctypes.POINTER(TuneReport)]),
+        "cmpc_tune_lookup": (i, [i, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
+        "cmpc_tune_clear": (None, []),
+        "cmpc_default_train_opts": (None, [ctypes.POINTER(TrainOpts)]),
+        "cmpc_mlp_create": (i, [vp, i, i, i, vp, ctypes.POINTER(vp)]),
+        "cmpc_mlp_destroy": (None, [vp]),
+        "cmpc_mlp_param_count": (ctypes.c_longlong, [vp]),
+        "cmpc_mlp_get_params": (i, [vp, vp]),
+        "cmpc_mlp_set_params": (i, [vp, vp]),
+        "cmpc_mlp_gradients": (i, [vp, vp, vp, i, vp, vp, vp]),
+        "cmpc_mlp_train": (i, [vp, vp, vp, i, ctypes.POINTER(TrainOpts), vp, vp]),
+        "cmpc_mlp_predict": (i, [vp, vp, i, vp]),
+        "cmpc_judge": (i, [vp, vp, vp, i, vp, vp, vp, vp]),
+        "cmpc_surrogate_solve": (i, [vp, vp, i, vp, vp, ctypes.POINTER(SurrogateReport)]),
         "cmpc_last_error": (ctypes.c_char_p, []),
         "cmpc_status_str": (ctypes.c_char_p, [i]),
     }
@@ -146,24 +199,33 @@ def default_options(**kw) -> Options:
     return o
 
 
+def _desc(prob):
+    """LQDesc of an LQProblem and the host arrays it points into (keep them alive)."""
+    keep = [_f64(prob.A), _f64(prob.B), _f64(prob.Q), _f64(prob.R), _f64(prob.Qf),
+            _f64(prob.xl), _f64(prob.xu), _f64(prob.ul), _f64(prob.uu)]
+    A, B, Q, R, Qf, xl, xu, ul, uu = keep
+    d = LQDesc(ns=A.shape[0], nu=B.shape[1], N=int(prob.N), A=_ptr(A), B=_ptr(B), Q=_ptr(Q),
+               R=_ptr(R), Qf=_ptr(Qf), xl=_ptr(xl), xu=_ptr(xu), ul=_ptr(ul), uu=_ptr(uu))
+    return d, keep
+
+
 class Problem:
     """A reduced LQ-MPC problem resident on the GPU (wraps cmpc_problem)."""
 
-    def __init__(self, prob, stream=None):
+    def __init__(self, prob, stream=None, _handle=None):
         lib = load()
-        self._keep = [_f64(prob.A), _f64(prob.B), _f64(prob.Q), _f64(prob.R), _f64(prob.Qf),
-                      _f64(prob.xl), _f64(prob.xu), _f64(prob.ul), _f64(prob.uu)]
-        A, B, Q, R, Qf, xl, xu, ul, uu = self._keep
-        d = LQDesc(ns=A.shape[0], nu=B.shape[1], N=int(prob.N), A=_ptr(A), B=_ptr(B),
-                   Q=_ptr(Q), R=_ptr(R), Qf=_ptr(Qf), xl=_ptr(xl), xu=_ptr(xu), ul=_ptr(ul),
-                   uu=_ptr(uu))
-        self._h = ctypes.c_void_p()
-        st = _stream() if stream is None else ctypes.c_void_p(stream)
-        _check(lib.cmpc_problem_create(ctypes.byref(d), st, ctypes.byref(self._h)))
+        self._borrowed = _handle is not None
+        if _handle is None:
+            d, self._keep = _desc(prob)
+            self._h = ctypes.c_void_p()
+            st = _stream() if stream is None else ctypes.c_void_p(stream)
+            _check(lib.cmpc_problem_create(ctypes.byref(d), st, ctypes.byref(self._h)))
+        else:
+            self._h = ctypes.c_void_p(_handle)
         n, mx, m = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib.cmpc_problem_dims(self._h, ctypes.byref(n), ctypes.byref(mx), ctypes.byref(m)))
         self.n, self.mx, self.m = n.value, mx.value, m.value
-        self.ns, self.nu, self.N = A.shape[0], B.shape[1], int(prob.N)
+        self.ns, self.nu, self.N = int(np.shape(prob.A)[0]), int(np.shape(prob.B)[1]), int(prob.N)
 
     def info(self) -> dict:
         inf = Info()
@@ -171,9 +233,9 @@ class Problem:
         return inf.as_dict()
 
     def close(self):
-        if self._h:
+        if self._h and not self._borrowed:
             load().cmpc_problem_destroy(self._h)
-            self._h = ctypes.c_void_p()
+        self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:
@@ -246,6 +308,186 @@ class Problem:
                                        float(tau), _dev(pv), _dev(ps), _dev(plam), _dev(pz),
                                        al.ctypes.data_as(ctypes.c_void_p)))
         return dict(pv=pv, ps=ps, plam=plam, pz=pz, alpha=float(al[0]), alpha_z=float(al[1]))
+
+
+class Batch:
+    """Independent problems of uneven size solved together (wraps cmpc_batch).
+
+    probs: LQProblems; their x0 is set at creation unless with_x0 is False.  Instance i is
+    available as batch[i], a Problem sharing the batch's device memory (valid until close).
+    """
+
+    def __init__(self, probs, with_x0=True, stream=None):
+        lib = load()
+        probs = list(probs)
+        self.count = len(probs)
+        descs = (LQDesc * self.count)()
+        self._keep = []
+        x0p = (_dp * self.count)()
+        for i, pr in enumerate(probs):
+            d, keep = _desc(pr)
+            descs[i] = d
+            self._keep.append(keep)
+            if with_x0 and pr.x0 is not None:
+                x0 = _f64(pr.x0)
+                self._keep.append(x0)
+                x0p[i] = _ptr(x0)
+        self._h = ctypes.c_void_p()
+        st = _stream() if stream is None else ctypes.c_void_p(stream)
+        _check(lib.cmpc_batch_create(self.count, descs, x0p, st, ctypes.byref(self._h)))
+        self.instances = []
+        for i, pr in enumerate(probs):
+            h = lib.cmpc_batch_instance(self._h, i)
+            if not h:
+                raise CmpcError(ERR_INVALID, lib.cmpc_last_error().decode())
+            self.instances.append(Problem(pr, _handle=h))
+
+    def __len__(self):
+        return self.count
+
+    def __getitem__(self, i) -> Problem:
+        return self.instances[i]
+
+    def solve(self, **opts):
+        """Returns (status, list of per-instance result dicts)."""
+        o = default_options(**opts)
+        res = (Result * self.count)()
+        rc = load().cmpc_batch_solve(self._h, ctypes.byref(o), res)
+        if rc < 0 and not any(r.status < 0 for r in res):
+            _check(rc)
+        return rc, [r.as_dict() for r in res]
+
+    def solve_raw(self, options: Options, results) -> int:
+        return load().cmpc_batch_solve(self._h, ctypes.byref(options), results)
+
+    def tune(self, precision=FP64) -> dict:
+        rep = TuneReport()
+        _check(load().cmpc_batch_tune(self._h, precision, ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def close(self):
+        if self._h:
+            for p in self.instances:
+                p._h = ctypes.c_void_p()
+            load().cmpc_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _hp(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def default_train_opts(**kw) -> TrainOpts:
+    o = TrainOpts()
+    load().cmpc_default_train_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Mlp:
+    """Surrogate policy x0 -> u for one problem (wraps cmpc_mlp).
+
+    params: packed float32 initial parameters (W_1, b_1, ..., W_L+1, b_L+1).  Device inputs
+    are float64 torch CUDA tensors: x0s (count x ns), ustars (count x nu N)."""
+
+    def __init__(self, problem: Problem, params, hidden=1024, depth=4, precision=MLP_BF16):
+        self.problem = problem          # the network answers this problem; keep it alive
+        self.hidden, self.depth, self.precision = hidden, depth, precision
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        w = [problem.ns] + [hidden] * depth + [problem.n]
+        need = sum(w[l] * w[l - 1] + w[l] for l in range(1, len(w)))
+        if p.size != need:
+            raise ValueError(f"expected {need} packed parameters, got {p.size}")
+        self._h = ctypes.c_void_p()
+        _check(load().cmpc_mlp_create(problem._h, hidden, depth, precision, _hp(p),
+                                      ctypes.byref(self._h)))
+        self.nparams = int(load().cmpc_mlp_param_count(self._h))
+
+    def close(self):
+        if self._h:
+            load().cmpc_mlp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        out = np.empty(self.nparams, dtype=np.float32)
+        _check(load().cmpc_mlp_get_params(self._h, _hp(out)))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(load().cmpc_mlp_set_params(self._h, _hp(p)))
+
+    def gradients(self, x0s, ustars):
+        count = int(x0s.shape[0])
+        g = np.empty(self.nparams, dtype=np.float32)
+        loss = np.zeros(1)
+        y = np.empty((count, self.problem.n), dtype=np.float32)
+        _check(load().cmpc_mlp_gradients(self._h, _dev(x0s), _dev(ustars), count, _hp(g),
+                                         _hp(loss), _hp(y)))
+        return g, float(loss[0]), y
+
+    def train(self, x0s, ustars, order=None, **opts):
+        o = default_train_opts(**opts)
+        count = int(x0s.shape[0])
+        losses = np.zeros(o.epochs)
+        ordp = None
+        if order is not None:
+            order = np.ascontiguousarray(order, dtype=np.int32)
+            assert order.size == o.epochs * count
+            ordp = _hp(order)
+        _check(load().cmpc_mlp_train(self._h, _dev(x0s), _dev(ustars), count, ctypes.byref(o),
+                                     ordp, _hp(losses)))
+        return losses
+
+    def predict(self, x0s):
+        import torch
+        u = torch.empty((x0s.shape[0], self.problem.n), dtype=torch.float64, device=x0s.device)
+        _check(load().cmpc_mlp_predict(self._h, _dev(x0s), int(x0s.shape[0]), _dev(u)))
+        return u
+
+    def judge(self, x0s, u):
+        count = int(x0s.shape[0])
+        acc = np.zeros(count, dtype=np.int32)
+        vio, f, lb = np.zeros(count), np.zeros(count), np.zeros(count)
+        _check(load().cmpc_judge(self._h, _dev(x0s), _dev(u), count, _hp(acc), _hp(vio), _hp(f),
+                                 _hp(lb)))
+        return acc.astype(bool), vio, f, lb
+
+    def solve(self, x0s):
+        """(u device tensor, accepted bool array, report dict) for a batch of queries."""
+        import torch
+        count = int(x0s.shape[0])
+        u = torch.empty((count, self.problem.n), dtype=torch.float64, device=x0s.device)
+        acc = np.zeros(max(1, count), dtype=np.int32)
+        rep = SurrogateReport()
+        rc = load().cmpc_surrogate_solve(self._h, _dev(x0s), count, _dev(u), _hp(acc),
+                                         ctypes.byref(rep))
+        _check(rc, allow_positive=True)
+        return u, acc[:count].astype(bool), rep.as_dict()
+
+
+def tune_lookup(n, mx, precision=FP64):
+    """(quantum, persistent) of the tuning-table entry, or None."""
+    q, pers = ctypes.c_int(), ctypes.c_int()
+    rc = load().cmpc_tune_lookup(n, mx, precision, ctypes.byref(q), ctypes.byref(pers))
+    return (q.value, pers.value) if rc == 0 else None
+
+
+def tune_clear():
+    load().cmpc_tune_clear()
 
 
 def potrf(K, ld=None):

@@ -18,7 +18,7 @@ __global__ void add_vec_kernel(const double* __restrict__ a, const double* __res
   if (i < len) out[i] = a[i] + b[i];
 }
 
-static void free_problem(Problem* p) {
+void free_problem(Problem* p) {
   if (!p) return;
   if (p->stream) hipStreamSynchronize(p->stream);
   else hipDeviceSynchronize();
@@ -28,7 +28,7 @@ static void free_problem(Problem* p) {
                      &p->lam, &p->z,  &p->gv,   &p->pv,    &p->ps,   &p->plam, &p->pz,
                      &p->gpv, &p->rhs, &p->Dx,  &p->Du,    &p->wx,   &p->wu,   &p->gt,
                      &p->Hv, &p->tmpn, &p->tmpn2, &p->tmpmx, &p->norm_part, &p->alpha_part,
-                     &p->gt_part, &p->Wdiag, &p->ref_res, &p->ref_dlt, &p->ref_gt};
+                     &p->gt_part, &p->Wdiag, &p->ref_res, &p->ref_dlt, &p->ref_gt, &p->eqs};
   for (double** b : bufs) {
     if (*b) hipFree(*b);
     *b = nullptr;
@@ -61,7 +61,7 @@ static int upload(double** dst, const double* src, size_t len, hipStream_t s) {
   return 0;
 }
 
-static int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
+int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
   if (!desc || !out) {
     set_error("NULL argument");
     return CMPC_ERR_INVALID;
@@ -278,7 +278,7 @@ static int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
   return 0;
 }
 
-static int set_x0(Problem& p, const double* x0, int on_device) {
+int set_x0(Problem& p, const double* x0, int on_device) {
   if (!on_device) {
     for (int i = 0; i < p.ns; ++i)
       if (!std::isfinite(x0[i])) {
@@ -311,7 +311,7 @@ static int set_x0(Problem& p, const double* x0, int on_device) {
   return 0;
 }
 
-static int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
+int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
   if (!p.have_x0) {
     set_error("cmpc_set_x0 must be called before cmpc_solve");
     return CMPC_ERR_INVALID;
@@ -322,8 +322,18 @@ static int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
   }
   const int check = std::max(1, o.check_every);
   const bool prof = o.profile != 0;
-  const int mixed = o.precision == CMPC_FP32_SYRK ? 1 : 0;
-  if (mixed && launch_convert_gamma(p, CMPC_FP32_SYRK)) return CMPC_ERR_HIP;
+  // mixed: starting precision level of the SYRK (2 BF16, 1 FP32), 0 = plain FP64
+  const int mixed = o.precision == CMPC_BF16_SYRK ? 2 : (o.precision == CMPC_FP32_SYRK ? 1 : 0);
+  {
+    bool changed = false;
+    const int rc = ensure_plan(p, o.precision, &changed);
+    if (rc) return rc;
+  }
+  if (mixed) {
+    const int rc = launch_convert_gamma(p, o.precision);
+    if (rc) return rc;
+  }
+  p.eq_on = o.equilibrate < 0 ? mixed > 0 : o.equilibrate != 0;
   if (prof) {
     const size_t need = 4 * (size_t)(o.max_iter + 1);
     while (p.prof_ev.size() < need) {
@@ -374,6 +384,7 @@ static int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
     rc = launch_prep(p);
     if (!rc) rc = launch_mu_rhs(p);
     if (!rc) rc = launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K, e0, e1, mixed);
+    if (!rc && p.eq_on) rc = launch_equilibrate(p.stream, p.K, p.n, p.n, p.eqs, &p.st->done);
     if (!rc) rc = launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info,
                                &p.st->status, e2, e3, mixed ? &p.st->use_low : nullptr);
     if (!rc) rc = launch_step(p, mixed ? o.max_refine : 0);
@@ -424,10 +435,6 @@ static int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
 
 using namespace cmpc;
 
-struct cmpc_problem {
-  Problem* p;
-};
-
 extern "C" {
 
 void cmpc_default_options(cmpc_options* o) {
@@ -439,6 +446,7 @@ void cmpc_default_options(cmpc_options* o) {
   o->mu_switch = 1e-6;
   o->check_every = 2;
   o->profile = 0;
+  o->equilibrate = -1;
 }
 
 int cmpc_problem_info(const cmpc_problem* h, cmpc_info* info) {
@@ -473,12 +481,12 @@ int cmpc_problem_create(const cmpc_lq_desc* desc, void* stream, cmpc_problem** o
   Problem* p = nullptr;
   const int rc = create(desc, (hipStream_t)stream, &p);
   if (rc) return rc;
-  *out = new cmpc_problem{p};
+  *out = new cmpc_problem{p, false};
   return 0;
 }
 
 void cmpc_problem_destroy(cmpc_problem* h) {
-  if (!h) return;
+  if (!h || h->borrowed) return;  // instances of a batch belong to the batch
   free_problem(h->p);
   delete h;
 }
@@ -510,7 +518,8 @@ int cmpc_solve(cmpc_problem* h, const cmpc_options* opts, cmpc_result* res) {
   cmpc_options o;
   cmpc_default_options(&o);
   if (opts) o = *opts;
-  if (o.precision != CMPC_FP64 && o.precision != CMPC_FP32_SYRK) {
+  if (o.precision != CMPC_FP64 && o.precision != CMPC_FP32_SYRK &&
+      o.precision != CMPC_BF16_SYRK) {
     set_error("unsupported precision mode");
     return CMPC_ERR_INVALID;
   }
@@ -593,12 +602,12 @@ int cmpc_form_condensed(cmpc_problem* h, const double* sigma, double* K, int pre
     set_error("NULL argument");
     return CMPC_ERR_INVALID;
   }
-  if (precision != CMPC_FP64 && precision != CMPC_FP32_SYRK) {
+  if (precision != CMPC_FP64 && precision != CMPC_FP32_SYRK && precision != CMPC_BF16_SYRK) {
     set_error("unsupported precision");
     return CMPC_ERR_INVALID;
   }
   Problem& p = *h->p;
-  if (precision == CMPC_FP32_SYRK && launch_convert_gamma(p, precision)) return CMPC_ERR_HIP;
+  if (precision != CMPC_FP64 && launch_convert_gamma(p, precision)) return CMPC_ERR_HIP;
   CMPC_HIP(hipMemsetAsync(&p.st->done, 0, sizeof(int), p.stream));
   if (launch_sigma_fold(p, sigma)) return CMPC_ERR_HIP;
   if (launch_syrk(p, precision, p.Dx, p.H, p.Du, K)) return CMPC_ERR_HIP;

@@ -17,6 +17,15 @@ typedef short s8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWave = 64;
 
+typedef unsigned short bf16_t;  // bfloat16 bit pattern
+
+__device__ inline bf16_t f2bf(float x) {  // round to nearest, ties to even
+  unsigned int b = __float_as_uint(x);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (bf16_t)(b >> 16);
+}
+__device__ inline float bf2f(bf16_t h) { return __uint_as_float(((unsigned int)h) << 16); }
+
 // Thread-local message of the last error (set by the C ABI layer).
 void set_error(const std::string& msg);
 

@@ -256,11 +256,11 @@ __device__ inline void load_w(const double* __restrict__ Wk, Tile& W) {
   for (int e = threadIdx.x; e < 4096; e += 256) W[e >> 6][e & 63] = Wk[e];
 }
 
-// Pivot failure: a low-precision K (mixed modes) is retried in FP64 (done = 2 skips the
-// rest of the iteration); otherwise the breakdown is reported.
+// Pivot failure: a low-precision K (mixed modes) is formed again one precision level higher
+// (done = 2 skips the rest of the iteration); otherwise the breakdown is reported.
 __device__ inline void chol_fail(int col, int* done, int* info, int* status, int* lowflag) {
   if (lowflag != nullptr && *lowflag) {
-    *lowflag = 0;
+    *lowflag -= 1;  // one precision level up (BF16 -> FP32 -> FP64) and redo the iteration
     *done = 2;
     return;
   }
@@ -269,7 +269,7 @@ __device__ inline void chol_fail(int col, int* done, int* info, int* status, int
   *done = 1;
 }
 
-__global__ __launch_bounds__(256) void chol_first_kernel(double* __restrict__ K, int ld, int n,
+__device__ __forceinline__ void chol_first_body(int bid, double* __restrict__ K, int ld, int n,
                                                          double* __restrict__ Wall, int* done,
                                                          int* info, int* status, int* lowflag) {
   __shared__ Tile T, W;
@@ -287,10 +287,16 @@ __global__ __launch_bounds__(256) void chol_first_kernel(double* __restrict__ K,
   write_w(Wall, W);
 }
 
+__global__ __launch_bounds__(256) void chol_first_kernel(double* __restrict__ K, int ld, int n,
+                                                         double* __restrict__ Wall, int* done,
+                                                         int* info, int* status, int* lowflag) {
+  chol_first_body(blockIdx.x, K, ld, n, Wall, done, info, status, lowflag);
+}
+
 // Launch k: (A) the panel of block column k-1, L_i,k-1 = A_i,k-1 W_k-1' for i >= k, written
 // now because launch k-1 still read A_i,k-1 while forming its updates; (B) for k <= nt-2 the
 // trailing update with block column k, and the factorisation of the next pivot tile.
-__global__ __launch_bounds__(256) void chol_step_kernel(double* __restrict__ K, int ld, int n,
+__device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, int ld, int n,
                                                         int k, int nt, double* __restrict__ Wall,
                                                         int* done, int* info, int* status,
                                                         int* lowflag) {
@@ -300,7 +306,7 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double* __restrict__ K, 
   if (*done) return;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
   const int wr = wave >> 1, wc = wave & 1;
-  int b = blockIdx.x;
+  int b = bid;
   d4 acc[2][2];
   const int npanel = k >= 1 ? nt - k : 0;
   if (b < npanel) {  // (A) panel tile (k + b, k - 1)
@@ -369,6 +375,13 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double* __restrict__ K, 
   }
   write_tile_lower(K, ld, n, r0, c0, Xj, true);
   write_w(Wall + (long long)(k + 1) * 4096, Xi);
+}
+
+__global__ __launch_bounds__(256) void chol_step_kernel(double* __restrict__ K, int ld, int n,
+                                                        int k, int nt, double* __restrict__ Wall,
+                                                        int* done, int* info, int* status,
+                                                        int* lowflag) {
+  chol_step_body(blockIdx.x, K, ld, n, k, nt, Wall, done, info, status, lowflag);
 }
 
 int launch_potrf(hipStream_t s, double* K, int n, int ld, double* Wall, int* done, int* info,
@@ -440,7 +453,7 @@ __device__ inline void tile_mv64(const double* __restrict__ M, const double* u, 
   if (p == 0) v[r] = acc;
 }
 
-__global__ __launch_bounds__(256) void trsv_fwd_step_kernel(const double* __restrict__ L, int ld,
+__device__ __forceinline__ void trsv_fwd_step_body(int bid, const double* __restrict__ L, int ld,
                                                            int n, const double* __restrict__ Wall,
                                                            double* __restrict__ b,
                                                            double* __restrict__ y, int k,
@@ -452,8 +465,8 @@ __global__ __launch_bounds__(256) void trsv_fwd_step_kernel(const double* __rest
   __syncthreads();
   tile_mv64(Wall + (long long)k * 4096, bk, yk, false);
   __syncthreads();
-  if (blockIdx.x == 0 && t < 64 && k0 + t < n) y[k0 + t] = yk[t];
-  const int i0 = k0 + 64 * (1 + (int)blockIdx.x);
+  if (bid == 0 && t < 64 && k0 + t < n) y[k0 + t] = yk[t];
+  const int i0 = k0 + 64 * (1 + (int)bid);
   if (i0 >= n) return;
   // b_i -= L_ik y_k: 4 lanes per row of block i
   const int r = t >> 2, p = t & 3;
@@ -467,7 +480,15 @@ __global__ __launch_bounds__(256) void trsv_fwd_step_kernel(const double* __rest
   if (p == 0 && i0 + r < n) b[i0 + r] -= acc;
 }
 
-__global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const double* __restrict__ L, int ld,
+__global__ __launch_bounds__(256) void trsv_fwd_step_kernel(const double* __restrict__ L, int ld,
+                                                           int n, const double* __restrict__ Wall,
+                                                           double* __restrict__ b,
+                                                           double* __restrict__ y, int k,
+                                                           const int* __restrict__ done) {
+  trsv_fwd_step_body(blockIdx.x, L, ld, n, Wall, b, y, k, done);
+}
+
+__device__ __forceinline__ void trsv_bwd_step_body(int bid, const double* __restrict__ L, int ld,
                                                            int n, const double* __restrict__ Wall,
                                                            double* __restrict__ y,
                                                            double* __restrict__ x, int k,
@@ -479,8 +500,8 @@ __global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const double* __rest
   __syncthreads();
   tile_mv64(Wall + (long long)k * 4096, ykk, xk, true);
   __syncthreads();
-  if (blockIdx.x == 0 && t < 64 && k0 + t < n) x[k0 + t] = xk[t];
-  const int j = blockIdx.x;
+  if (bid == 0 && t < 64 && k0 + t < n) x[k0 + t] = xk[t];
+  const int j = bid;
   if (j >= k) return;
   // y_j -= L_kj' x_k: column c of block j gets sum_r L[k0 + r][64 j + c] x_k[r]
   const int c = t & 63, g = t >> 6;
@@ -493,13 +514,79 @@ __global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const double* __rest
   if (g == 0) y[64 * j + c] -= (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
 }
 
-// x = (L L')^-1 b.  work: n doubles of scratch (the reduced right-hand side); x may alias b
-// only if work differs from both.
+__global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const double* __restrict__ L, int ld,
+                                                           int n, const double* __restrict__ Wall,
+                                                           double* __restrict__ y,
+                                                           double* __restrict__ x, int k,
+                                                           const int* __restrict__ done) {
+  trsv_bwd_step_body(blockIdx.x, L, ld, n, Wall, y, x, k, done);
+}
+
+// dst = eq o src (eq == NULL: plain copy); returns at entry when *gate is set
+__global__ void scale_copy_kernel(double* __restrict__ dst, const double* __restrict__ src,
+                                  const double* __restrict__ eq, int n,
+                                  const int* __restrict__ gate) {
+  if (gate != nullptr && *gate) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = eq ? eq[i] * src[i] : src[i];
+}
+
+// Diagonal equilibration of the lower triangle of K before the factorisation (mixed
+// modes): eq_i = K_ii^-1/2 (1 if K_ii is not positive: the factorisation reports it), then
+// K_ij <- eq_i K_ij eq_j.  The solution of K p = r is p = S (S K S)^-1 S r, S = diag(eq).
+__device__ __forceinline__ void equil_diag_body(int bid, const double* __restrict__ K, int n,
+                                                int ld, double* __restrict__ eq,
+                                                const int* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  const int i = bid * 256 + threadIdx.x;
+  if (i < n) {
+    const double d = K[(long long)i * ld + i];
+    eq[i] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+  }
+}
+
+// one wavefront per row (4 rows per workgroup)
+__device__ __forceinline__ void equil_scale_body(int bid, double* __restrict__ K, int n, int ld,
+                                                 const double* __restrict__ eq,
+                                                 const int* __restrict__ done) {
+  if (done != nullptr && *done) return;
+  const int i = bid * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const double ei = eq[i];
+  double* row = K + (long long)i * ld;
+  for (int j = threadIdx.x & 63; j <= i; j += 64) row[j] *= ei * eq[j];
+}
+
+__global__ __launch_bounds__(256) void equil_diag_kernel(const double* __restrict__ K, int n,
+                                                         int ld, double* __restrict__ eq,
+                                                         const int* __restrict__ done) {
+  equil_diag_body(blockIdx.x, K, n, ld, eq, done);
+}
+__global__ __launch_bounds__(256) void equil_scale_kernel(double* __restrict__ K, int n, int ld,
+                                                          const double* __restrict__ eq,
+                                                          const int* __restrict__ done) {
+  equil_scale_body(blockIdx.x, K, n, ld, eq, done);
+}
+
+int launch_equilibrate(hipStream_t s, double* K, int n, int ld, double* eq, const int* done) {
+  hipLaunchKernelGGL(equil_diag_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, K, n, ld, eq,
+                     done);
+  CMPC_LAUNCH_CHECK();
+  hipLaunchKernelGGL(equil_scale_kernel, dim3(ceil_div(n, 4)), dim3(256), 0, s, K, n, ld, eq,
+                     done);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// x = (L L')^-1 b (eq != NULL: x = S (L L')^-1 S b).  work: n doubles of scratch (the reduced
+// right-hand side); x may alias b only if work differs from both.
 int launch_potrs(hipStream_t s, const double* L, int n, int ld, const double* Wall,
-                 const double* b, double* x, double* work, const int* done) {
+                 const double* b, double* x, double* work, const int* done, const double* eq) {
   const int nt = ceil_div(n, 64);
-  if (work != b) {
-    CMPC_HIP(hipMemcpyAsync(work, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  if (work != b || eq != nullptr) {
+    hipLaunchKernelGGL(scale_copy_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, work, b, eq, n,
+                       done);
+    CMPC_LAUNCH_CHECK();
   }
   for (int k = 0; k < nt; ++k) {  // forward: y (into x) from work
     hipLaunchKernelGGL(trsv_fwd_step_kernel, dim3(nt - k - 1 > 0 ? nt - k - 1 : 1), dim3(256), 0,
@@ -511,8 +598,118 @@ int launch_potrs(hipStream_t s, const double* L, int n, int ld, const double* Wa
                        x, work, k, done);
     CMPC_LAUNCH_CHECK();
   }
-  CMPC_HIP(hipMemcpyAsync(x, work, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(scale_copy_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, x, work, eq, n,
+                     done);
+  CMPC_LAUNCH_CHECK();
   return 0;
+}
+
+// ---- work-list forms (batches).  Step k of every instance runs in one launch; an instance
+// takes part in chol_step k when it has more than one tile column and k < nt, exactly as its
+// own launch sequence would.  The factorisation kernels take one item per workgroup (grid =
+// list length): their fully unrolled tile code does not fit the registers inside an item
+// loop, and one step's list is short.  which = 0: solve rhs -> pv (gate st->done); which = 1: solve
+// ref_res -> ref_dlt (gate st->ref_skip).  tmpn is the reduced right-hand side.
+__global__ __launch_bounds__(256) void chol_first_batch_kernel(const InstView* __restrict__ views,
+                                                               const WorkItem* __restrict__ items,
+                                                               int nitems, int mixed) {
+  if ((int)blockIdx.x >= nitems) return;
+  const WorkItem it = items[blockIdx.x];
+  const InstView& V = views[it.inst];
+  chol_first_body(it.local, V.K, V.n, V.n, V.Wdiag, &V.st->done, &V.st->info, &V.st->status,
+                  mixed ? &V.st->use_low : nullptr);
+}
+
+__global__ __launch_bounds__(256) void chol_step_batch_kernel(const InstView* __restrict__ views,
+                                                              const WorkItem* __restrict__ items,
+                                                              int nitems, int k, int mixed) {
+  if ((int)blockIdx.x >= nitems) return;
+  const WorkItem it = items[blockIdx.x];
+  const InstView& V = views[it.inst];
+  chol_step_body(it.local, V.K, V.n, V.n, k, V.nt, V.Wdiag, &V.st->done, &V.st->info,
+                 &V.st->status, mixed ? &V.st->use_low : nullptr);
+}
+
+// dir 0: tmpn = b (b = rhs or ref_res); dir 1: x = tmpn (x = pv or ref_dlt).  Items over
+// 256-entry blocks of n.
+__global__ __launch_bounds__(256) void potrs_copy_batch_kernel(const InstView* __restrict__ views,
+                                                               const WorkItem* __restrict__ items,
+                                                               int nitems, int which, int dir,
+                                                               int eq) {
+  CMPC_ITEMS_BEGIN
+  if (*gate_of(V, which) == 0) {
+    const int i = bid * 256 + threadIdx.x;
+    if (i < V.n) {
+      const double sc = eq ? V.eqs[i] : 1.0;
+      if (dir == 0)
+        V.tmpn[i] = eq ? sc * (which ? V.ref_res[i] : V.rhs[i]) : (which ? V.ref_res[i] : V.rhs[i]);
+      else
+        (which ? V.ref_dlt : V.pv)[i] = eq ? sc * V.tmpn[i] : V.tmpn[i];
+    }
+  }
+  CMPC_ITEMS_END
+}
+
+__global__ __launch_bounds__(256) void equil_diag_batch_kernel(const InstView* __restrict__ views,
+                                                               const WorkItem* __restrict__ items,
+                                                               int nitems) {
+  CMPC_ITEMS_BEGIN
+  equil_diag_body(bid, V.K, V.n, V.n, V.eqs, &V.st->done);
+  CMPC_ITEMS_END
+}
+
+__global__ __launch_bounds__(256) void equil_scale_batch_kernel(const InstView* __restrict__ views,
+                                                                const WorkItem* __restrict__ items,
+                                                                int nitems) {
+  CMPC_ITEMS_BEGIN
+  equil_scale_body(bid, V.K, V.n, V.n, V.eqs, &V.st->done);
+  CMPC_ITEMS_END
+}
+
+__global__ __launch_bounds__(256) void trsv_fwd_batch_kernel(const InstView* __restrict__ views,
+                                                             const WorkItem* __restrict__ items,
+                                                             int nitems, int k, int which) {
+  CMPC_ITEMS_BEGIN
+  trsv_fwd_step_body(bid, V.K, V.n, V.n, V.Wdiag, V.tmpn, which ? V.ref_dlt : V.pv, k,
+                     gate_of(V, which));
+  CMPC_ITEMS_END
+}
+
+__global__ __launch_bounds__(256) void trsv_bwd_batch_kernel(const InstView* __restrict__ views,
+                                                             const WorkItem* __restrict__ items,
+                                                             int nitems, int k, int which) {
+  CMPC_ITEMS_BEGIN
+  trsv_bwd_step_body(bid, V.K, V.n, V.n, V.Wdiag, which ? V.ref_dlt : V.pv, V.tmpn, k,
+                     gate_of(V, which));
+  CMPC_ITEMS_END
+}
+
+int launch_b_chol_first(const ListArg& L, int mixed) {
+  ListArg M = L;
+  M.persistent = 0;  // one item per workgroup
+  CMPC_LAUNCH_LIST(chol_first_batch_kernel, M, mixed);
+}
+int launch_b_chol_step(const ListArg& L, int k, int mixed) {
+  ListArg M = L;
+  M.persistent = 0;
+  CMPC_LAUNCH_LIST(chol_step_batch_kernel, M, k, mixed);
+}
+int launch_b_potrs_copy(const ListArg& L, int which, int dir, int eq) {
+  CMPC_LAUNCH_LIST(potrs_copy_batch_kernel, L, which, dir, eq);
+}
+static int launch_b_equil_diag(const ListArg& L) { CMPC_LAUNCH_LIST(equil_diag_batch_kernel, L); }
+static int launch_b_equil_scale(const ListArg& L) {
+  CMPC_LAUNCH_LIST(equil_scale_batch_kernel, L);
+}
+int launch_b_equilibrate(const ListArg& Ln256, const ListArg& Ln4) {
+  if (launch_b_equil_diag(Ln256)) return CMPC_ERR_HIP;
+  return launch_b_equil_scale(Ln4);
+}
+int launch_b_trsv_fwd(const ListArg& L, int k, int which) {
+  CMPC_LAUNCH_LIST(trsv_fwd_batch_kernel, L, k, which);
+}
+int launch_b_trsv_bwd(const ListArg& L, int k, int which) {
+  CMPC_LAUNCH_LIST(trsv_bwd_batch_kernel, L, k, which);
 }
 
 }  // namespace cmpc

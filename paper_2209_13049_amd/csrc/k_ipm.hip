@@ -20,7 +20,7 @@ constexpr double kTauMin = 0.99, kMuInit = 0.1, kSInitMin = 1e-2, kAlphaMin = 1e
 int ipm_alloc_work(Problem& p) {
   const size_t n = p.n, m = p.m, mx = p.mx;
   const size_t nmax = (size_t)(p.n > p.ns ? p.n : p.ns);
-  double** vecs_n[] = {&p.v, &p.pv, &p.rhs, &p.Du, &p.Hv, &p.h, &p.tmpn};
+  double** vecs_n[] = {&p.v, &p.pv, &p.rhs, &p.Du, &p.Hv, &p.h, &p.tmpn, &p.eqs};
   for (double** q : vecs_n) CMPC_HIP(hipMalloc(q, sizeof(double) * n));
   CMPC_HIP(hipMalloc(&p.tmpn2, sizeof(double) * nmax));
   double** vecs_r[] = {&p.ref_res, &p.ref_dlt, &p.ref_gt};
@@ -54,13 +54,13 @@ int ipm_alloc_work(Problem& p) {
 // Threads form TPC columns x RG row groups (TPC = 64, 128 or 256 by the row length), so
 // short rows of early blocks still keep every lane busy; row groups are summed in LDS.
 template <int NV>
-__global__ __launch_bounds__(256) void gamma_t_partial_kernel(
+__device__ __forceinline__ void gamma_t_partial_body(int bid, 
     const double* __restrict__ Gam, const long long* __restrict__ off,
     const double* __restrict__ W, long long wstride, double* __restrict__ part, int ns, int nu,
     int n, int rc, int cpb, const int* __restrict__ done) {
   __shared__ double red[NV][256];
   if (done != nullptr && *done) return;
-  const int chunk = blockIdx.x;
+  const int chunk = bid;
   const int t = chunk / cpb + 1, q = chunk - (t - 1) * cpb;
   const int len = t * nu;
   const int r0 = q * rc, r1 = min(ns, r0 + rc);
@@ -96,17 +96,25 @@ __global__ __launch_bounds__(256) void gamma_t_partial_kernel(
   }
 }
 
+template <int NV>
+__global__ __launch_bounds__(256) void gamma_t_partial_kernel(
+    const double* __restrict__ Gam, const long long* __restrict__ off,
+    const double* __restrict__ W, long long wstride, double* __restrict__ part, int ns, int nu,
+    int n, int rc, int cpb, const int* __restrict__ done) {
+  gamma_t_partial_body<NV>(blockIdx.x, Gam, off, W, wstride, part, ns, nu, n, rc, cpb, done);
+}
+
 // out[k][a] = sum over chunks whose block covers column a (fixed order): 16 columns x 16
 // chunk groups per workgroup.
 template <int NV>
-__global__ __launch_bounds__(256) void gamma_t_reduce_kernel(const double* __restrict__ part,
+__device__ __forceinline__ void gamma_t_reduce_body(int bid, const double* __restrict__ part,
                                                              double* __restrict__ out, int n,
                                                              int nu, int cpb, int nchunks,
                                                              const int* __restrict__ done) {
   __shared__ double sh[16][NV][16];
   if (done != nullptr && *done) return;
   const int l = threadIdx.x & 15, g = threadIdx.x >> 4;
-  const int a = blockIdx.x * 16 + l;
+  const int a = bid * 16 + l;
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
@@ -128,6 +136,14 @@ __global__ __launch_bounds__(256) void gamma_t_reduce_kernel(const double* __res
       out[(long long)k * n + a] = sum;
     }
   }
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void gamma_t_reduce_kernel(const double* __restrict__ part,
+                                                             double* __restrict__ out, int n,
+                                                             int nu, int cpb, int nchunks,
+                                                             const int* __restrict__ done) {
+  gamma_t_reduce_body<NV>(blockIdx.x, part, out, n, nu, cpb, nchunks, done);
 }
 
 int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int* done) {
@@ -152,13 +168,13 @@ int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int
 }
 
 // ---------------------------------------------------------------- y = Gamma x
-__global__ __launch_bounds__(256) void gamma_mv_kernel(const double* __restrict__ Gam,
+__device__ __forceinline__ void gamma_mv_body(int bid, const double* __restrict__ Gam,
                                                        const long long* __restrict__ off,
                                                        const double* __restrict__ x,
                                                        double* __restrict__ y, int ns, int nu,
                                                        int mx, const int* __restrict__ done) {
   if (done != nullptr && *done) return;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int r = bid * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (r >= mx) return;
   const int t = r / ns + 1, i = r - (t - 1) * ns;
@@ -170,6 +186,14 @@ __global__ __launch_bounds__(256) void gamma_mv_kernel(const double* __restrict_
   if (lane == 0) y[r] = acc;
 }
 
+__global__ __launch_bounds__(256) void gamma_mv_kernel(const double* __restrict__ Gam,
+                                                       const long long* __restrict__ off,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y, int ns, int nu,
+                                                       int mx, const int* __restrict__ done) {
+  gamma_mv_body(blockIdx.x, Gam, off, x, y, ns, nu, mx, done);
+}
+
 int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done) {
   hipLaunchKernelGGL(gamma_mv_kernel, dim3(ceil_div(p.mx, 4)), dim3(256), 0, p.stream, p.Gam,
                      p.goff, x, y, p.ns, p.nu, p.mx, done);
@@ -179,12 +203,12 @@ int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done) {
 
 // ---------------------------------------------------------------- y = H x (H symmetric)
 // One wavefront per row, lanes stride the (contiguous) row.
-__global__ __launch_bounds__(256) void hv_kernel(const double* __restrict__ H,
+__device__ __forceinline__ void hv_body(int bid, const double* __restrict__ H,
                                                  const double* __restrict__ x,
                                                  double* __restrict__ y, int n,
                                                  const int* __restrict__ done) {
   if (done != nullptr && *done) return;
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int c = bid * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= n) return;
   const double* row = H + (long long)c * n;
@@ -192,6 +216,13 @@ __global__ __launch_bounds__(256) void hv_kernel(const double* __restrict__ H,
   for (int j = lane; j < n; j += 64) acc = fma(row[j], x[j], acc);
   acc = wave_sum(acc);
   if (lane == 0) y[c] = acc;
+}
+
+__global__ __launch_bounds__(256) void hv_kernel(const double* __restrict__ H,
+                                                 const double* __restrict__ x,
+                                                 double* __restrict__ y, int n,
+                                                 const int* __restrict__ done) {
+  hv_body(blockIdx.x, H, x, y, n, done);
 }
 
 static int launch_hv(Problem& p, const double* x, double* y, const int* done) {
@@ -202,12 +233,12 @@ static int launch_hv(Problem& p, const double* x, double* y, const int* done) {
 }
 
 // ---------------------------------------------------------------- start point
-__global__ void ipm_init_kernel(const double* __restrict__ d, double* __restrict__ s,
+__device__ __forceinline__ void ipm_init_body(int bid, const double* __restrict__ d, double* __restrict__ s,
                                 double* __restrict__ lam, double* __restrict__ z,
                                 double* __restrict__ v, double* __restrict__ gv, int m, int n,
                                 int mx, IpmState* st, double tol, int max_iter, int low,
                                 double mu_switch) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long i = (long long)bid * blockDim.x + threadIdx.x;
   if (i < m) {
     const double di = d[i];
     if (isinf(di)) {
@@ -246,9 +277,17 @@ __global__ void ipm_init_kernel(const double* __restrict__ d, double* __restrict
   }
 }
 
+__global__ void ipm_init_kernel(const double* __restrict__ d, double* __restrict__ s,
+                                double* __restrict__ lam, double* __restrict__ z,
+                                double* __restrict__ v, double* __restrict__ gv, int m, int n,
+                                int mx, IpmState* st, double tol, int max_iter, int low,
+                                double mu_switch) {
+  ipm_init_body(blockIdx.x, d, s, lam, z, v, gv, m, n, mx, st, tol, max_iter, low, mu_switch);
+}
+
 int launch_ipm_init(Problem& p, const cmpc_options& o) {
   const long long len = p.m;
-  const int low = o.precision != CMPC_FP64 ? 1 : 0;
+  const int low = o.precision == CMPC_BF16_SYRK ? 2 : (o.precision == CMPC_FP32_SYRK ? 1 : 0);
   hipLaunchKernelGGL(ipm_init_kernel, dim3(ceil_div(len, 256)), dim3(256), 0, p.stream, p.d, p.s,
                      p.lam, p.z, p.v, p.gv, p.m, p.n, p.mx, p.st, o.tol, o.max_iter, low,
                      o.mu_switch);
@@ -278,7 +317,7 @@ __device__ inline PairRows pair_rows(int p, int mx, int n, const double* gv, con
 }
 
 // sigma, folded weights, Gamma' right-hand sides and the residual norms of the iterate.
-__global__ __launch_bounds__(256) void prep_kernel(
+__device__ __forceinline__ void prep_body(int bid, 
     const double* __restrict__ d, const double* __restrict__ s, const double* __restrict__ lam,
     const double* __restrict__ z, const double* __restrict__ gv, const double* __restrict__ v,
     double* __restrict__ Dx, double* __restrict__ Du, double* __restrict__ wx,
@@ -286,7 +325,7 @@ __global__ __launch_bounds__(256) void prep_kernel(
     const int* __restrict__ done) {
   __shared__ double sh[4];
   if (*done) return;
-  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int p = bid * 256 + threadIdx.x;
   double nr3 = 0.0, nlz = 0.0, szmax = 0.0, szmin = INFINITY, gap = 0.0;
   if (p < mx + n) {
     const PairRows pr = pair_rows(p, mx, n, gv, v);
@@ -332,13 +371,22 @@ __global__ __launch_bounds__(256) void prep_kernel(
   szmin = block_min256(szmin, sh);
   gap = block_sum256(gap, sh);
   if (threadIdx.x == 0) {
-    double* np = norm_part + 5LL * blockIdx.x;
+    double* np = norm_part + 5LL * bid;
     np[0] = nr3;
     np[1] = nlz;
     np[2] = szmax;
     np[3] = szmin;
     np[4] = gap;
   }
+}
+
+__global__ __launch_bounds__(256) void prep_kernel(
+    const double* __restrict__ d, const double* __restrict__ s, const double* __restrict__ lam,
+    const double* __restrict__ z, const double* __restrict__ gv, const double* __restrict__ v,
+    double* __restrict__ Dx, double* __restrict__ Du, double* __restrict__ wx,
+    double* __restrict__ wu, double* __restrict__ norm_part, int mx, int n,
+    const int* __restrict__ done) {
+  prep_body(blockIdx.x, d, s, lam, z, gv, v, Dx, Du, wx, wu, norm_part, mx, n, done);
 }
 
 int launch_prep(Problem& p) {
@@ -353,7 +401,7 @@ int launch_prep(Problem& p) {
 //   while E_mu <= kappa_eps mu: mu <- max(mu_min, min(kappa_mu mu, mu^theta_mu)),
 //   rhs = -r1 + J' r2 - J' Sigma r3 = -(H v + h) - mu J' S^-1 1 - J' Sigma r3.
 // fixed_mu != 0: no test and no update (used for a single step from a given iterate).
-__global__ __launch_bounds__(256) void mu_rhs_kernel(
+__device__ __forceinline__ void mu_rhs_body(int bid, 
     const double* __restrict__ Hv, const double* __restrict__ h, const double* __restrict__ gt,
     const double* __restrict__ wu, const double* __restrict__ norm_part, int nparts,
     const double* __restrict__ v, double* __restrict__ rhs, int n, IpmState* st, int fixed_mu) {
@@ -398,12 +446,14 @@ __global__ __launch_bounds__(256) void mu_rhs_kernel(
       if (threadIdx.x == 0) {
         st->status = CMPC_OK;
         st->done = 1;
+        st->ref_skip = 1;  // no refinement work in iterations queued after the stop
       }
       stop = true;
     } else if (st->iter >= st->max_iter) {
       if (threadIdx.x == 0) {
         st->status = CMPC_MAX_ITER;
         st->done = 1;
+        st->ref_skip = 1;
       }
       stop = true;
     } else {
@@ -428,6 +478,13 @@ __global__ __launch_bounds__(256) void mu_rhs_kernel(
   }
 }
 
+__global__ __launch_bounds__(256) void mu_rhs_kernel(
+    const double* __restrict__ Hv, const double* __restrict__ h, const double* __restrict__ gt,
+    const double* __restrict__ wu, const double* __restrict__ norm_part, int nparts,
+    const double* __restrict__ v, double* __restrict__ rhs, int n, IpmState* st, int fixed_mu) {
+  mu_rhs_body(blockIdx.x, Hv, h, gt, wu, norm_part, nparts, v, rhs, n, st, fixed_mu);
+}
+
 int launch_mu_rhs(Problem& p) {
   const int* done = &p.st->done;
   if (launch_gamma_t(p, p.wx, 3, p.gt, done)) return CMPC_ERR_HIP;
@@ -441,7 +498,7 @@ int launch_mu_rhs(Problem& p) {
 // ---------------------------------------------------------------- step recovery
 // p_s = -r3 - J p_v;  p_lambda = -r2 + Sigma r3 + Sigma J p_v = -r2 - Sigma p_s;
 // p_z = mu S^-1 1 - z - Sigma p_s;  per-block minima of the fraction-to-boundary ratios.
-__global__ __launch_bounds__(256) void step_kernel(
+__device__ __forceinline__ void step_body(int bid, 
     const double* __restrict__ d, const double* __restrict__ s, const double* __restrict__ lam,
     const double* __restrict__ z, const double* __restrict__ gv, const double* __restrict__ v,
     const double* __restrict__ gpv, const double* __restrict__ pv, double* __restrict__ ps,
@@ -450,7 +507,7 @@ __global__ __launch_bounds__(256) void step_kernel(
   __shared__ double sh[4];
   if (st->done) return;
   const double mu = st->mu, tau = st->tau;
-  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int p = bid * 256 + threadIdx.x;
   double amin = INFINITY, azmin = INFINITY;
   if (p < mx + n) {
     const PairRows pr = pair_rows(p, mx, n, gv, v);
@@ -482,14 +539,24 @@ __global__ __launch_bounds__(256) void step_kernel(
   amin = block_min256(amin, sh);
   azmin = block_min256(azmin, sh);
   if (threadIdx.x == 0) {
-    alpha_part[2LL * blockIdx.x] = amin;
-    alpha_part[2LL * blockIdx.x + 1] = azmin;
+    alpha_part[2LL * bid] = amin;
+    alpha_part[2LL * bid + 1] = azmin;
   }
+}
+
+__global__ __launch_bounds__(256) void step_kernel(
+    const double* __restrict__ d, const double* __restrict__ s, const double* __restrict__ lam,
+    const double* __restrict__ z, const double* __restrict__ gv, const double* __restrict__ v,
+    const double* __restrict__ gpv, const double* __restrict__ pv, double* __restrict__ ps,
+    double* __restrict__ plam, double* __restrict__ pz, double* __restrict__ alpha_part, int mx,
+    int n, const IpmState* st) {
+  step_body(blockIdx.x, d, s, lam, z, gv, v, gpv, pv, ps, plam, pz, alpha_part, mx, n, st);
 }
 
 int launch_step(Problem& p, int refine) {
   const int* done = &p.st->done;
-  if (launch_potrs(p.stream, p.K, p.n, p.n, p.Wdiag, p.rhs, p.pv, p.tmpn, done))
+  if (launch_potrs(p.stream, p.K, p.n, p.n, p.Wdiag, p.rhs, p.pv, p.tmpn, done,
+                   p.eq_on ? p.eqs : nullptr))
     return CMPC_ERR_HIP;
   for (int r = 0; r < refine; ++r)
     if (launch_refine_step(p)) return CMPC_ERR_HIP;
@@ -505,7 +572,7 @@ int launch_step(Problem& p, int refine) {
 // Every workgroup reduces the step-length partials itself (min is order independent), then
 // v += alpha p_v, s += alpha p_s, lambda += alpha p_lambda, z += alpha_z p_z, and z is
 // safeguarded into [mu/(kappa s), kappa mu/s].  apply == 0 only records alpha, alpha_z.
-__global__ __launch_bounds__(256) void update_kernel(
+__device__ __forceinline__ void update_body(int bid, 
     const double* __restrict__ d, double* __restrict__ s, double* __restrict__ lam,
     double* __restrict__ z, double* __restrict__ gv, double* __restrict__ v,
     const double* __restrict__ gpv, const double* __restrict__ pv, const double* __restrict__ ps,
@@ -521,19 +588,19 @@ __global__ __launch_bounds__(256) void update_kernel(
   const double alpha = block_min256(amin, sh);
   const double alpha_z = block_min256(azmin, sh);
   const double mu = st->mu;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bid == 0 && threadIdx.x == 0) {
     st->alpha = alpha;
     st->alpha_z = alpha_z;
   }
   if (!apply) return;
   if (alpha < kAlphaMin) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
       st->status = CMPC_SMALL_STEP;
       st->done = 1;
     }
     return;
   }
-  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int p = bid * 256 + threadIdx.x;
   if (p < mx + n) {
     long long rows[2];
     if (p < mx) {
@@ -559,7 +626,16 @@ __global__ __launch_bounds__(256) void update_kernel(
       z[r] = zn;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->iter += 1;
+  if (bid == 0 && threadIdx.x == 0) st->iter += 1;
+}
+
+__global__ __launch_bounds__(256) void update_kernel(
+    const double* __restrict__ d, double* __restrict__ s, double* __restrict__ lam,
+    double* __restrict__ z, double* __restrict__ gv, double* __restrict__ v,
+    const double* __restrict__ gpv, const double* __restrict__ pv, const double* __restrict__ ps,
+    const double* __restrict__ plam, const double* __restrict__ pz,
+    const double* __restrict__ alpha_part, int nparts, int mx, int n, IpmState* st, int apply) {
+  update_body(blockIdx.x, d, s, lam, z, gv, v, gpv, pv, ps, plam, pz, alpha_part, nparts, mx, n, st, apply);
 }
 
 // End-of-iteration flag for the host: 1 = still running, 2 = done, written with a
@@ -613,22 +689,32 @@ int launch_sigma_fold(Problem& p, const double* sigma) {
 // exact FP64 operator  K p = H p + Gamma'(D_x o Gamma p) + D_u o p:
 //   res = rhs - K p;  stop when |res| <= 1e-12 |rhs|;  else p += (L L')^-1 res.
 // A step that does not shrink |res| by 10x counts as not contracting; after two the SYRK
-// switches to FP64 from the next iteration on.  Every kernel is gated by st->ref_skip.
-__global__ void scale_by_kernel(double* __restrict__ x, const double* __restrict__ w, int len,
+// moves one precision level up (BF16 -> FP32 -> FP64) from the next iteration on.  Every kernel is gated by st->ref_skip.
+__device__ __forceinline__ void scale_by_body(int bid, double* __restrict__ x, const double* __restrict__ w, int len,
                                 const int* __restrict__ skip) {
   if (*skip) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bid * blockDim.x + threadIdx.x;
   if (i < len) x[i] *= w[i];
+}
+
+__global__ void scale_by_kernel(double* __restrict__ x, const double* __restrict__ w, int len,
+                                const int* __restrict__ skip) {
+  scale_by_body(blockIdx.x, x, w, len, skip);
+}
+
+__device__ __forceinline__ void axpy_gated_body(int bid, double* __restrict__ y, const double* __restrict__ x, int len,
+                                  const int* __restrict__ skip) {
+  if (*skip) return;
+  const int i = bid * blockDim.x + threadIdx.x;
+  if (i < len) y[i] += x[i];
 }
 
 __global__ void axpy_gated_kernel(double* __restrict__ y, const double* __restrict__ x, int len,
                                   const int* __restrict__ skip) {
-  if (*skip) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < len) y[i] += x[i];
+  axpy_gated_body(blockIdx.x, y, x, len, skip);
 }
 
-__global__ __launch_bounds__(256) void refine_check_kernel(
+__device__ __forceinline__ void refine_check_body(int bid, 
     const double* __restrict__ rhs, const double* __restrict__ Hp, const double* __restrict__ gtp,
     const double* __restrict__ Du, const double* __restrict__ p, double* __restrict__ res, int n,
     IpmState* st) {
@@ -649,12 +735,22 @@ __global__ __launch_bounds__(256) void refine_check_kernel(
     } else {
       if (nr > 0.1 * st->res_prev) {
         st->nonc += 1;
-        if (st->nonc >= 2) st->use_low = 0;
+        if (st->nonc >= 2 && st->use_low > 0) {  // next iteration one precision level up
+          st->use_low -= 1;
+          st->nonc = 0;
+        }
       }
       st->res_prev = nr;
       st->refine_steps += 1;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void refine_check_kernel(
+    const double* __restrict__ rhs, const double* __restrict__ Hp, const double* __restrict__ gtp,
+    const double* __restrict__ Du, const double* __restrict__ p, double* __restrict__ res, int n,
+    IpmState* st) {
+  refine_check_body(blockIdx.x, rhs, Hp, gtp, Du, p, res, n, st);
 }
 
 int launch_refine_step(Problem& p) {
@@ -668,7 +764,8 @@ int launch_refine_step(Problem& p) {
   hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(256), 0, p.stream, p.rhs, p.Hv, p.ref_gt,
                      p.Du, p.pv, p.ref_res, p.n, p.st);
   CMPC_LAUNCH_CHECK();
-  if (launch_potrs(p.stream, p.K, p.n, p.n, p.Wdiag, p.ref_res, p.ref_dlt, p.tmpn, skip))
+  if (launch_potrs(p.stream, p.K, p.n, p.n, p.Wdiag, p.ref_res, p.ref_dlt, p.tmpn, skip,
+                   p.eq_on ? p.eqs : nullptr))
     return CMPC_ERR_HIP;
   hipLaunchKernelGGL(axpy_gated_kernel, dim3(ceil_div(p.n, 256)), dim3(256), 0, p.stream, p.pv,
                      p.ref_dlt, p.n, skip);
@@ -688,6 +785,7 @@ __global__ void set_step_state_kernel(IpmState* st, double mu, double tau) {
 int launch_step_given(Problem& p, const double* v, const double* s, const double* lam,
                       const double* z, double mu, double tau) {
   const size_t m = p.m;
+  p.eq_on = false;  // plain FP64 step
   CMPC_HIP(hipMemcpyAsync(p.v, v, sizeof(double) * p.n, hipMemcpyDeviceToDevice, p.stream));
   CMPC_HIP(hipMemcpyAsync(p.s, s, sizeof(double) * m, hipMemcpyDeviceToDevice, p.stream));
   CMPC_HIP(hipMemcpyAsync(p.lam, lam, sizeof(double) * m, hipMemcpyDeviceToDevice, p.stream));
@@ -709,6 +807,202 @@ int launch_step_given(Problem& p, const double* v, const double* s, const double
   hipLaunchKernelGGL(update_kernel, dim3(1), dim3(256), 0, p.stream, p.d, p.s, p.lam, p.z, p.gv,
                      p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part, p.n_step_blocks, p.mx,
                      p.n, p.st, 0);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+
+// ================================================================ work-list (batched) forms
+// Each kernel walks a list of (instance, block) items; the per-item work is the body of the
+// single-instance kernel above with the same block decomposition, so every instance of a
+// batch computes bit for bit what it computes alone.  Workgroups loop over the list with
+// stride gridDim.x (persistent when the grid is smaller than the list); the barrier at the
+// top of the loop separates the LDS use of consecutive items.  Items of a finished instance
+// return at entry (their st->done is set).
+
+
+__global__ __launch_bounds__(256) void ipm_init_batch_kernel(const InstView* __restrict__ views,
+                                                             const WorkItem* __restrict__ items,
+                                                             int nitems, double tol, int max_iter,
+                                                             int low, double mu_switch) {
+  CMPC_ITEMS_BEGIN
+  ipm_init_body(bid, V.d, V.s, V.lam, V.z, V.v, V.gv, V.m, V.n, V.mx, V.st, tol, max_iter, low,
+                mu_switch);
+  CMPC_ITEMS_END
+}
+
+__global__ __launch_bounds__(256) void prep_batch_kernel(const InstView* __restrict__ views,
+                                                         const WorkItem* __restrict__ items,
+                                                         int nitems) {
+  CMPC_ITEMS_BEGIN
+  prep_body(bid, V.d, V.s, V.lam, V.z, V.gv, V.v, V.Dx, V.Du, V.wx, V.wu, V.norm_part, V.mx, V.n,
+            &V.st->done);
+  CMPC_ITEMS_END
+}
+
+// which = 0: Gamma' [wx] (3 vectors) -> gt under st->done; which = 1: Gamma' gpv -> ref_gt
+// under st->ref_skip.
+template <int NV>
+__global__ __launch_bounds__(256) void gamma_t_partial_batch_kernel(
+    const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems) {
+  CMPC_ITEMS_BEGIN
+  gamma_t_partial_body<NV>(bid, V.Gam, V.goff, NV == 3 ? V.wx : V.gpv, (long long)V.mx,
+                           V.gt_part, V.ns, V.nu, V.n, V.gt_rows, V.gt_cpb,
+                           gate_of(V, NV == 3 ? 0 : 1));
+  CMPC_ITEMS_END
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void gamma_t_reduce_batch_kernel(
+    const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems) {
+  CMPC_ITEMS_BEGIN
+  gamma_t_reduce_body<NV>(bid, V.gt_part, NV == 3 ? V.gt : V.ref_gt, V.n, V.nu, V.gt_cpb,
+                          V.gt_chunks, gate_of(V, NV == 3 ? 0 : 1));
+  CMPC_ITEMS_END
+}
+
+// gate 0: Hv = H v; gate 1: Hv = H pv (refinement)
+__global__ __launch_bounds__(256) void hv_batch_kernel(const InstView* __restrict__ views,
+                                                       const WorkItem* __restrict__ items,
+                                                       int nitems, int gate) {
+  CMPC_ITEMS_BEGIN
+  hv_body(bid, V.H, gate ? V.pv : V.v, V.Hv, V.n, gate_of(V, gate));
+  CMPC_ITEMS_END
+}
+
+__global__ __launch_bounds__(256) void mu_rhs_batch_kernel(const InstView* __restrict__ views,
+                                                           const WorkItem* __restrict__ items,
+                                                           int nitems) {
+  CMPC_ITEMS_BEGIN
+  mu_rhs_body(bid, V.Hv, V.h, V.gt, V.wu, V.norm_part, V.nblk, V.v, V.rhs, V.n, V.st, 0);
+  CMPC_ITEMS_END
+}
+
+// gpv = Gamma pv (gate 0: the step; gate 1: the refinement product)
+__global__ __launch_bounds__(256) void gamma_mv_batch_kernel(const InstView* __restrict__ views,
+                                                             const WorkItem* __restrict__ items,
+                                                             int nitems, int gate) {
+  CMPC_ITEMS_BEGIN
+  gamma_mv_body(bid, V.Gam, V.goff, V.pv, V.gpv, V.ns, V.nu, V.mx, gate_of(V, gate));
+  CMPC_ITEMS_END
+}
+
+__global__ __launch_bounds__(256) void step_batch_kernel(const InstView* __restrict__ views,
+                                                         const WorkItem* __restrict__ items,
+                                                         int nitems) {
+  CMPC_ITEMS_BEGIN
+  step_body(bid, V.d, V.s, V.lam, V.z, V.gv, V.v, V.gpv, V.pv, V.ps, V.plam, V.pz, V.alpha_part,
+            V.mx, V.n, V.st);
+  CMPC_ITEMS_END
+}
+
+__global__ __launch_bounds__(256) void update_batch_kernel(const InstView* __restrict__ views,
+                                                           const WorkItem* __restrict__ items,
+                                                           int nitems) {
+  CMPC_ITEMS_BEGIN
+  update_body(bid, V.d, V.s, V.lam, V.z, V.gv, V.v, V.gpv, V.pv, V.ps, V.plam, V.pz,
+              V.alpha_part, V.nblk, V.mx, V.n, V.st, 1);
+  CMPC_ITEMS_END
+}
+
+// refinement: gpv *= Dx (items over 256-row blocks of mx)
+__global__ __launch_bounds__(256) void scale_by_batch_kernel(const InstView* __restrict__ views,
+                                                             const WorkItem* __restrict__ items,
+                                                             int nitems) {
+  CMPC_ITEMS_BEGIN
+  scale_by_body(bid, V.gpv, V.Dx, V.mx, &V.st->ref_skip);
+  CMPC_ITEMS_END
+}
+
+__global__ __launch_bounds__(256) void refine_check_batch_kernel(
+    const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems) {
+  CMPC_ITEMS_BEGIN
+  refine_check_body(bid, V.rhs, V.Hv, V.ref_gt, V.Du, V.pv, V.ref_res, V.n, V.st);
+  CMPC_ITEMS_END
+}
+
+// refinement: pv += ref_dlt (items over 256-entry blocks of n)
+__global__ __launch_bounds__(256) void axpy_batch_kernel(const InstView* __restrict__ views,
+                                                         const WorkItem* __restrict__ items,
+                                                         int nitems) {
+  CMPC_ITEMS_BEGIN
+  axpy_gated_body(bid, V.pv, V.ref_dlt, V.n, &V.st->ref_skip);
+  CMPC_ITEMS_END
+}
+
+// End of a batch iteration: instances whose low-precision Cholesky failed (done = 2) are
+// re-armed, the running ones are counted, and count + 1 is stored with a system-scope
+// release into slot (iteration % ring) of the host-mapped ring.  One workgroup.
+__global__ __launch_bounds__(256) void publish_batch_kernel(const InstView* __restrict__ views,
+                                                            int count, int* __restrict__ iter,
+                                                            int* __restrict__ flags, int ring) {
+  __shared__ double sh[4];
+  double running = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) {
+    IpmState* st = views[i].st;
+    int d = st->done;
+    if (d == 2) {
+      st->done = 0;
+      d = 0;
+    }
+    running += d == 0 ? 1.0 : 0.0;
+  }
+  running = block_sum256(running, sh);
+  if (threadIdx.x == 0) {
+    const int k = *iter;
+    *iter = k + 1;
+    __hip_atomic_store(flags + (k % ring), (int)running + 1, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+__global__ void batch_reset_kernel(int* iter) { *iter = 0; }
+
+// Gather the per-instance states into one array (one device-to-host copy at the end).
+__global__ void gather_state_kernel(const InstView* __restrict__ views, int count,
+                                    IpmState* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = *views[i].st;
+}
+
+int launch_b_init(const ListArg& L, double tol, int max_iter, int low, double mu_switch) {
+  CMPC_LAUNCH_LIST(ipm_init_batch_kernel, L, tol, max_iter, low, mu_switch);
+}
+int launch_b_prep(const ListArg& L) { CMPC_LAUNCH_LIST(prep_batch_kernel, L); }
+int launch_b_gamma_t_partial(const ListArg& L, int nv) {
+  if (nv == 3) CMPC_LAUNCH_LIST(gamma_t_partial_batch_kernel<3>, L);
+  CMPC_LAUNCH_LIST(gamma_t_partial_batch_kernel<1>, L);
+}
+int launch_b_gamma_t_reduce(const ListArg& L, int nv) {
+  if (nv == 3) CMPC_LAUNCH_LIST(gamma_t_reduce_batch_kernel<3>, L);
+  CMPC_LAUNCH_LIST(gamma_t_reduce_batch_kernel<1>, L);
+}
+int launch_b_hv(const ListArg& L, int gate) { CMPC_LAUNCH_LIST(hv_batch_kernel, L, gate); }
+int launch_b_mu_rhs(const ListArg& L) { CMPC_LAUNCH_LIST(mu_rhs_batch_kernel, L); }
+int launch_b_gamma_mv(const ListArg& L, int gate) {
+  CMPC_LAUNCH_LIST(gamma_mv_batch_kernel, L, gate);
+}
+int launch_b_step(const ListArg& L) { CMPC_LAUNCH_LIST(step_batch_kernel, L); }
+int launch_b_update(const ListArg& L) { CMPC_LAUNCH_LIST(update_batch_kernel, L); }
+int launch_b_scale_by(const ListArg& L) { CMPC_LAUNCH_LIST(scale_by_batch_kernel, L); }
+int launch_b_refine_check(const ListArg& L) { CMPC_LAUNCH_LIST(refine_check_batch_kernel, L); }
+int launch_b_axpy(const ListArg& L) { CMPC_LAUNCH_LIST(axpy_batch_kernel, L); }
+
+int launch_b_publish(hipStream_t s, const InstView* views, int count, int* iter, int* flags,
+                     int ring) {
+  hipLaunchKernelGGL(publish_batch_kernel, dim3(1), dim3(256), 0, s, views, count, iter, flags,
+                     ring);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+int launch_b_reset(hipStream_t s, int* iter) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, s, iter);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+int launch_b_gather(hipStream_t s, const InstView* views, int count, IpmState* out) {
+  hipLaunchKernelGGL(gather_state_kernel, dim3(ceil_div(count, 64)), dim3(64), 0, s, views, count,
+                     out);
   CMPC_LAUNCH_CHECK();
   return 0;
 }

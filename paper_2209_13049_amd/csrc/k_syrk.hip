@@ -45,7 +45,7 @@ void syrk_free(SyrkPlan& sp) {
   sp = SyrkPlan();
 }
 
-int syrk_plan(Problem& p) {
+int syrk_plan(Problem& p, int quantum) {
   SyrkPlan& sp = p.syrk;
   const int ns = p.ns, nu = p.nu, N = p.N, n = p.n;
   sp.nt = ceil_div(n, 64);
@@ -72,7 +72,7 @@ int syrk_plan(Problem& p) {
     const double len = (double)t * nu;
     sp.flops_structural += (double)ns * len * (len + 1.0);
   }
-  int nwg = (int)(total / 12000.0);
+  int nwg = (int)(total / (double)quantum);
   nwg = std::max(8, std::min(512, nwg));
   nwg = (nwg + 7) / 8 * 8;
   const double target = total / nwg;
@@ -120,6 +120,7 @@ int syrk_plan(Problem& p) {
     for (int s = 0; s < sp.nslots; ++s) slots[fill[slot_tile[s]]++] = s;
   }
   sp.nwg = nwg;
+  sp.quantum = quantum;
   CMPC_HIP(hipMalloc(&sp.tiles, sizeof(int2) * tiles.size()));
   CMPC_HIP(hipMalloc(&sp.jobs, sizeof(SyrkJob) * std::max<size_t>(1, jobs.size())));
   CMPC_HIP(hipMalloc(&sp.wg_begin, sizeof(int) * (nwg + 1)));
@@ -159,6 +160,52 @@ struct MfmaOps<float> {
   // output element v of lane l sits at row 4 (l/16) + v, column l%16
   __device__ static inline int out_row(int lk, int v) { return 4 * lk + v; }
 };
+
+template <>
+struct MfmaOps<bf16_t> {
+  typedef f4 acc_t;
+  // v_mfma_f32_16x16x32_bf16: output element v of lane l sits at row 4 (l/16) + v, column l%16
+  __device__ static inline int out_row(int lk, int v) { return 4 * lk + v; }
+};
+
+// BF16 inputs: rows [r0, r1) in groups of 32 per v_mfma_f32_16x16x32_bf16, every wavefront
+// taking every 4th group; lane (li, lk) supplies rows 8 lk .. 8 lk + 7 of the group in
+// column 16 q + li.  The left operand is scaled by D in float32 and rounded to bfloat16,
+// products accumulate in float32.
+__device__ __forceinline__ void syrk_rows_bf16(f4 (&acc)[4][4], const bf16_t* __restrict__ base,
+                                               const double* __restrict__ Dt, int len, int a0,
+                                               int b0, int r0, int r1, int wave, int li, int lk) {
+  bool va[4], vb[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    va[q] = a0 + 16 * q + li < len;
+    vb[q] = b0 + 16 * q + li < len;
+  }
+  const int ngroups = (r1 - r0 + 31) >> 5;
+  for (int g = wave; g < ngroups; g += 4) {
+    const int rbase = r0 + 32 * g + 8 * lk;
+    s8 A[4], B[4];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int r = rbase + e;
+      const bool vr = r < r1;
+      const bf16_t* row = base + (long long)(vr ? r : r0) * len;
+      const float d = vr ? (float)Dt[r] : 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bf16_t ga = (vr && va[q]) ? row[a0 + 16 * q + li] : (bf16_t)0;
+        const bf16_t gb = (vr && vb[q]) ? row[b0 + 16 * q + li] : (bf16_t)0;
+        A[q][e] = (short)f2bf(bf2f(ga) * d);
+        B[q][e] = (short)gb;
+      }
+    }
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ib], B[jb], acc[ib][jb], 0, 0, 0);
+  }
+}
 
 // Rows [r0, r1) of one row block against one tile.  Every wavefront takes every 4th group
 // of 4 rows; operands are loaded straight into the MFMA lane layout (lane l: column l%16 of
@@ -210,7 +257,7 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
 }
 
 template <typename TIn>
-__global__ __launch_bounds__(256, 2) void syrk_streamk_kernel(
+__device__ __forceinline__ void syrk_streamk_body(int bid, 
     const TIn* __restrict__ Gam, const long long* __restrict__ off, const double* __restrict__ D,
     const SyrkJob* __restrict__ jobs, const int* __restrict__ wg_begin,
     const int2* __restrict__ tiles, double* __restrict__ partials, int ns, int nu, int nwg,
@@ -219,9 +266,8 @@ __global__ __launch_bounds__(256, 2) void syrk_streamk_kernel(
   typedef typename Ops::acc_t acc_t;
   __shared__ double red[64 * 64];
   if (done != nullptr && *done) return;
-  if (lowflag != nullptr && (*lowflag != 0) != (want_low != 0)) return;
-  const int per = nwg >> 3;
-  const int wg = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (lowflag != nullptr && *lowflag != want_low) return;
+  const int wg = bid;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   acc_t acc[4][4];
@@ -238,7 +284,10 @@ __global__ __launch_bounds__(256, 2) void syrk_streamk_kernel(
     const int len = job.t * nu;
     const TIn* __restrict__ base = Gam + off[job.t - 1];
     const double* __restrict__ Dt = D + (long long)(job.t - 1) * ns;
-    syrk_rows<TIn>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
+    if constexpr (sizeof(TIn) == 2)
+      syrk_rows_bf16(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
+    else
+      syrk_rows<TIn>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
     if (job.slot >= 0) {
       __syncthreads();
       for (int w = 0; w < 4; ++w) {
@@ -266,15 +315,24 @@ __global__ __launch_bounds__(256, 2) void syrk_streamk_kernel(
   }
 }
 
+template <typename TIn>
+__global__ __launch_bounds__(256, 2) void syrk_streamk_kernel(
+    const TIn* __restrict__ Gam, const long long* __restrict__ off, const double* __restrict__ D,
+    const SyrkJob* __restrict__ jobs, const int* __restrict__ wg_begin,
+    const int2* __restrict__ tiles, double* __restrict__ partials, int ns, int nu, int nwg,
+    const int* __restrict__ done, const int* __restrict__ lowflag, int want_low) {
+  syrk_streamk_body<TIn>((blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3), Gam, off, D, jobs, wg_begin, tiles, partials, ns, nu, nwg, done, lowflag, want_low);
+}
+
 // K(lower) = Hb(lower) + sum of the tile's partial slots (fixed order) + diag(Ddiag).
 // 16 workgroups per tile, one element per thread.
-__global__ __launch_bounds__(256) void syrk_finish_kernel(
+__device__ __forceinline__ void syrk_finish_body(int bid, 
     const double* __restrict__ partials, const int* __restrict__ slot_begin,
     const int* __restrict__ slots, const int2* __restrict__ tiles, const double* __restrict__ Hb,
     const double* __restrict__ Ddiag, double* __restrict__ K, int n, const int* __restrict__ done) {
   if (done != nullptr && *done) return;
-  const int tile = blockIdx.x >> 4;
-  const int e = ((blockIdx.x & 15) << 8) + threadIdx.x;
+  const int tile = bid >> 4;
+  const int e = ((bid & 15) << 8) + threadIdx.x;
   const int2 tl = tiles[tile];
   const int gi = tl.x * 64 + (e >> 6), gj = tl.y * 64 + (e & 63);
   if (gi >= n || gj > gi) return;
@@ -286,32 +344,81 @@ __global__ __launch_bounds__(256) void syrk_finish_kernel(
   K[(long long)gi * n + gj] = val;
 }
 
+__global__ __launch_bounds__(256) void syrk_finish_kernel(
+    const double* __restrict__ partials, const int* __restrict__ slot_begin,
+    const int* __restrict__ slots, const int2* __restrict__ tiles, const double* __restrict__ Hb,
+    const double* __restrict__ Ddiag, double* __restrict__ K, int n, const int* __restrict__ done) {
+  syrk_finish_body(blockIdx.x, partials, slot_begin, slots, tiles, Hb, Ddiag, K, n, done);
+}
+
+// ---- work-list forms (batches): one item = one stream-K workgroup (or one finish block) of
+// one instance, with that instance's own plan, so the result is the single-instance one.
+// mixed != 0: the item runs only when the instance's precision level st->use_low equals
+// want_low (2 = BF16, 1 = FP32, 0 = FP64).
+template <typename TIn>
+__global__ __launch_bounds__(256, 2) void syrk_batch_kernel(const InstView* __restrict__ views,
+                                                            const WorkItem* __restrict__ items,
+                                                            int nitems, int mixed, int want_low) {
+  CMPC_ITEMS_BEGIN
+  const TIn* G = sizeof(TIn) == 8 ? (const TIn*)V.Gam
+                                   : (sizeof(TIn) == 4 ? (const TIn*)V.Gam32 : (const TIn*)V.Gam16);
+  syrk_streamk_body<TIn>(bid, G, V.goff, V.Dx, V.jobs, V.wg_begin, V.tiles, V.partials, V.ns,
+                         V.nu, V.syrk_nwg, &V.st->done, mixed ? &V.st->use_low : nullptr,
+                         want_low);
+  CMPC_ITEMS_END
+}
+
+__global__ __launch_bounds__(256) void syrk_finish_batch_kernel(const InstView* __restrict__ views,
+                                                                const WorkItem* __restrict__ items,
+                                                                int nitems) {
+  CMPC_ITEMS_BEGIN
+  syrk_finish_body(bid, V.partials, V.slot_begin, V.slots, V.tiles, V.H, V.Du, V.K, V.n,
+                   &V.st->done);
+  CMPC_ITEMS_END
+}
+
+template __global__ void syrk_batch_kernel<double>(const InstView*, const WorkItem*, int, int, int);
+template __global__ void syrk_batch_kernel<float>(const InstView*, const WorkItem*, int, int, int);
+template __global__ void syrk_batch_kernel<bf16_t>(const InstView*, const WorkItem*, int, int, int);
+
+int launch_b_syrk(const ListArg& L, int level, int mixed, int want_low) {
+  if (level == 2) CMPC_LAUNCH_LIST(syrk_batch_kernel<bf16_t>, L, mixed, want_low);
+  if (level == 1) CMPC_LAUNCH_LIST(syrk_batch_kernel<float>, L, mixed, want_low);
+  CMPC_LAUNCH_LIST(syrk_batch_kernel<double>, L, mixed, want_low);
+}
+int launch_b_finish(const ListArg& L) { CMPC_LAUNCH_LIST(syrk_finish_batch_kernel, L); }
+
 int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hbase,
                 const double* Ddiag, double* K, hipEvent_t ev_start, hipEvent_t ev_stop,
                 int mixed) {
   SyrkPlan& sp = p.syrk;
   const int* done = p.st ? &p.st->done : nullptr;
   const int* low = mixed ? &p.st->use_low : nullptr;
-  const bool want32 = mixed || precision == CMPC_FP32_SYRK;
-  const bool want64 = mixed || precision != CMPC_FP32_SYRK;
-  if (want32) {
-    if (p.Gam32 == nullptr) {
-      set_error("FP32 copy of Gamma not allocated");
-      return CMPC_ERR_INVALID;
-    }
-    hipExtLaunchKernelGGL(syrk_streamk_kernel<float>, dim3(sp.nwg), dim3(256), 0, p.stream,
-                          ev_start, want64 ? nullptr : ev_stop, 0, (const float*)p.Gam32,
-                          (const long long*)p.goff, Drow, (const SyrkJob*)sp.jobs,
-                          (const int*)sp.wg_begin, (const int2*)sp.tiles, sp.partials, p.ns, p.nu,
-                          sp.nwg, done, low, 1);
-    CMPC_LAUNCH_CHECK();
+  // levels queued: mixed -> every level from the starting one down to FP64, each gated on
+  // st->use_low; otherwise only the requested precision
+  const int top = mixed ? mixed : (precision == CMPC_BF16_SYRK ? 2 : (precision == CMPC_FP32_SYRK ? 1 : 0));
+  const int bottom = mixed ? 0 : top;
+  if ((top >= 1 && bottom <= 1 && p.Gam32 == nullptr) || (top == 2 && p.Gam16 == nullptr)) {
+    set_error("low-precision copy of Gamma not allocated");
+    return CMPC_ERR_INVALID;
   }
-  if (want64) {
-    hipExtLaunchKernelGGL(syrk_streamk_kernel<double>, dim3(sp.nwg), dim3(256), 0, p.stream,
-                          want32 ? nullptr : ev_start, ev_stop, 0, (const double*)p.Gam,
-                          (const long long*)p.goff, Drow, (const SyrkJob*)sp.jobs,
-                          (const int*)sp.wg_begin, (const int2*)sp.tiles, sp.partials, p.ns, p.nu,
-                          sp.nwg, done, low, 0);
+  for (int lev = top; lev >= bottom; --lev) {
+    hipEvent_t e0 = lev == top ? ev_start : nullptr, e1 = lev == bottom ? ev_stop : nullptr;
+    if (lev == 2)
+      hipExtLaunchKernelGGL(syrk_streamk_kernel<bf16_t>, dim3(sp.nwg), dim3(256), 0, p.stream, e0,
+                            e1, 0, (const bf16_t*)p.Gam16, (const long long*)p.goff, Drow,
+                            (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
+                            (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done, low, 2);
+    else if (lev == 1)
+      hipExtLaunchKernelGGL(syrk_streamk_kernel<float>, dim3(sp.nwg), dim3(256), 0, p.stream, e0,
+                            e1, 0, (const float*)p.Gam32, (const long long*)p.goff, Drow,
+                            (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
+                            (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done, low, 1);
+    else
+      hipExtLaunchKernelGGL(syrk_streamk_kernel<double>, dim3(sp.nwg), dim3(256), 0, p.stream, e0,
+                            e1, 0, (const double*)p.Gam, (const long long*)p.goff, Drow,
+                            (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
+                            (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done, low, 0);
     CMPC_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(syrk_finish_kernel, dim3(sp.ntiles * 16), dim3(256), 0, p.stream, sp.partials,
@@ -330,9 +437,27 @@ __global__ void convert_f32_kernel(const double* __restrict__ in, float* __restr
   if (i < len) out[i] = (float)in[i];
 }
 
-// Low-precision copy of the packed Gamma for the mixed-precision SYRK (made once).
+__global__ void convert_bf16_kernel(const double* __restrict__ in, bf16_t* __restrict__ out,
+                                    long long len) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) out[i] = f2bf((float)in[i]);
+}
+
+// Low-precision copies of the packed Gamma for the mixed-precision SYRK (made once):
+// CMPC_FP32_SYRK makes the float copy, CMPC_BF16_SYRK both (a BF16 solve may step to FP32).
 int launch_convert_gamma(Problem& p, int precision) {
   const long long nnz = p.off[p.N];
+  if (precision == CMPC_BF16_SYRK && p.Gam16 == nullptr) {
+    if (hipMalloc(&p.Gam16, sizeof(bf16_t) * (size_t)nnz) != hipSuccess) {
+      p.Gam16 = nullptr;
+      set_error("out of device memory (BF16 Gamma)");
+      return CMPC_ERR_NOMEM;
+    }
+    hipLaunchKernelGGL(convert_bf16_kernel, dim3(ceil_div(nnz, 256)), dim3(256), 0, p.stream,
+                       p.Gam, (bf16_t*)p.Gam16, nnz);
+    CMPC_LAUNCH_CHECK();
+  }
+  if (precision == CMPC_BF16_SYRK) precision = CMPC_FP32_SYRK;
   if (precision == CMPC_FP32_SYRK && p.Gam32 == nullptr) {
     if (hipMalloc(&p.Gam32, sizeof(float) * (size_t)nnz) != hipSuccess) {
       p.Gam32 = nullptr;

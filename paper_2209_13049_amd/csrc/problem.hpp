@@ -18,13 +18,13 @@ struct IpmState {
   int done;      // nonzero: every later kernel of the solve returns at entry
   int info;      // Cholesky: 1-based failing column
   int max_iter;
-  int use_low;   // mixed modes: current SYRK is the low-precision one
+  int use_low;   // mixed modes: precision level of the SYRK (2 BF16, 1 FP32, 0 FP64)
   int switch_iter;
   int refine_steps;
   int nonc;      // mixed modes: refinement failures so far
   int x0_flag;   // device x0 check: 1 = outside the bounds, 2 = not finite
   int ref_skip;  // mixed modes: nonzero = no (more) refinement in this iteration
-  int mixed;     // the solve started with a low-precision SYRK
+  int mixed;     // starting precision level of the solve (0 = plain FP64)
   double mu_switch, res_prev;
 };
 
@@ -39,6 +39,7 @@ struct SyrkJob {
 
 struct SyrkPlan {
   int nt = 0, ntiles = 0, nwg = 0, nslots = 0;
+  int quantum = 0;               // target work per workgroup (row-tile units, see syrk_plan)
   int2* tiles = nullptr;         // (I, J) tile coordinates, I >= J, 64 x 64 tiles
   SyrkJob* jobs = nullptr;
   int* wg_begin = nullptr;       // nwg + 1
@@ -64,6 +65,7 @@ struct Problem {
   unsigned short* Gam16 = nullptr;  // BF16 copy (mixed modes)
   double *H = nullptr;           // n x n, full symmetric
   double *Wdiag = nullptr;       // inverses of the diagonal 64 x 64 factor tiles
+  double *eqs = nullptr;         // equilibration scales diag(K)^-1/2 (n)
   double *K = nullptr;           // n x n workspace (lower triangle = condensed matrix / factor)
   int *a_rowptr = nullptr, *a_col = nullptr;  // CSR copy of A when it is sparse
   double* a_val = nullptr;
@@ -79,6 +81,7 @@ struct Problem {
   double *ref_res = nullptr, *ref_dlt = nullptr, *ref_gt = nullptr;  // refinement vectors (n)
   double *norm_part = nullptr, *alpha_part = nullptr, *gt_part = nullptr;
   int n_prep_blocks = 0, n_step_blocks = 0, gt_chunks = 0, gt_rows = 0;
+  bool eq_on = false;               // this solve factors the equilibrated S K S
   IpmState* st = nullptr;
   SyrkPlan syrk;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -87,6 +90,117 @@ struct Problem {
   int* dflags = nullptr;            // device alias of hflags
   std::vector<double> xl_host, xu_host;
 };
+
+// ---- host driver (capi.hip) and tuning table (batch.hip) ----
+int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out);
+void free_problem(Problem* p);
+int set_x0(Problem& p, const double* x0, int on_device);
+int solve(Problem& p, const cmpc_options& o, cmpc_result* res);
+// Rebuild the SYRK plan if the tuning table holds another work quantum for
+// (n, mx, precision); *changed tells whether it did.
+int ensure_plan(Problem& p, int precision, bool* changed);
+
+// ---- batches ----
+// One instance as the work-list kernels see it (an array of these lives in device memory).
+struct InstView {
+  int ns, nu, N, n, mx, m;
+  int nblk;                      // 256-pair blocks of the vector kernels
+  int gt_rows, gt_cpb, gt_chunks;
+  int nt;                        // ceil(n / 64)
+  int syrk_nwg;
+  const double* Gam;
+  const float* Gam32;
+  const bf16_t* Gam16;
+  const long long* goff;
+  const double *H, *d, *h;
+  double *K, *Wdiag, *eqs;
+  double *v, *s, *lam, *z, *gv, *pv, *ps, *plam, *pz, *gpv;
+  double *rhs, *Dx, *Du, *wx, *wu, *gt, *Hv, *tmpn;
+  double *ref_res, *ref_dlt, *ref_gt;
+  double *norm_part, *alpha_part, *gt_part;
+  IpmState* st;
+  const SyrkJob* jobs;
+  const int* wg_begin;
+  const int2* tiles;
+  double* partials;
+  const int *slot_begin, *slots;
+};
+
+// One entry of a work list: block `local` of instance `inst`.
+struct WorkItem {
+  int inst, local;
+};
+
+// Gate of a work-list kernel: 0 = the solve (st->done), 1 = the refinement (st->ref_skip).
+__device__ inline const int* gate_of(const InstView& V, int gate) {
+  return gate ? &V.st->ref_skip : &V.st->done;
+}
+
+// Loop of a work-list kernel over items[0, nitems) with stride gridDim.x (persistent when
+// the grid is smaller than the list).  The barrier at the top separates the LDS use of
+// consecutive items; V is the item's instance and bid its block index in that instance.
+#define CMPC_ITEMS_BEGIN                                                  \
+  for (int w_ = blockIdx.x; w_ < nitems; w_ += gridDim.x) {              \
+    __syncthreads();                                                      \
+    const WorkItem it_ = items[w_];                                       \
+    const InstView& V = views[it_.inst];                                  \
+    const int bid = it_.local;
+#define CMPC_ITEMS_END }
+
+// A work list as handed to a launcher: items [0, count) of the batch's device list; grid =
+// count, or (persistent) at most the resident workgroups of the kernel on `cus` CUs.
+struct ListArg {
+  const InstView* views;
+  const WorkItem* items;
+  int count;
+  int persistent;
+  int cus;
+  hipStream_t stream;
+};
+int occupancy_per_cu(const void* kernel);  // resident 256-thread workgroups per CU
+inline int grid_for(const ListArg& L, const void* kernel) {
+  if (!L.persistent) return L.count;
+  const int cap = occupancy_per_cu(kernel) * L.cus;
+  return L.count < cap ? L.count : (cap > 0 ? cap : 1);
+}
+
+// Launch a work-list kernel (arguments: views, items, count, then the extra ones) and return.
+#define CMPC_LAUNCH_LIST(kernel, L, ...)                                                   \
+  do {                                                                                     \
+    if ((L).count > 0) {                                                                   \
+      hipLaunchKernelGGL(kernel, dim3(grid_for((L), (const void*)(kernel))), dim3(256), 0, \
+                         (L).stream, (L).views, (L).items, (L).count, ##__VA_ARGS__);      \
+      CMPC_LAUNCH_CHECK();                                                                 \
+    }                                                                                      \
+    return 0;                                                                              \
+  } while (0)
+
+// ---- work-list launchers (k_ipm.hip, k_syrk.hip, k_chol.hip); a list of length 0 launches
+// nothing.  gate / which: 0 = the solve, 1 = the refinement (see gate_of).
+int launch_b_init(const ListArg& L, double tol, int max_iter, int low, double mu_switch);
+int launch_b_prep(const ListArg& L);
+int launch_b_gamma_t_partial(const ListArg& L, int nv);
+int launch_b_gamma_t_reduce(const ListArg& L, int nv);
+int launch_b_hv(const ListArg& L, int gate);
+int launch_b_mu_rhs(const ListArg& L);
+int launch_b_gamma_mv(const ListArg& L, int gate);
+int launch_b_step(const ListArg& L);
+int launch_b_update(const ListArg& L);
+int launch_b_scale_by(const ListArg& L);
+int launch_b_refine_check(const ListArg& L);
+int launch_b_axpy(const ListArg& L);
+int launch_b_publish(hipStream_t s, const InstView* views, int count, int* iter, int* flags,
+                     int ring);
+int launch_b_reset(hipStream_t s, int* iter);
+int launch_b_gather(hipStream_t s, const InstView* views, int count, IpmState* out);
+int launch_b_syrk(const ListArg& L, int fp32, int mixed, int want_low);
+int launch_b_finish(const ListArg& L);
+int launch_b_equilibrate(const ListArg& Ln256, const ListArg& Ln4);
+int launch_b_chol_first(const ListArg& L, int mixed);
+int launch_b_chol_step(const ListArg& L, int k, int mixed);
+int launch_b_potrs_copy(const ListArg& L, int which, int dir, int eq);
+int launch_b_trsv_fwd(const ListArg& L, int k, int which);
+int launch_b_trsv_bwd(const ListArg& L, int k, int which);
 
 // ---- setup kernels (k_build.hip) ----
 int launch_gemm_f64(hipStream_t s, int M, int Nc, int Kd, double alpha, const double* A,
@@ -104,7 +218,8 @@ int launch_mirror_lower(hipStream_t s, double* H, int n);
 int launch_dense_gamma(Problem& p, double* dense);
 
 // ---- SYRK (k_syrk.hip) ----
-int syrk_plan(Problem& p);
+constexpr int kSyrkQuantumDefault = 12000;
+int syrk_plan(Problem& p, int quantum = kSyrkQuantumDefault);
 void syrk_free(SyrkPlan& sp);
 // K(lower) = Hbase(lower) + Gamma' diag(Drow) Gamma + diag(Ddiag)   (Ddiag may be NULL)
 // ev_start / ev_stop (optional): timing events attached to the stream-K kernel's dispatch.
@@ -123,9 +238,13 @@ int launch_convert_gamma(Problem& p, int precision);
 int launch_potrf(hipStream_t s, double* K, int n, int ld, double* Wall, int* done, int* info,
                  int* status, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
                  int* lowflag = nullptr);
-// x = (L L')^-1 b with n doubles of scratch `work` (distinct from b and x); x may alias b
+// x = (L L')^-1 b with n doubles of scratch `work` (distinct from b and x); x may alias b.
+// eq != NULL: L is the factor of the equilibrated S K S (S = diag(eq)) and x = S (L L')^-1 S b.
 int launch_potrs(hipStream_t s, const double* L, int n, int ld, const double* Wall,
-                 const double* b, double* x, double* work, const int* done);
+                 const double* b, double* x, double* work, const int* done,
+                 const double* eq = nullptr);
+// Diagonal equilibration in place: eq_i = K_ii^-1/2, K_ij <- eq_i K_ij eq_j (lower triangle).
+int launch_equilibrate(hipStream_t s, double* K, int n, int ld, double* eq, const int* done);
 int launch_tri_inv(hipStream_t s, const double* L, int n, int ld, double* Wall);
 
 // ---- IPM vector kernels (k_ipm.hip) ----
@@ -144,3 +263,10 @@ int launch_step_given(Problem& p, const double* v, const double* s, const double
                       const double* z, double mu, double tau);
 
 }  // namespace cmpc
+
+// Handle behind the C ABI's cmpc_problem; instances of a batch are borrowed (the batch owns
+// them and cmpc_problem_destroy leaves them alone).
+struct cmpc_problem {
+  cmpc::Problem* p;
+  bool borrowed;
+};

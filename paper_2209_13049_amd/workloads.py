@@ -215,3 +215,40 @@ def smooth_x0(ns: int, count: int, seed: int = 4, amp: float = 0.4, modes: int =
     scale = np.max(np.abs(f), axis=1)
     scale[scale == 0] = 1.0
     return _f64(rho[:, None] * amp * f / scale[:, None])
+
+
+# ---------------------------------------------------------------- surrogate inputs
+def mlp_widths(ns: int, n_out: int, hidden: int = 1024, depth: int = 4) -> list:
+    return [ns] + [hidden] * depth + [n_out]
+
+
+def mlp_init(widths, seed: int = 5) -> np.ndarray:
+    """Packed float32 initial parameters W_1, b_1, ..., W_L, b_L (W_l row-major, d_l x d_(l-1)),
+    every entry ~ U(-1/sqrt(d_(l-1)), 1/sqrt(d_(l-1)))."""
+    rng = np.random.default_rng([seed, len(widths)])
+    parts = []
+    for l in range(1, len(widths)):
+        bound = 1.0 / np.sqrt(widths[l - 1])
+        parts.append(rng.uniform(-bound, bound, size=widths[l] * widths[l - 1]))
+        parts.append(rng.uniform(-bound, bound, size=widths[l]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def unpack_params(flat, widths) -> list:
+    """[(W_l, b_l)] float64 views of a packed parameter vector."""
+    out, off = [], 0
+    flat = np.asarray(flat, dtype=np.float64)
+    for l in range(1, len(widths)):
+        nW = widths[l] * widths[l - 1]
+        W = flat[off:off + nW].reshape(widths[l], widths[l - 1])
+        off += nW
+        b = flat[off:off + widths[l]]
+        off += widths[l]
+        out.append((W, b))
+    return out
+
+
+def shuffle_order(count: int, epochs: int, seed: int = 6) -> np.ndarray:
+    """Row order of each training epoch (epochs x count, int32)."""
+    rng = np.random.default_rng([seed, count])
+    return np.concatenate([rng.permutation(count) for _ in range(epochs)]).astype(np.int32)

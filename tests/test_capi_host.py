@@ -46,7 +46,7 @@ def test_library_loads_and_binds(built):
     # pure host functions can be called without a GPU
     o = condmpc.default_options()
     assert o.tol == 1e-8 and o.max_iter == 200 and o.precision == condmpc.FP64
-    assert o.check_every == 2 and o.profile == 0
+    assert o.check_every == 2 and o.profile == 0 and o.equilibrate == -1
     assert condmpc.status_str(condmpc.ERR_CHOLESKY) == "Cholesky breakdown"
     assert condmpc.status_str(condmpc.OK) == "converged"
 
@@ -70,6 +70,9 @@ def test_struct_layouts_match_header():
     assert fields("cmpc_options") == [f for f, _ in condmpc.Options._fields_]
     assert fields("cmpc_result") == [f for f, _ in condmpc.Result._fields_]
     assert fields("cmpc_info") == [f for f, _ in condmpc.Info._fields_]
+    assert fields("cmpc_tune_report") == [f for f, _ in condmpc.TuneReport._fields_]
+    assert fields("cmpc_train_opts") == [f for f, _ in condmpc.TrainOpts._fields_]
+    assert fields("cmpc_surrogate_report") == [f for f, _ in condmpc.SurrogateReport._fields_]
 
 
 def test_null_arguments_are_rejected_without_gpu(built):
@@ -120,3 +123,43 @@ def test_invalid_problem_data_rejected_on_host(built, case, code):
     rc = condmpc.load().cmpc_problem_create(ctypes.byref(d), None, ctypes.byref(h))
     assert rc == code, condmpc.load().cmpc_last_error()
     assert not h.value
+
+
+def test_batch_calls_without_gpu(built):
+    lib = condmpc.load()
+    h = ctypes.c_void_p()
+    assert lib.cmpc_batch_create(0, None, None, None, ctypes.byref(h)) == condmpc.ERR_INVALID
+    assert not h.value
+    assert lib.cmpc_batch_size(None) == 0
+    assert lib.cmpc_batch_instance(None, 0) is None
+    assert lib.cmpc_batch_solve(None, None, None) == condmpc.ERR_INVALID
+    assert lib.cmpc_batch_tune(None, condmpc.FP64, None) == condmpc.ERR_INVALID
+    lib.cmpc_tune_clear()
+    assert lib.cmpc_tune_lookup(64, 100, condmpc.FP64, None, None) == 1
+    assert condmpc.tune_lookup(64, 100) is None
+
+
+def test_batch_rejects_invalid_instance_on_host(built):
+    """Validation of the first instance happens before any device work."""
+    import numpy as np
+    A = 0.5 * np.eye(3)
+    A[0, 1] = np.inf
+    d, keep = _desc(A=A)
+    descs = (condmpc.LQDesc * 2)(d, d)
+    h = ctypes.c_void_p()
+    rc = condmpc.load().cmpc_batch_create(2, descs, None, None, ctypes.byref(h))
+    assert rc == condmpc.ERR_NONFINITE
+    assert b"instance 0" in condmpc.load().cmpc_last_error()
+    assert not h.value
+
+
+def test_surrogate_calls_without_gpu(built):
+    lib = condmpc.load()
+    o = condmpc.default_train_opts()
+    assert o.batch == 512 and o.epochs == 20 and abs(o.lr - 1e-3) < 1e-9
+    h = ctypes.c_void_p()
+    assert lib.cmpc_mlp_create(None, 64, 2, condmpc.MLP_BF16, None, ctypes.byref(h)) == \
+        condmpc.ERR_INVALID
+    assert lib.cmpc_mlp_param_count(None) == 0
+    assert lib.cmpc_mlp_train(None, None, None, 0, None, None, None) == condmpc.ERR_INVALID
+    assert lib.cmpc_surrogate_solve(None, None, 0, None, None, None) == condmpc.ERR_INVALID

@@ -293,3 +293,51 @@ def test_mixed_precision_solve(problems, name):
     assert abs(res["iters"] - ref.iters) <= 2
     u, _ = gp.solution(with_x=False)
     assert rel_err(u, ref.v) <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["small", "ragged", "wide"])
+def test_condensed_matrix_bf16(problems, name):
+    """The BF16-MFMA SYRK (Gamma rounded to bfloat16, D-scaled operand rounded again, float32
+    accumulation; FP64 H and diagonal): each product carries <= 3 roundings of 2^-8, so the
+    error is within 2e-2 of the largest entry, and nonzero."""
+    p, gp, red = problems[name]
+    rng = np.random.default_rng(6)
+    sig = rng.uniform(0.01, 10.0, red.d.size)
+    full, _ = _sigma_full(gp, red, sig)
+    K = torch.zeros(gp.n, gp.n, dtype=torch.float64, device=DEV)
+    gp.form_condensed(gpu(full), K, precision=condmpc.BF16_SYRK)
+    K_ref = oracle.condensed_matrix(red, sig)
+    lo = np.tril_indices(gp.n)
+    err = rel_err(K.cpu().numpy()[lo], K_ref[lo])
+    print(f"[bf16] {name}: K rel err {err:.2e}", flush=True)
+    assert 0 < err <= 2e-2
+
+
+@pytest.mark.parametrize("name", ["small", "ragged", "wide", "tight", "inf", "genq"])
+def test_bf16_mixed_solve(problems, name):
+    """BF16 start, staged FP32 -> FP64, equilibrated FP64 Cholesky and FP64 refinement: the
+    FP64 bar on the objective and the KKT residuals."""
+    p, gp, red = problems[name]
+    ref = oracle.solve(p, red=red)
+    res = gp.solve(precision=condmpc.BF16_SYRK)
+    print(f"[bf16 mixed] {name}: iters {res['iters']} (oracle {ref.iters}) switch "
+          f"{res['precision_switch_iter']} refine {res['refine_steps']} obj rel "
+          f"{abs(res['obj'] - ref.obj) / max(1, abs(ref.obj)):.2e}", flush=True)
+    assert res["status"] == condmpc.OK
+    assert abs(res["obj"] - ref.obj) <= 1e-8 * max(1.0, abs(ref.obj))
+    assert res["primal_res"] <= 1e-8 and res["dual_res"] <= 1e-8 and res["compl_res"] <= 1e-8
+    assert abs(res["iters"] - ref.iters) <= 4
+    u, _ = gp.solution(with_x=False)
+    assert rel_err(u, ref.v) <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["small", "tight", "wide"])
+def test_equilibrated_fp64_solve(problems, name):
+    """Factoring S K S (S = diag(K)^-1/2) instead of K changes only rounding: same status and
+    iteration count as the oracle, objective within 1e-8."""
+    p, gp, red = problems[name]
+    ref = oracle.solve(p, red=red)
+    res = gp.solve(equilibrate=1)
+    assert res["status"] == condmpc.OK and res["iters"] == ref.iters
+    assert abs(res["obj"] - ref.obj) <= 1e-8 * max(1.0, abs(ref.obj))
+    assert res["primal_res"] <= 1e-8 and res["dual_res"] <= 1e-8
