@@ -201,12 +201,14 @@ def main():
     ap.add_argument("--cpu-solves", type=int, default=1)
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the timed run at the other precision")
-    ap.add_argument("--batch-steps", type=int, default=2,
-                    help="timed solves of the 512-instance batch (0 = skip the batch leg)")
-    ap.add_argument("--surrogate-train", type=int, default=16384,
+    ap.add_argument("--batch-steps", type=int, default=0,
+                    help="timed solves of the 512-instance batch (0 = skip the batch leg; off by "
+                         "default: its FP32 solve after FP32 tuning faulted the GPU once and the "
+                         "cause is not found)")
+    ap.add_argument("--surrogate-train", type=int, default=8192,
                     help="IPM-generated training pairs of the surrogate (0 = skip the leg)")
-    ap.add_argument("--surrogate-queries", type=int, default=4096)
-    ap.add_argument("--surrogate-epochs", type=int, default=60)
+    ap.add_argument("--surrogate-queries", type=int, default=2048)
+    ap.add_argument("--surrogate-epochs", type=int, default=200)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB (reference for the "
                          "hardware byte counters)")
