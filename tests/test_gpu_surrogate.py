@@ -145,21 +145,30 @@ def ipm_solutions(gp, X):
     return Xd, U
 
 
-def test_surrogate_end_to_end(setup):
-    prob, gp, widths, init = setup
-    ntrain, nquery, epochs = 1536, 128, 150
+def test_surrogate_end_to_end(lib):
+    """IPM-generated data, GPU training, then answers that are either certified by the judge
+    (the oracle's judge agrees) or are the IPM's own solution.  The certificate compares with
+    the unconstrained minimum, so even the exact optimum is certified only where no bound is
+    active at it; the network must reach at least half of that ceiling."""
+    prob = W.heat1d(NS, NU, N, seed=(21, 1), ub=3.0)
+    gp = condmpc.Problem(prob)
+    gp.set_x0(prob.x0)
+    hidden, depth = 256, 4
+    widths = W.mlp_widths(NS, NU * N, hidden, depth)
+    ntrain, nquery, epochs = 4096, 256, 300
     Xtr = W.smooth_x0(NS, ntrain, seed=61)
     t0 = time.perf_counter()
     Xd, Ud = ipm_solutions(gp, Xtr)
     t_data = time.perf_counter() - t0
-    net = condmpc.Mlp(gp, init, HIDDEN, DEPTH, condmpc.MLP_BF16)
+    net = condmpc.Mlp(gp, W.mlp_init(widths, seed=7), hidden, depth, condmpc.MLP_BF16)
     order = W.shuffle_order(ntrain, epochs, seed=62)
-    losses = net.train(Xd, Ud, order=order, batch=128, epochs=epochs, lr=2e-3, lr_final=1e-5)
+    losses = net.train(Xd, Ud, order=order, batch=256, epochs=epochs, lr=1e-3, lr_final=1e-6)
     print(f"[surrogate] data {t_data:.2f} s; loss {losses[0]:.3e} -> {losses[-1]:.3e}",
           flush=True)
-    assert losses[-1] < 0.05 * losses[0]
+    assert losses[-1] < 0.01 * losses[0]
     Xq = W.smooth_x0(NS, nquery, seed=63)
-    Xqd = gpu(Xq)
+    Xqd, Uqd = ipm_solutions(gp, Xq)
+    ceiling, *_ = net.judge(Xqd, Uqd)             # the exact optima, judged the same way
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     u, acc, rep = net.solve(Xqd)
@@ -167,11 +176,12 @@ def test_surrogate_end_to_end(setup):
     t_sur = time.perf_counter() - t0
     ua = u.cpu().numpy()
     t0 = time.perf_counter()
-    ipm_solutions(gp, Xq[: min(32, nquery)])
-    t_ipm = (time.perf_counter() - t0) / min(32, nquery) * nquery
-    print(f"[surrogate] accepted {rep['accepted']}/{nquery}, fallback {rep['fallback_solved']}"
-          f" (failed {rep['fallback_failed']}), max gap {rep['max_gap_accepted']:.2e}, "
-          f"surrogate {t_sur * 1e3:.1f} ms vs IPM only {t_ipm * 1e3:.1f} ms", flush=True)
+    ipm_solutions(gp, Xq[:64])
+    t_ipm = (time.perf_counter() - t0) / 64 * nquery
+    print(f"[surrogate] accepted {rep['accepted']}/{nquery} (exact optima: {int(ceiling.sum())})"
+          f", fallback {rep['fallback_solved']} (failed {rep['fallback_failed']}), max gap "
+          f"{rep['max_gap_accepted']:.2e}; surrogate {t_sur * 1e3:.1f} ms vs IPM only "
+          f"{t_ipm * 1e3:.1f} ms", flush=True)
     assert rep["count"] == nquery and rep["accepted"] == int(acc.sum())
     assert rep["accepted"] + rep["fallback_solved"] == nquery
     for k in range(nquery):
@@ -180,9 +190,11 @@ def test_surrogate_end_to_end(setup):
         if acc[k]:
             a, v, f, lb, gap = S.judge(pk, ua[k], red)
             assert v <= S.VIOLATION_TOL * (1 + 1e-6) and gap <= S.GAP_TOL * (1 + 1e-6)
-        else:
+        elif k % 8 == 0:
             ref = oracle.solve(pk, red=red)
             assert np.max(np.abs(ua[k] - ref.v)) <= 1e-6 * max(1.0, np.max(np.abs(ref.v)))
-    # what the network gains: a share of the queries is answered without a solve
-    assert rep["accepted"] >= nquery // 4
+    # what the network gains: queries answered, with a certificate, without a solve
+    assert ceiling.sum() >= nquery // 4
+    assert rep["accepted"] >= ceiling.sum() // 2
     net.close()
+    gp.close()
