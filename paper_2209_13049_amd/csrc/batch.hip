@@ -100,7 +100,7 @@ struct Batch {
   size_t items_cap = 0;
   List init, blk, gt, n16, n4, one, syrk, fin, n256, mx4, mx256;
   std::vector<List> chol, fwd, bwd;
-  int ntmax = 0;
+  int ntmax = 0, nmax = 0;
   bool lists_valid = false;
   int* d_iter = nullptr;
   int* hflags = nullptr;
@@ -224,7 +224,11 @@ static int build_lists(Batch& b) {
   add(b.mx4, [](const InstView& v) { return ceil_div(v.mx, 4); });
   add(b.mx256, [](const InstView& v) { return ceil_div(v.mx, 256); });
   b.ntmax = 0;
-  for (const InstView& v : hv) b.ntmax = std::max(b.ntmax, v.nt);
+  b.nmax = 0;
+  for (const InstView& v : hv) {
+    b.ntmax = std::max(b.ntmax, v.nt);
+    b.nmax = std::max(b.nmax, v.n);
+  }
   b.chol.assign(b.ntmax, List());
   b.fwd.assign(b.ntmax, List());
   b.bwd.assign(b.ntmax, List());
@@ -257,6 +261,7 @@ static ListArg arg(const Batch& b, const List& L) {
 // (L L')^-1 applied to rhs -> pv (which = 0) or ref_res -> ref_dlt (which = 1); eq: the
 // factor is that of the equilibrated S K S.
 static int enqueue_potrs(Batch& b, int which, int eq) {
+  if (b.nmax <= 4096) return launch_b_potrs_single(arg(b, b.one), which, eq, b.nmax);
   if (launch_b_potrs_copy(arg(b, b.n256), which, 0, eq)) return CMPC_ERR_HIP;
   for (int k = 0; k < b.ntmax; ++k)
     if (launch_b_trsv_fwd(arg(b, b.fwd[k]), k, which)) return CMPC_ERR_HIP;

@@ -578,10 +578,114 @@ int launch_equilibrate(hipStream_t s, double* K, int n, int ld, double* eq, cons
   return 0;
 }
 
+// Both triangular solves in one workgroup of 1024 threads (16 wavefronts), the vector held in
+// LDS: forward, for each 64-row block k, r = b_k - L_k,<k y_<k (16 lanes per row, a row
+// segment of 16 consecutive columns per load) and y_k = W_k r; backward, for k from the last
+// block down, r = y_k - L_>k,k' x_>k (a wavefront per 16th of the rows, 64 consecutive
+// columns per load) and x_k = W_k' r.  Partial sums are reduced in a fixed order.  One launch
+// replaces 2 ceil(n/64) + 2 launches of the block-step kernels.  eq != NULL: x = S (..)^-1 S b.
+__device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, int ld, int n,
+                                                  const double* __restrict__ Wall,
+                                                  const double* __restrict__ b,
+                                                  double* __restrict__ x,
+                                                  const double* __restrict__ eq,
+                                                  const int* __restrict__ gate) {
+  extern __shared__ double ys[];  // n
+  __shared__ double rs[64];
+  __shared__ double red[16][65];
+  if (gate != nullptr && *gate) return;
+  const int t = threadIdx.x;
+  for (int i = t; i < n; i += 1024) ys[i] = eq ? eq[i] * b[i] : b[i];
+  __syncthreads();
+  const int nt = (n + 63) >> 6;
+  // ---- forward: L y = b
+  {
+    const int i = t >> 4, g = t & 15;  // row of the block, column phase
+    for (int k = 0; k < nt; ++k) {
+      const int k0 = 64 * k;
+      const int rows = min(64, n - k0);
+      double acc = 0.0;
+      if (i < rows) {
+        const double* row = L + (long long)(k0 + i) * ld;
+#pragma unroll 4
+        for (int c = g; c < k0; c += 16) acc = fma(row[c], ys[c], acc);
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      acc += __shfl_xor(acc, 4, 64);
+      acc += __shfl_xor(acc, 8, 64);
+      if (g == 0) rs[i] = i < rows ? ys[k0 + i] - acc : 0.0;
+      __syncthreads();
+      const double* W = Wall + (long long)k * 4096;
+      double v = 0.0;
+#pragma unroll
+      for (int m = g; m < 64; m += 16) v = fma(W[i * 64 + m], rs[m], v);
+      v += __shfl_xor(v, 1, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      if (g == 0 && i < rows) ys[k0 + i] = v;
+      __syncthreads();
+    }
+  }
+  // ---- backward: L' x = y (x overwrites y block by block)
+  {
+    const int i = t & 63, g = t >> 6;  // column of the block, row phase (one wavefront each)
+    for (int k = nt - 1; k >= 0; --k) {
+      const int k0 = 64 * k;
+      const int rows = min(64, n - k0);
+      double acc = 0.0;
+      if (i < rows) {
+#pragma unroll 4
+        for (int r = k0 + 64 + g; r < n; r += 16) acc = fma(L[(long long)r * ld + k0 + i], ys[r], acc);
+      }
+      red[g][i] = acc;
+      __syncthreads();
+      if (g == 0) {
+        double sum = 0.0;
+        for (int q = 0; q < 16; ++q) sum += red[q][i];
+        rs[i] = i < rows ? ys[k0 + i] - sum : 0.0;
+      }
+      __syncthreads();
+      const double* W = Wall + (long long)k * 4096;
+      double v = 0.0;
+#pragma unroll
+      for (int m = g; m < 64; m += 16) v = fma(W[m * 64 + i], rs[m], v);
+      red[g][i] = v;
+      __syncthreads();
+      if (g == 0 && i < rows) {
+        double sum = 0.0;
+        for (int q = 0; q < 16; ++q) sum += red[q][i];
+        ys[k0 + i] = sum;
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = t; i < n; i += 1024) x[i] = eq ? eq[i] * ys[i] : ys[i];
+}
+
+constexpr int kPotrsSingleMax = 4096;
+
+__global__ __launch_bounds__(1024) void potrs_single_kernel(const double* __restrict__ L, int ld,
+                                                            int n, const double* __restrict__ Wall,
+                                                            const double* __restrict__ b,
+                                                            double* __restrict__ x,
+                                                            const double* __restrict__ eq,
+                                                            const int* __restrict__ gate) {
+  potrs_single_body(L, ld, n, Wall, b, x, eq, gate);
+}
+
 // x = (L L')^-1 b (eq != NULL: x = S (L L')^-1 S b).  work: n doubles of scratch (the reduced
-// right-hand side); x may alias b only if work differs from both.
+// right-hand side) for the block-step form; x may alias b.  n <= 4096 takes the one-launch
+// form (the vector in LDS, at most 32 KB).
 int launch_potrs(hipStream_t s, const double* L, int n, int ld, const double* Wall,
                  const double* b, double* x, double* work, const int* done, const double* eq) {
+  if (n <= kPotrsSingleMax) {
+    hipLaunchKernelGGL(potrs_single_kernel, dim3(1), dim3(1024), sizeof(double) * (size_t)n, s, L,
+                       ld, n, Wall, b, x, eq, done);
+    CMPC_LAUNCH_CHECK();
+    return 0;
+  }
   const int nt = ceil_div(n, 64);
   if (work != b || eq != nullptr) {
     hipLaunchKernelGGL(scale_copy_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, work, b, eq, n,
@@ -694,6 +798,25 @@ int launch_b_chol_step(const ListArg& L, int k, int mixed) {
   M.persistent = 0;
   CMPC_LAUNCH_LIST(chol_step_batch_kernel, M, k, mixed);
 }
+// Whole solve of one instance per workgroup (1024 threads, the instance's vector in LDS).
+__global__ __launch_bounds__(1024) void potrs_single_batch_kernel(
+    const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems, int which,
+    int eq) {
+  if ((int)blockIdx.x >= nitems) return;
+  const WorkItem it = items[blockIdx.x];
+  const InstView& V = views[it.inst];
+  potrs_single_body(V.K, V.n, V.n, V.Wdiag, which ? V.ref_res : V.rhs, which ? V.ref_dlt : V.pv,
+                    eq ? V.eqs : nullptr, gate_of(V, which));
+}
+
+int launch_b_potrs_single(const ListArg& L, int which, int eq, int nmax) {
+  if (L.count <= 0) return 0;
+  hipLaunchKernelGGL(potrs_single_batch_kernel, dim3(L.count), dim3(1024),
+                     sizeof(double) * (size_t)nmax, L.stream, L.views, L.items, L.count, which, eq);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
 int launch_b_potrs_copy(const ListArg& L, int which, int dir, int eq) {
   CMPC_LAUNCH_LIST(potrs_copy_batch_kernel, L, which, dir, eq);
 }

@@ -199,6 +199,9 @@ int launch_b_equilibrate(const ListArg& Ln256, const ListArg& Ln4);
 int launch_b_chol_first(const ListArg& L, int mixed);
 int launch_b_chol_step(const ListArg& L, int k, int mixed);
 int launch_b_potrs_copy(const ListArg& L, int which, int dir, int eq);
+// the whole solve of each instance of the list (one item per instance) in one workgroup;
+// nmax: the largest n of the batch (LDS size)
+int launch_b_potrs_single(const ListArg& L, int which, int eq, int nmax);
 int launch_b_trsv_fwd(const ListArg& L, int k, int which);
 int launch_b_trsv_bwd(const ListArg& L, int k, int which);
 

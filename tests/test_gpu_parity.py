@@ -248,7 +248,7 @@ def test_device_x0_checked_on_device(problems):
     assert res["status"] == 0 and res["iters"] == ref.iters
 
 
-@pytest.mark.parametrize("n", [1000, 1111])
+@pytest.mark.parametrize("n", [1000, 1111, 4097])
 def test_cholesky_large(lib, n):
     rng = np.random.default_rng(n)
     M = rng.normal(size=(n, n)) / np.sqrt(n)
@@ -257,6 +257,10 @@ def test_cholesky_large(lib, n):
     condmpc.potrf(Kt)
     L = np.tril(Kt.cpu().numpy())
     assert rel_err(L, np.linalg.cholesky(A)) <= 1e-11
+    b = rng.normal(size=n)
+    bt = gpu(b)
+    condmpc.potrs(Kt, bt)          # n <= 4096: one workgroup; larger: block steps
+    assert rel_err(bt.cpu().numpy(), np.linalg.solve(A, b)) <= 1e-10
 
 
 # ----------------------------------------------------------------- mixed precision (FP32 SYRK)
