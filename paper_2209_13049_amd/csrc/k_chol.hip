@@ -30,11 +30,21 @@ __device__ inline double recip(double x) {
   return fma(r, e, r);
 }
 
+// All 16 loads of a thread are issued before the first LDS store, so their latencies overlap
+// (a load-store-load loop waits for each load in turn).
 __device__ inline void load_tile(const double* __restrict__ K, int ld, int n, int r0, int c0,
                                  Tile& T) {
-  for (int e = threadIdx.x; e < 4096; e += 256) {
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
     const int i = e >> 6, j = e & 63;
-    T[i][j] = (r0 + i < n && c0 + j < n) ? K[(long long)(r0 + i) * ld + c0 + j] : 0.0;
+    v[q] = (r0 + i < n && c0 + j < n) ? K[(long long)(r0 + i) * ld + c0 + j] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    T[e >> 6][e & 63] = v[q];
   }
 }
 
@@ -253,7 +263,14 @@ __device__ inline void write_w(double* __restrict__ Wk, const Tile& W) {
 }
 
 __device__ inline void load_w(const double* __restrict__ Wk, Tile& W) {
-  for (int e = threadIdx.x; e < 4096; e += 256) W[e >> 6][e & 63] = Wk[e];
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = Wk[threadIdx.x + 256 * q];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    W[e >> 6][e & 63] = v[q];
+  }
 }
 
 // Pivot failure: a low-precision K (mixed modes) is formed again one precision level higher
@@ -345,6 +362,7 @@ __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, 
   __syncthreads();
   if (!(diag && ti == k + 1)) {
     if (diag && wc > wr) return;
+    double old[2][2][4];
 #pragma unroll
     for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
@@ -353,7 +371,17 @@ __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, 
         for (int v = 0; v < 4; ++v) {
           const int gi = r0 + 32 * wr + 16 * ib + lk + 4 * v;
           const int gj = c0 + 32 * wc + 16 * jb + li;
-          if (gi < n && gj <= gi) K[(long long)gi * ld + gj] -= acc[ib][jb][v];
+          old[ib][jb][v] = (gi < n && gj <= gi) ? K[(long long)gi * ld + gj] : 0.0;
+        }
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gi = r0 + 32 * wr + 16 * ib + lk + 4 * v;
+          const int gj = c0 + 32 * wc + 16 * jb + li;
+          if (gi < n && gj <= gi) K[(long long)gi * ld + gj] = old[ib][jb][v] - acc[ib][jb][v];
         }
     return;
   }
