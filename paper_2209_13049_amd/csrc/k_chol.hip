@@ -632,11 +632,22 @@ __device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, 
     for (int k = 0; k < nt; ++k) {
       const int k0 = 64 * k;
       const int rows = min(64, n - k0);
+      const double* W = Wall + (long long)k * 4096;
+      double wv[4];  // this lane's entries of row i of W_k, loaded behind the dot product
+#pragma unroll
+      for (int q = 0; q < 4; ++q) wv[q] = W[i * 64 + g + 16 * q];
       double acc = 0.0;
       if (i < rows) {
         const double* row = L + (long long)(k0 + i) * ld;
-#pragma unroll 4
-        for (int c = g; c < k0; c += 16) acc = fma(row[c], ys[c], acc);
+        double acc2 = 0.0;  // two chains; 16 loads in flight per lane
+        int c = g;
+#pragma unroll 8
+        for (; c + 16 < k0; c += 32) {
+          acc = fma(row[c], ys[c], acc);
+          acc2 = fma(row[c + 16], ys[c + 16], acc2);
+        }
+        if (c < k0) acc = fma(row[c], ys[c], acc);
+        acc += acc2;
       }
       acc += __shfl_xor(acc, 1, 64);
       acc += __shfl_xor(acc, 2, 64);
@@ -644,10 +655,9 @@ __device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, 
       acc += __shfl_xor(acc, 8, 64);
       if (g == 0) rs[i] = i < rows ? ys[k0 + i] - acc : 0.0;
       __syncthreads();
-      const double* W = Wall + (long long)k * 4096;
       double v = 0.0;
 #pragma unroll
-      for (int m = g; m < 64; m += 16) v = fma(W[i * 64 + m], rs[m], v);
+      for (int q = 0; q < 4; ++q) v = fma(wv[q], rs[g + 16 * q], v);
       v += __shfl_xor(v, 1, 64);
       v += __shfl_xor(v, 2, 64);
       v += __shfl_xor(v, 4, 64);
@@ -662,10 +672,21 @@ __device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, 
     for (int k = nt - 1; k >= 0; --k) {
       const int k0 = 64 * k;
       const int rows = min(64, n - k0);
+      const double* W = Wall + (long long)k * 4096;
+      double wv[4];  // entries (m, i) of W_k for m = g + 16 q
+#pragma unroll
+      for (int q = 0; q < 4; ++q) wv[q] = W[(g + 16 * q) * 64 + i];
       double acc = 0.0;
       if (i < rows) {
-#pragma unroll 4
-        for (int r = k0 + 64 + g; r < n; r += 16) acc = fma(L[(long long)r * ld + k0 + i], ys[r], acc);
+        double acc2 = 0.0;
+        int r = k0 + 64 + g;
+#pragma unroll 8
+        for (; r + 16 < n; r += 32) {
+          acc = fma(L[(long long)r * ld + k0 + i], ys[r], acc);
+          acc2 = fma(L[(long long)(r + 16) * ld + k0 + i], ys[r + 16], acc2);
+        }
+        if (r < n) acc = fma(L[(long long)r * ld + k0 + i], ys[r], acc);
+        acc += acc2;
       }
       red[g][i] = acc;
       __syncthreads();
@@ -675,10 +696,9 @@ __device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, 
         rs[i] = i < rows ? ys[k0 + i] - sum : 0.0;
       }
       __syncthreads();
-      const double* W = Wall + (long long)k * 4096;
       double v = 0.0;
 #pragma unroll
-      for (int m = g; m < 64; m += 16) v = fma(W[m * 64 + i], rs[m], v);
+      for (int q = 0; q < 4; ++q) v = fma(wv[q], rs[g + 16 * q], v);
       red[g][i] = v;
       __syncthreads();
       if (g == 0 && i < rows) {

@@ -37,8 +37,10 @@ int ipm_alloc_work(Problem& p) {
   p.n_step_blocks = p.n_prep_blocks;
   CMPC_HIP(hipMalloc(&p.norm_part, sizeof(double) * 5 * p.n_prep_blocks));
   CMPC_HIP(hipMalloc(&p.alpha_part, sizeof(double) * 2 * p.n_step_blocks));
-  int rc = 128;
-  while ((long long)ceil_div(p.ns, rc) * p.N > 2048 && rc < 4096) rc *= 2;
+  // Gamma' passes: chunks of rc rows of one row block, enough of them to keep every CU
+  // streaming (64-row chunks unless that makes more than 4096)
+  int rc = 64;
+  while ((long long)ceil_div(p.ns, rc) * p.N > 4096 && rc < 4096) rc *= 2;
   p.gt_rows = rc;
   p.gt_chunks = ceil_div(p.ns, rc) * p.N;
   CMPC_HIP(hipMalloc(&p.gt_part, sizeof(double) * 3 * n * (size_t)p.gt_chunks));
@@ -75,7 +77,7 @@ __device__ __forceinline__ void gamma_t_partial_body(int bid,
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-#pragma unroll 4
+#pragma unroll 16
     for (int r = r0 + rg; r < r1; r += rgs) {
       const double g = va ? base[(long long)r * len + a] : 0.0;
 #pragma unroll
@@ -121,6 +123,7 @@ __device__ __forceinline__ void gamma_t_reduce_body(int bid, const double* __res
   if (a < n) {
     const int tmin = a / nu + 1;  // first block with t nu > a
     const int c0 = (tmin - 1) * cpb;
+#pragma unroll 4
     for (int ch = c0 + g; ch < nchunks; ch += 16)
 #pragma unroll
       for (int k = 0; k < NV; ++k) acc[k] += part[((long long)ch * NV + k) * n + a];

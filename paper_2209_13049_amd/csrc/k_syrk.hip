@@ -337,7 +337,8 @@ __device__ __forceinline__ void syrk_finish_body(int bid,
   const int gi = tl.x * 64 + (e >> 6), gj = tl.y * 64 + (e & 63);
   if (gi >= n || gj > gi) return;
   const int q0 = slot_begin[tile], q1 = slot_begin[tile + 1];
-  double sum = 0.0;
+  double sum = 0.0;  // fixed order; unrolled so that the loads are in flight together
+#pragma unroll 8
   for (int q = q0; q < q1; ++q) sum += partials[(long long)slots[q] * 4096 + e];
   double val = Hb[(long long)gi * n + gj] + sum;
   if (gi == gj && Ddiag != nullptr) val += Ddiag[gi];
