@@ -7,7 +7,7 @@ a different seeded x0.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--precision fp64] [--no-cpu-baseline]
 
-The dominant kernel is the stream-K SYRK that forms K; its duration is measured with HIP
+The dominant kernel is the split-K SYRK that forms K; its duration is measured with HIP
 events on the library's stream over the timed solves and priced against the FP64 MFMA peak
 with the structural FLOP count (only the nonzero blocks of Gamma).
 """
@@ -300,8 +300,8 @@ def main():
         "ms_per_iter_syrk_potrf": main_run["ms_per_iter_syrk_potrf"],
         "ms_per_iter_syrk_kernel": main_run["ms_per_iter_syrk_kernel"],
         "ms_per_iter_potrf": main_run["ms_per_iter_potrf"],
-        "roofline": {"bound": "mfma", "kernel": "syrk_streamk_kernel<double>" if
-                     args.precision == "fp64" else "syrk_streamk_kernel<float>",
+        "roofline": {"bound": "mfma", "kernel": "syrk_splitk_kernel<double>" if
+                     args.precision == "fp64" else "syrk_splitk_kernel<float>",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic() if
                      args.precision == "fp64" else None,

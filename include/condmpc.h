@@ -97,7 +97,7 @@ typedef struct {
   double mu;           /* final barrier parameter */
   double gap;          /* s'z */
   double ms_total;     /* wall time of the solve on the stream, milliseconds */
-  double ms_syrk;      /* profile: time in the stream-K SYRK kernel over the iterations */
+  double ms_syrk;      /* profile: time in the split-K SYRK kernel over the iterations */
   double ms_form;      /* profile: time forming K (SYRK + adding H, diag and partials) */
   double ms_potrf;     /* profile: time in the Cholesky factorisation over the iterations */
 } cmpc_result;
@@ -193,7 +193,8 @@ typedef struct cmpc_batch cmpc_batch;
 
 /* Result of cmpc_batch_tune. */
 typedef struct {
-  int quantum;        /* chosen SYRK work quantum (target work per stream-K workgroup) */
+  int quantum;        /* chosen SYRK work quantum: least work of one split-K workgroup, in
+                         row x 16-block units (a piece holds at least quantum / 16 rows) */
   int persistent;     /* chosen grid policy: 1 = persistent workgroups loop over each work
                          list, 0 = one workgroup per work item */
   int candidates;     /* settings timed */

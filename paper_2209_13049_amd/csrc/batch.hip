@@ -8,8 +8,8 @@
 // launches of one iteration are captured once as a HIP graph and replayed; instances that
 // have converged are predicated off (their items return at entry) until all are done.
 //
-// The tuning table maps (n, mx, precision) to the SYRK work quantum (target work per
-// stream-K workgroup) and the grid policy of the work-list launches; cmpc_batch_tune fills
+// The tuning table maps (n, mx, precision) to the SYRK work quantum (least work per
+// split-K workgroup) and the grid policy of the work-list launches; cmpc_batch_tune fills
 // it by timing the batched SYRK over candidate settings, and every later solve of a
 // problem with that key (batched or not) builds its plan from it.
 #include <algorithm>

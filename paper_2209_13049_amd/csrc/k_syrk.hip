@@ -5,15 +5,17 @@
 // Design (gfx950):
 //  * Gamma is stored packed by row block t (ns x t nu), so only its structural nonzeros
 //    are read; tile (I, J) of K receives row block t only if t nu > 64 I.
-//  * Work = (64 x 64 output tile, row block, row range) segments, ordered block-major and
-//    cut into equal-cost pieces, one piece per workgroup (stream-K).  Workgroups that run
-//    on the same XCD get neighbouring pieces, so a row block is fetched from HBM once per
-//    XCD and re-read from that XCD's L2 by every tile that needs it.
-//  * Each of the 4 wavefronts of a workgroup accumulates the whole 64 x 64 tile over every
-//    4th group of 4 rows with v_mfma_f64_16x16x4f64 (or the f32 variant), operands loaded
-//    straight from memory in the MFMA lane layout through a register prefetch ring and
-//    scaled by D on the fly; structurally zero columns (>= t nu) load as zeros.
-//  * At the end of a tile's piece the 4 accumulators are summed in LDS and written to a
+//  * Split-K: each 64 x 64 output tile's rows (its row blocks, t descending, all ns rows
+//    of each) are cut into pieces of equal cost, one piece per workgroup, all pieces
+//    resident at once (at most 512 workgroups, 2 per CU).  Pieces that cover the same rows
+//    of different tiles run together on one XCD, so those rows come from HBM once and are
+//    re-read from that XCD's L2 by every tile that needs them.
+//  * Each of the 4 wavefronts of a workgroup accumulates the whole tile over every 4th
+//    group of 4 rows with v_mfma_f64_16x16x4f64 (or the f32 / bf16 variants), operands
+//    loaded straight from memory in the MFMA lane layout through a register prefetch ring
+//    and scaled by D on the fly; structurally zero columns (>= t nu) enter as zeros, and a
+//    diagonal tile computes only its 10 blocks on or below the diagonal.
+//  * At the end of its piece a workgroup sums the 4 accumulators in LDS and writes a
 //    partial slot; a second kernel adds the slots of each tile in a fixed order to Hbase
 //    (deterministic, no atomics).
 #include <algorithm>
@@ -53,66 +55,66 @@ int syrk_plan(Problem& p, int quantum) {
   for (int I = 0; I < sp.nt; ++I)
     for (int J = 0; J <= I; ++J) tiles.push_back(make_int2(I, J));
   sp.ntiles = (int)tiles.size();
-  struct Seg {
-    int tile, t, cpr;
-  };
-  std::vector<Seg> segs;
-  double total = 0.0;
-  for (int t = N; t >= 1; --t)
-    for (int q = 0; q < sp.ntiles; ++q) {
-      // a segment exists when the block reaches the tile's rows; the kernel always runs the
-      // full 4 x 4 set of 16 x 16 blocks, so every row costs the same
-      if (nblocks16(tiles[q].x, tiles[q].y, t * nu) > 0) {
-        segs.push_back({q, t, 16});
-        total += 16.0 * ns;
-      }
-    }
   sp.flops_structural = 0.0;
   for (int t = 1; t <= N; ++t) {
     const double len = (double)t * nu;
     sp.flops_structural += (double)ns * len * (len + 1.0);
   }
-  int nwg = (int)(total / (double)quantum);
-  nwg = std::max(8, std::min(512, nwg));
-  nwg = (nwg + 7) / 8 * 8;
-  const double target = total / nwg;
+  // Tile q receives row blocks t = N, N-1, ..., t_q (a tile is reached once t nu > 64 I, so
+  // its blocks are the last ones); its work is the row sequence of those blocks, t
+  // descending, rows ascending, L_q rows long.  Every row costs the same (the kernel runs
+  // all 4 x 4 blocks of 16 x 16), so position p of every tile's sequence is the same row
+  // (t = N - p / ns, r = p % ns).
+  std::vector<long long> L(sp.ntiles, 0);
+  for (int q = 0; q < sp.ntiles; ++q)
+    for (int t = N; t >= 1 && nblocks16(tiles[q].x, tiles[q].y, t * nu) > 0; --t) L[q] += ns;
+  // Pieces: tile q's sequence cut every P_q rows, one piece per workgroup.  A row of a
+  // diagonal tile costs 10 blocks of 16 x 16 (those on or below the diagonal), of any other
+  // tile 16, so P_q = P for off-diagonal and about 1.6 P for diagonal tiles, P the
+  // smallest multiple of 16 (at least quantum / 16) for which all pieces fit one resident
+  // round of kMaxWg workgroups.  Pieces with the same index j of the off-diagonal tiles
+  // cover the same rows: they are listed together, and consecutive pieces run on the same
+  // XCD, so that those rows are fetched from HBM once into that XCD's L2 and re-read there
+  // by each tile.
+  constexpr int kMaxWg = 512;
+  auto rows_of = [&](int q, long long P) {
+    return tiles[q].x == tiles[q].y ? std::max<long long>(16, P * 16 / 10 / 16 * 16) : P;
+  };
+  auto count = [&](long long P) {
+    long long c = 0;
+    for (int q = 0; q < sp.ntiles; ++q) c += (L[q] + rows_of(q, P) - 1) / rows_of(q, P);
+    return c;
+  };
+  long long total = 0;
+  for (int q = 0; q < sp.ntiles; ++q) total += L[q];
+  long long P = std::max<long long>(16, (quantum / 16 + 15) / 16 * 16);
+  P = std::max(P, (total / kMaxWg + 15) / 16 * 16 * 10 / 16 / 16 * 16);
+  while (count(P) > kMaxWg) P += 16;
+  long long nfront = 0;
+  for (int q = 0; q < sp.ntiles; ++q)
+    nfront = std::max(nfront, (L[q] + rows_of(q, P) - 1) / rows_of(q, P));
   std::vector<SyrkJob> jobs;
-  std::vector<int> job_wg;
-  int wg = 0;
-  double acc = 0.0;
-  for (const Seg& sg : segs) {
-    int r = 0;
-    while (r < ns) {
-      const double room = target * (wg + 1) - acc;
-      int take = ns - r;
-      if (wg < nwg - 1) {
-        int want = (int)std::ceil(std::max(room, 1.0) / sg.cpr);
-        want = (want + 15) / 16 * 16;
-        take = std::min(take, std::max(16, want));
-      }
-      jobs.push_back({sg.tile, sg.t, r, r + take, -1});
-      job_wg.push_back(wg);
-      acc += (double)take * sg.cpr;
-      r += take;
-      if (wg < nwg - 1 && acc >= target * (wg + 1) - 1e-9) ++wg;
-    }
-  }
-  // workgroup ranges (jobs are emitted in workgroup order) and flush points
-  std::vector<int> wg_begin(nwg + 1, (int)jobs.size());
-  for (int j = (int)jobs.size() - 1; j >= 0; --j) wg_begin[job_wg[j]] = j;
-  for (int w = nwg - 1; w >= 0; --w)
-    if (wg_begin[w] > wg_begin[w + 1]) wg_begin[w] = wg_begin[w + 1];
+  std::vector<int> wg_begin;
   std::vector<int> slot_tile;
-  for (size_t j = 0; j < jobs.size(); ++j) {
-    const bool last = (j + 1 == jobs.size()) || job_wg[j + 1] != job_wg[j] ||
-                      jobs[j + 1].tile != jobs[j].tile;
-    if (last) {
-      jobs[j].slot = (int)slot_tile.size();
-      slot_tile.push_back(jobs[j].tile);
+  for (long long j = 0; j < nfront; ++j)
+    for (int q = 0; q < sp.ntiles; ++q) {
+      const long long Pq = rows_of(q, P);
+      if (L[q] <= j * Pq) continue;
+      const long long p0 = j * Pq, p1 = std::min(L[q], p0 + Pq);
+      wg_begin.push_back((int)jobs.size());
+      for (long long pos = p0; pos < p1;) {
+        const int t = N - (int)(pos / ns), r0 = (int)(pos % ns);
+        const int r1 = (int)std::min<long long>(ns, r0 + (p1 - pos));
+        jobs.push_back({q, t, r0, r1, -1});
+        pos += r1 - r0;
+      }
+      jobs.back().slot = (int)slot_tile.size();
+      slot_tile.push_back(q);
     }
-  }
+  int nwg = std::max(8, ((int)wg_begin.size() + 7) / 8 * 8);
+  wg_begin.resize(nwg + 1, (int)jobs.size());
   sp.nslots = (int)slot_tile.size();
-  std::vector<int> slot_begin(sp.ntiles + 1, 0), slots(sp.nslots);
+  std::vector<int> slot_begin(sp.ntiles + 1, 0), slots(std::max(1, sp.nslots));
   for (int s = 0; s < sp.nslots; ++s) slot_begin[slot_tile[s] + 1]++;
   for (int q = 0; q < sp.ntiles; ++q) slot_begin[q + 1] += slot_begin[q];
   {
@@ -171,7 +173,8 @@ struct MfmaOps<bf16_t> {
 // BF16 inputs: rows [r0, r1) in groups of 32 per v_mfma_f32_16x16x32_bf16, every wavefront
 // taking every 4th group; lane (li, lk) supplies rows 8 lk .. 8 lk + 7 of the group in
 // column 16 q + li.  The left operand is scaled by D in float32 and rounded to bfloat16,
-// products accumulate in float32.
+// products accumulate in float32.  DIAG as for syrk_rows below.
+template <bool DIAG>
 __device__ __forceinline__ void syrk_rows_bf16(f4 (&acc)[4][4], const bf16_t* __restrict__ base,
                                                const double* __restrict__ Dt, int len, int a0,
                                                int b0, int r0, int r1, int wave, int li, int lk) {
@@ -194,7 +197,7 @@ __device__ __forceinline__ void syrk_rows_bf16(f4 (&acc)[4][4], const bf16_t* __
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const bf16_t ga = (vr && va[q]) ? row[a0 + 16 * q + li] : (bf16_t)0;
-        const bf16_t gb = (vr && vb[q]) ? row[b0 + 16 * q + li] : (bf16_t)0;
+        const bf16_t gb = DIAG ? ga : ((vr && vb[q]) ? row[b0 + 16 * q + li] : (bf16_t)0);
         A[q][e] = (short)f2bf(bf2f(ga) * d);
         B[q][e] = (short)gb;
       }
@@ -203,7 +206,9 @@ __device__ __forceinline__ void syrk_rows_bf16(f4 (&acc)[4][4], const bf16_t* __
     for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
       for (int jb = 0; jb < 4; ++jb)
-        acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ib], B[jb], acc[ib][jb], 0, 0, 0);
+        if (!DIAG || jb <= ib)
+          acc[ib][jb] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ib], B[jb], acc[ib][jb], 0, 0, 0);
   }
 }
 
@@ -211,15 +216,20 @@ __device__ __forceinline__ void syrk_rows_bf16(f4 (&acc)[4][4], const bf16_t* __
 // of 4 rows; operands are loaded straight into the MFMA lane layout (lane l: column l%16 of
 // a 16-column block, row l/16 of the 4-row group) through a PF-deep register ring, so PF-1
 // groups of loads are in flight behind the MFMAs of the current group.  Columns >= t nu
-// (structural zeros) and rows >= r1 load as 0 without touching memory; all 16 output blocks
-// are always computed (one code path keeps the accumulators in registers at 2 waves/SIMD).
-template <typename TIn>
+// (structural zeros) and rows >= r1 enter as 0.  DIAG (a diagonal tile, a0 == b0): both
+// operands come from the same 64 columns, loaded once, and only the 10 blocks on or below
+// the diagonal are computed; otherwise all 16 blocks are.
+template <typename TIn, bool DIAG>
 __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4][4],
                                           const TIn* __restrict__ base,
                                           const double* __restrict__ Dt, int len, int a0, int b0,
                                           int r0, int r1, int wave, int li, int lk) {
   typedef MfmaOps<TIn> Ops;
+#ifndef CMPC_SYRK_PF
   constexpr int PF = 3;
+#else
+  constexpr int PF = CMPC_SYRK_PF;
+#endif
   bool va[4], vb[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -228,46 +238,73 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
   }
   const int nsteps = (r1 - r0 + 15) >> 4;
   TIn ra[PF][4], rb[PF][4], rd[PF];
+  // Every load is issued unconditionally from an in-bounds address (row r0, column 0 for
+  // lanes outside the rows or columns), and the ring keeps the raw values; rows and columns
+  // outside the piece are zeroed where a group is consumed.  With no branch around a load
+  // and no use of a value before its group is due, the compiler waits for exactly that
+  // group instead of draining every load in flight.
+  int ca[4], cb[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ca[q] = va[q] ? a0 + 16 * q + li : 0;
+    cb[q] = vb[q] ? b0 + 16 * q + li : 0;
+  }
   auto load = [&](int step, TIn (&xa)[4], TIn (&xb)[4], TIn& xd) {
     const int r = r0 + 16 * step + 4 * wave + lk;
-    const bool vr = r < r1;
-    const TIn* row = base + (long long)(vr ? r : r0) * len;
-    xd = vr ? (TIn)Dt[r] : (TIn)0;
+    const int rr = r < r1 ? r : r0;
+    const TIn* row = base + (long long)rr * len;
+    xd = (TIn)Dt[rr];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      xa[q] = (vr && va[q]) ? row[a0 + 16 * q + li] : (TIn)0;
-      xb[q] = (vr && vb[q]) ? row[b0 + 16 * q + li] : (TIn)0;
+      xa[q] = row[ca[q]];
+      if constexpr (!DIAG) xb[q] = row[cb[q]];
     }
   };
 #pragma unroll
-  for (int u = 0; u < PF; ++u) load(u, ra[u], rb[u], rd[u]);
+  for (int u = 0; u < PF; ++u) {
+    load(u, ra[u], rb[u], rd[u]);
+    asm volatile("" ::: "memory");  // groups issued in ring order (see below)
+    __builtin_amdgcn_sched_barrier(0);
+  }
   for (int step = 0; step < nsteps; step += PF) {
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-      TIn sa[4];
+      const bool vr = r0 + 16 * (step + u) + 4 * wave + lk < r1;
+      const TIn d = vr ? rd[u] : (TIn)0;
+      TIn sa[4], sb[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sa[q] = ra[u][q] * rd[u];
+      for (int q = 0; q < 4; ++q) {
+        sa[q] = va[q] ? ra[u][q] * d : (TIn)0;
+        sb[q] = vb[q] ? (DIAG ? ra[u][q] : rb[u][q]) : (TIn)0;
+      }
 #pragma unroll
       for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = Ops::mma(sa[ib], rb[u][jb], acc[ib][jb]);
+        for (int jb = 0; jb < 4; ++jb)
+          if (!DIAG || jb <= ib) acc[ib][jb] = Ops::mma(sa[ib], sb[jb], acc[ib][jb]);
       load(step + u + PF, ra[u], rb[u], rd[u]);
+      // Keep each group's loads here, PF - 1 groups ahead of their use, and each group's
+      // masking with its MFMAs: without the fences the compiler moves the loads down to
+      // the iteration that consumes them and hoists the masking of later groups, and either
+      // way every load in flight is waited for at the top of the loop.
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
 
-template <typename TIn>
-__device__ __forceinline__ void syrk_streamk_body(int bid, 
-    const TIn* __restrict__ Gam, const long long* __restrict__ off, const double* __restrict__ D,
-    const SyrkJob* __restrict__ jobs, const int* __restrict__ wg_begin,
-    const int2* __restrict__ tiles, double* __restrict__ partials, int ns, int nu, int nwg,
-    const int* __restrict__ done, const int* __restrict__ lowflag, int want_low) {
+// The jobs [j0, j1) of one workgroup (all on one tile): accumulate, and at a job that
+// carries a slot sum the 4 wavefronts' accumulators in LDS and write the partial tile.
+template <typename TIn, bool DIAG>
+__device__ __forceinline__ void syrk_jobs(const TIn* __restrict__ Gam,
+                                          const long long* __restrict__ off,
+                                          const double* __restrict__ D,
+                                          const SyrkJob* __restrict__ jobs, int j0, int j1,
+                                          const int2* __restrict__ tiles,
+                                          double* __restrict__ partials, int ns, int nu,
+                                          double* red) {
   typedef MfmaOps<TIn> Ops;
   typedef typename Ops::acc_t acc_t;
-  __shared__ double red[64 * 64];
-  if (done != nullptr && *done) return;
-  if (lowflag != nullptr && *lowflag != want_low) return;
-  const int wg = bid;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   acc_t acc[4][4];
@@ -275,9 +312,7 @@ __device__ __forceinline__ void syrk_streamk_body(int bid,
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-
-  const int jend = wg_begin[wg + 1];
-  for (int jj = wg_begin[wg]; jj < jend; ++jj) {
+  for (int jj = j0; jj < j1; ++jj) {
     const SyrkJob job = jobs[jj];
     const int2 tl = tiles[job.tile];
     const int a0 = tl.x * 64, b0 = tl.y * 64;
@@ -285,9 +320,9 @@ __device__ __forceinline__ void syrk_streamk_body(int bid,
     const TIn* __restrict__ base = Gam + off[job.t - 1];
     const double* __restrict__ Dt = D + (long long)(job.t - 1) * ns;
     if constexpr (sizeof(TIn) == 2)
-      syrk_rows_bf16(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
+      syrk_rows_bf16<DIAG>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
     else
-      syrk_rows<TIn>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
+      syrk_rows<TIn, DIAG>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
     if (job.slot >= 0) {
       __syncthreads();
       for (int w = 0; w < 4; ++w) {
@@ -316,12 +351,31 @@ __device__ __forceinline__ void syrk_streamk_body(int bid,
 }
 
 template <typename TIn>
-__global__ __launch_bounds__(256, 2) void syrk_streamk_kernel(
+__device__ __forceinline__ void syrk_splitk_body(int bid, 
     const TIn* __restrict__ Gam, const long long* __restrict__ off, const double* __restrict__ D,
     const SyrkJob* __restrict__ jobs, const int* __restrict__ wg_begin,
     const int2* __restrict__ tiles, double* __restrict__ partials, int ns, int nu, int nwg,
     const int* __restrict__ done, const int* __restrict__ lowflag, int want_low) {
-  syrk_streamk_body<TIn>((blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3), Gam, off, D, jobs, wg_begin, tiles, partials, ns, nu, nwg, done, lowflag, want_low);
+  __shared__ double red[64 * 64];
+  if (done != nullptr && *done) return;
+  if (lowflag != nullptr && *lowflag != want_low) return;
+  const int j0 = wg_begin[bid], j1 = wg_begin[bid + 1];
+  if (j0 >= j1) return;
+  // every job of a workgroup is on the same tile (the planner cuts pieces per tile)
+  const int2 tl = tiles[jobs[j0].tile];
+  if (tl.x == tl.y)
+    syrk_jobs<TIn, true>(Gam, off, D, jobs, j0, j1, tiles, partials, ns, nu, red);
+  else
+    syrk_jobs<TIn, false>(Gam, off, D, jobs, j0, j1, tiles, partials, ns, nu, red);
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(256, 2) void syrk_splitk_kernel(
+    const TIn* __restrict__ Gam, const long long* __restrict__ off, const double* __restrict__ D,
+    const SyrkJob* __restrict__ jobs, const int* __restrict__ wg_begin,
+    const int2* __restrict__ tiles, double* __restrict__ partials, int ns, int nu, int nwg,
+    const int* __restrict__ done, const int* __restrict__ lowflag, int want_low) {
+  syrk_splitk_body<TIn>((blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3), Gam, off, D, jobs, wg_begin, tiles, partials, ns, nu, nwg, done, lowflag, want_low);
 }
 
 // K(lower) = Hb(lower) + sum of the tile's partial slots (fixed order) + diag(Ddiag).
@@ -352,7 +406,7 @@ __global__ __launch_bounds__(256) void syrk_finish_kernel(
   syrk_finish_body(blockIdx.x, partials, slot_begin, slots, tiles, Hb, Ddiag, K, n, done);
 }
 
-// ---- work-list forms (batches): one item = one stream-K workgroup (or one finish block) of
+// ---- work-list forms (batches): one item = one split-K workgroup (or one finish block) of
 // one instance, with that instance's own plan, so the result is the single-instance one.
 // mixed != 0: the item runs only when the instance's precision level st->use_low equals
 // want_low (2 = BF16, 1 = FP32, 0 = FP64).
@@ -363,7 +417,7 @@ __global__ __launch_bounds__(256, 2) void syrk_batch_kernel(const InstView* __re
   CMPC_ITEMS_BEGIN
   const TIn* G = sizeof(TIn) == 8 ? (const TIn*)V.Gam
                                    : (sizeof(TIn) == 4 ? (const TIn*)V.Gam32 : (const TIn*)V.Gam16);
-  syrk_streamk_body<TIn>(bid, G, V.goff, V.Dx, V.jobs, V.wg_begin, V.tiles, V.partials, V.ns,
+  syrk_splitk_body<TIn>(bid, G, V.goff, V.Dx, V.jobs, V.wg_begin, V.tiles, V.partials, V.ns,
                          V.nu, V.syrk_nwg, &V.st->done, mixed ? &V.st->use_low : nullptr,
                          want_low);
   CMPC_ITEMS_END
@@ -406,17 +460,17 @@ int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hba
   for (int lev = top; lev >= bottom; --lev) {
     hipEvent_t e0 = lev == top ? ev_start : nullptr, e1 = lev == bottom ? ev_stop : nullptr;
     if (lev == 2)
-      hipExtLaunchKernelGGL(syrk_streamk_kernel<bf16_t>, dim3(sp.nwg), dim3(256), 0, p.stream, e0,
+      hipExtLaunchKernelGGL(syrk_splitk_kernel<bf16_t>, dim3(sp.nwg), dim3(256), 0, p.stream, e0,
                             e1, 0, (const bf16_t*)p.Gam16, (const long long*)p.goff, Drow,
                             (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
                             (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done, low, 2);
     else if (lev == 1)
-      hipExtLaunchKernelGGL(syrk_streamk_kernel<float>, dim3(sp.nwg), dim3(256), 0, p.stream, e0,
+      hipExtLaunchKernelGGL(syrk_splitk_kernel<float>, dim3(sp.nwg), dim3(256), 0, p.stream, e0,
                             e1, 0, (const float*)p.Gam32, (const long long*)p.goff, Drow,
                             (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
                             (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done, low, 1);
     else
-      hipExtLaunchKernelGGL(syrk_streamk_kernel<double>, dim3(sp.nwg), dim3(256), 0, p.stream, e0,
+      hipExtLaunchKernelGGL(syrk_splitk_kernel<double>, dim3(sp.nwg), dim3(256), 0, p.stream, e0,
                             e1, 0, (const double*)p.Gam, (const long long*)p.goff, Drow,
                             (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
                             (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done, low, 0);

@@ -30,7 +30,7 @@ struct IpmState {
 
 constexpr int kRunning = 100;
 
-// One stream-K job of the SYRK: rows [r0, r1) of row block t (1-based) contribute to
+// One split-K job of the SYRK: rows [r0, r1) of row block t (1-based) contribute to
 // output tile `tile`; slot >= 0 means the accumulator is written to partial slot `slot`
 // after this job and cleared.
 struct SyrkJob {
@@ -39,7 +39,7 @@ struct SyrkJob {
 
 struct SyrkPlan {
   int nt = 0, ntiles = 0, nwg = 0, nslots = 0;
-  int quantum = 0;               // target work per workgroup (row-tile units, see syrk_plan)
+  int quantum = 0;               // least work per workgroup (row x 16-block units, see syrk_plan)
   int2* tiles = nullptr;         // (I, J) tile coordinates, I >= J, 64 x 64 tiles
   SyrkJob* jobs = nullptr;
   int* wg_begin = nullptr;       // nwg + 1
@@ -225,7 +225,7 @@ constexpr int kSyrkQuantumDefault = 12000;
 int syrk_plan(Problem& p, int quantum = kSyrkQuantumDefault);
 void syrk_free(SyrkPlan& sp);
 // K(lower) = Hbase(lower) + Gamma' diag(Drow) Gamma + diag(Ddiag)   (Ddiag may be NULL)
-// ev_start / ev_stop (optional): timing events attached to the stream-K kernel's dispatch.
+// ev_start / ev_stop (optional): timing events attached to the split-K kernel's dispatch.
 // precision CMPC_FP64 or CMPC_FP32_SYRK; mixed != 0 queues both variants, each running only
 // when the device flag st->use_low selects it.
 int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hbase,
