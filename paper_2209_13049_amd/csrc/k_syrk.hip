@@ -6,10 +6,11 @@
 //  * Gamma is stored packed by row block t (ns x t nu), so only its structural nonzeros
 //    are read; tile (I, J) of K receives row block t only if t nu > 64 I.
 //  * Split-K: each 64 x 64 output tile's rows (its row blocks, t descending, all ns rows
-//    of each) are cut into pieces of equal cost, one piece per workgroup, all pieces
-//    resident at once (at most 512 workgroups, 2 per CU).  Pieces that cover the same rows
-//    of different tiles run together on one XCD, so those rows come from HBM once and are
-//    re-read from that XCD's L2 by every tile that needs them.
+//    of each) are cut into pieces, and the pieces packed into workgroups of equal cost
+//    under a measured time model, all workgroups resident at once (at most 512, 2 per CU).
+//    Pieces that cover the same rows of different tiles run together on one XCD, so those
+//    rows come from HBM once and are re-read from that XCD's L2 by every tile that needs
+//    them.
 //  * Each of the 4 wavefronts of a workgroup accumulates the whole tile over every 4th
 //    group of 4 rows with v_mfma_f64_16x16x4f64 (or the f32 / bf16 variants), operands
 //    loaded straight from memory in the MFMA lane layout through a register prefetch ring
@@ -62,55 +63,129 @@ int syrk_plan(Problem& p, int quantum) {
   }
   // Tile q receives row blocks t = N, N-1, ..., t_q (a tile is reached once t nu > 64 I, so
   // its blocks are the last ones); its work is the row sequence of those blocks, t
-  // descending, rows ascending, L_q rows long.  Every row costs the same (the kernel runs
-  // all 4 x 4 blocks of 16 x 16), so position p of every tile's sequence is the same row
-  // (t = N - p / ns, r = p % ns).
-  std::vector<long long> L(sp.ntiles, 0);
-  for (int q = 0; q < sp.ntiles; ++q)
-    for (int t = N; t >= 1 && nblocks16(tiles[q].x, tiles[q].y, t * nu) > 0; --t) L[q] += ns;
-  // Pieces: tile q's sequence cut every P_q rows, one piece per workgroup.  A row of a
-  // diagonal tile costs 10 blocks of 16 x 16 (those on or below the diagonal), of any other
-  // tile 16, so P_q = P for off-diagonal and about 1.6 P for diagonal tiles, P the
-  // smallest multiple of 16 (at least quantum / 16) for which all pieces fit one resident
-  // round of kMaxWg workgroups.  Pieces with the same index j of the off-diagonal tiles
-  // cover the same rows: they are listed together, and consecutive pieces run on the same
-  // XCD, so that those rows are fetched from HBM once into that XCD's L2 and re-read there
-  // by each tile.
-  constexpr int kMaxWg = 512;
-  auto rows_of = [&](int q, long long P) {
-    return tiles[q].x == tiles[q].y ? std::max<long long>(16, P * 16 / 10 / 16 * 16) : P;
+  // descending, rows ascending.  A row of block t costs the 16 x 16 blocks the kernel
+  // computes for it: the row blocks of the tile's 64 rows that t nu reaches (nib of 4),
+  // times 4 column blocks, or, on a diagonal tile, the nib (nib + 1) / 2 blocks on or below
+  // the diagonal.
+  auto row_cost = [&](int q, int t) {
+    const int len = t * nu, a0 = 64 * tiles[q].x;
+    if (len <= a0) return 0;
+    const int nib = std::min(4, ceil_div(len - a0, 16));
+    return tiles[q].x == tiles[q].y ? nib * (nib + 1) / 2 : 4 * nib;
   };
-  auto count = [&](long long P) {
-    long long c = 0;
-    for (int q = 0; q < sp.ntiles; ++q) c += (L[q] + rows_of(q, P) - 1) / rows_of(q, P);
-    return c;
+  // Pieces: tile q's sequence cut into runs of cost at most C (whole groups of 16 rows) and
+  // wherever the row cost changes (the kernel specialises a piece's loop on it); the pieces
+  // are packed into workgroups of cost at most C, C the least (at least quantum) for which
+  // all workgroups fit one resident round of kMaxWg (2 per CU).
+  constexpr int kMaxWg = 512;
+  // Time model in block units (measured): a row also costs 4 for its loads, masking and
+  // address arithmetic, and a piece 800 for its prologue (the first groups' load latency)
+  // and its flush.
+  const long long kRowOverhead = 4, kPieceOverhead = 800;
+  auto cut = [&](int q, long long C, std::vector<std::vector<SyrkJob>>* out) {
+    long long npieces = 0, used = 0;
+    bool open = false;
+    std::vector<SyrkJob> cur;
+    auto close = [&]() {
+      if (!open) return;
+      ++npieces;
+      if (out) out->push_back(cur);
+      cur.clear();
+      used = 0;
+      open = false;
+    };
+    for (int t = N; t >= 1; --t) {
+      const int c = row_cost(q, t);
+      if (c == 0) break;
+      const long long w = c + kRowOverhead;
+      if (open && c != row_cost(q, cur.back().t)) close();
+      int r = 0;
+      while (r < ns) {
+        if (open && C - used < 16 * w) close();
+        if (!open) {
+          open = true;
+          used = kPieceOverhead;
+        }
+        long long take = std::max<long long>(16, (C - used) / w / 16 * 16);
+        take = std::min<long long>(take, ns - r);
+        cur.push_back({q, t, r, r + (int)take, -1});
+        used += take * w;
+        r += (int)take;
+      }
+    }
+    close();
+    return npieces;
+  };
+  struct Piece {
+    int q;
+    size_t j;  // index of the piece within its tile's sequence
+    long long cost;
+    std::vector<SyrkJob> jobs;
+  };
+  auto make_pieces = [&](long long C) {
+    std::vector<Piece> ps;
+    for (int q = 0; q < sp.ntiles; ++q) {
+      std::vector<std::vector<SyrkJob>> v;
+      cut(q, C, &v);
+      for (size_t j = 0; j < v.size(); ++j) {
+        long long c = kPieceOverhead;
+        for (const SyrkJob& jb : v[j]) c += (row_cost(q, jb.t) + kRowOverhead) * (jb.r1 - jb.r0);
+        ps.push_back({q, j, c, std::move(v[j])});
+      }
+    }
+    return ps;
+  };
+  // Workgroups: the pieces packed first-fit decreasing into bins of cost at most C (the
+  // tails of the tiles' sequences fill up the workgroups of other tiles' tails).
+  auto pack = [&](const std::vector<Piece>& ps, long long C, std::vector<std::vector<int>>* bins) {
+    std::vector<int> order(ps.size());
+    for (size_t i = 0; i < ps.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return ps[a].cost > ps[b].cost; });
+    std::vector<long long> load;
+    bins->clear();
+    for (int i : order) {
+      size_t b = 0;
+      while (b < load.size() && load[b] + ps[i].cost > C) ++b;
+      if (b == load.size()) {
+        load.push_back(0);
+        bins->emplace_back();
+      }
+      load[b] += ps[i].cost;
+      (*bins)[b].push_back(i);
+    }
+    return (long long)bins->size();
   };
   long long total = 0;
-  for (int q = 0; q < sp.ntiles; ++q) total += L[q];
-  long long P = std::max<long long>(16, (quantum / 16 + 15) / 16 * 16);
-  P = std::max(P, (total / kMaxWg + 15) / 16 * 16 * 10 / 16 / 16 * 16);
-  while (count(P) > kMaxWg) P += 16;
-  long long nfront = 0;
   for (int q = 0; q < sp.ntiles; ++q)
-    nfront = std::max(nfront, (L[q] + rows_of(q, P) - 1) / rows_of(q, P));
+    for (int t = N; t >= 1 && row_cost(q, t) > 0; --t)
+      total += (row_cost(q, t) + kRowOverhead) * ns;
+  long long C = std::max<long long>({(long long)quantum, 16LL * 16, (total + kMaxWg - 1) / kMaxWg});
+  std::vector<Piece> ps;
+  std::vector<std::vector<int>> bins;
+  for (;;) {
+    ps = make_pieces(C);
+    if (pack(ps, C, &bins) <= kMaxWg) break;
+    C += std::max<long long>(16, C / 200);
+  }
+  // Workgroups in the order of their largest piece's (index, tile): the full-length pieces
+  // with the same index cover the same rows of every tile, and consecutive workgroups run on
+  // the same XCD, so that those rows are fetched from HBM once into that XCD's L2 and
+  // re-read there by each tile.
+  auto key = [&](const std::vector<int>& bn) { return std::make_pair(ps[bn[0]].j, ps[bn[0]].q); };
+  std::stable_sort(bins.begin(), bins.end(),
+                   [&](const std::vector<int>& a, const std::vector<int>& b) { return key(a) < key(b); });
   std::vector<SyrkJob> jobs;
   std::vector<int> wg_begin;
   std::vector<int> slot_tile;
-  for (long long j = 0; j < nfront; ++j)
-    for (int q = 0; q < sp.ntiles; ++q) {
-      const long long Pq = rows_of(q, P);
-      if (L[q] <= j * Pq) continue;
-      const long long p0 = j * Pq, p1 = std::min(L[q], p0 + Pq);
-      wg_begin.push_back((int)jobs.size());
-      for (long long pos = p0; pos < p1;) {
-        const int t = N - (int)(pos / ns), r0 = (int)(pos % ns);
-        const int r1 = (int)std::min<long long>(ns, r0 + (p1 - pos));
-        jobs.push_back({q, t, r0, r1, -1});
-        pos += r1 - r0;
-      }
+  for (const std::vector<int>& bn : bins) {
+    wg_begin.push_back((int)jobs.size());
+    for (int i : bn) {
+      for (const SyrkJob& jb : ps[i].jobs) jobs.push_back(jb);
       jobs.back().slot = (int)slot_tile.size();
-      slot_tile.push_back(q);
+      slot_tile.push_back(ps[i].q);
     }
+  }
   int nwg = std::max(8, ((int)wg_begin.size() + 7) / 8 * 8);
   wg_begin.resize(nwg + 1, (int)jobs.size());
   sp.nslots = (int)slot_tile.size();
@@ -173,8 +248,8 @@ struct MfmaOps<bf16_t> {
 // BF16 inputs: rows [r0, r1) in groups of 32 per v_mfma_f32_16x16x32_bf16, every wavefront
 // taking every 4th group; lane (li, lk) supplies rows 8 lk .. 8 lk + 7 of the group in
 // column 16 q + li.  The left operand is scaled by D in float32 and rounded to bfloat16,
-// products accumulate in float32.  DIAG as for syrk_rows below.
-template <bool DIAG>
+// products accumulate in float32.  DIAG and NIB as for syrk_rows below.
+template <bool DIAG, int NIB>
 __device__ __forceinline__ void syrk_rows_bf16(f4 (&acc)[4][4], const bf16_t* __restrict__ base,
                                                const double* __restrict__ Dt, int len, int a0,
                                                int b0, int r0, int r1, int wave, int li, int lk) {
@@ -203,7 +278,7 @@ __device__ __forceinline__ void syrk_rows_bf16(f4 (&acc)[4][4], const bf16_t* __
       }
     }
 #pragma unroll
-    for (int ib = 0; ib < 4; ++ib)
+    for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
       for (int jb = 0; jb < 4; ++jb)
         if (!DIAG || jb <= ib)
@@ -216,20 +291,17 @@ __device__ __forceinline__ void syrk_rows_bf16(f4 (&acc)[4][4], const bf16_t* __
 // of 4 rows; operands are loaded straight into the MFMA lane layout (lane l: column l%16 of
 // a 16-column block, row l/16 of the 4-row group) through a PF-deep register ring, so PF-1
 // groups of loads are in flight behind the MFMAs of the current group.  Columns >= t nu
-// (structural zeros) and rows >= r1 enter as 0.  DIAG (a diagonal tile, a0 == b0): both
-// operands come from the same 64 columns, loaded once, and only the 10 blocks on or below
-// the diagonal are computed; otherwise all 16 blocks are.
-template <typename TIn, bool DIAG>
+// (structural zeros) and rows >= r1 enter as 0.  Only the first NIB row blocks of the tile
+// (those that t nu reaches: NIB = min(4, ceil((t nu - a0) / 16))) are loaded and computed.
+// DIAG (a diagonal tile, a0 == b0): both operands come from the same columns, loaded once,
+// and only the blocks on or below the diagonal are computed.
+template <typename TIn, bool DIAG, int NIB>
 __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4][4],
                                           const TIn* __restrict__ base,
                                           const double* __restrict__ Dt, int len, int a0, int b0,
                                           int r0, int r1, int wave, int li, int lk) {
   typedef MfmaOps<TIn> Ops;
-#ifndef CMPC_SYRK_PF
   constexpr int PF = 3;
-#else
-  constexpr int PF = CMPC_SYRK_PF;
-#endif
   bool va[4], vb[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -243,21 +315,25 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
   // outside the piece are zeroed where a group is consumed.  With no branch around a load
   // and no use of a value before its group is due, the compiler waits for exactly that
   // group instead of draining every load in flight.
-  int ca[4], cb[4];
+  // Byte offsets from the row block's base are 32-bit (a row block of Gamma is far below
+  // 4 GiB), so every load takes the uniform base in SGPRs plus one offset VGPR.
+  unsigned ca[4], cb[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    ca[q] = va[q] ? a0 + 16 * q + li : 0;
-    cb[q] = vb[q] ? b0 + 16 * q + li : 0;
+    ca[q] = (unsigned)(va[q] ? a0 + 16 * q + li : 0) * (unsigned)sizeof(TIn);
+    cb[q] = (unsigned)(vb[q] ? b0 + 16 * q + li : 0) * (unsigned)sizeof(TIn);
   }
+  const char* __restrict__ gb = (const char*)base;
+  const unsigned rowbytes = (unsigned)len * (unsigned)sizeof(TIn);
   auto load = [&](int step, TIn (&xa)[4], TIn (&xb)[4], TIn& xd) {
     const int r = r0 + 16 * step + 4 * wave + lk;
     const int rr = r < r1 ? r : r0;
-    const TIn* row = base + (long long)rr * len;
+    const unsigned ro = (unsigned)rr * rowbytes;
     xd = (TIn)Dt[rr];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      xa[q] = row[ca[q]];
-      if constexpr (!DIAG) xb[q] = row[cb[q]];
+      if (q < NIB) xa[q] = *(const TIn*)(gb + (ro + ca[q]));
+      if (!DIAG) xb[q] = *(const TIn*)(gb + (ro + cb[q]));
     }
   };
 #pragma unroll
@@ -274,11 +350,12 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
       TIn sa[4], sb[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        sa[q] = va[q] ? ra[u][q] * d : (TIn)0;
-        sb[q] = vb[q] ? (DIAG ? ra[u][q] : rb[u][q]) : (TIn)0;
+        if (q < NIB) sa[q] = va[q] ? ra[u][q] * d : (TIn)0;
+        if (!DIAG) sb[q] = vb[q] ? rb[u][q] : (TIn)0;
+        else if (q < NIB) sb[q] = vb[q] ? ra[u][q] : (TIn)0;
       }
 #pragma unroll
-      for (int ib = 0; ib < 4; ++ib)
+      for (int ib = 0; ib < NIB; ++ib)
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb)
           if (!DIAG || jb <= ib) acc[ib][jb] = Ops::mma(sa[ib], sb[jb], acc[ib][jb]);
@@ -293,9 +370,10 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
   }
 }
 
-// The jobs [j0, j1) of one workgroup (all on one tile): accumulate, and at a job that
-// carries a slot sum the 4 wavefronts' accumulators in LDS and write the partial tile.
-template <typename TIn, bool DIAG>
+// The jobs [j0, j1) of one workgroup (all on one tile, all with the same number NIB of row
+// blocks reached): accumulate, and at a job that carries a slot sum the 4 wavefronts'
+// accumulators in LDS and write the partial tile.
+template <typename TIn, bool DIAG, int NIB>
 __device__ __forceinline__ void syrk_jobs(const TIn* __restrict__ Gam,
                                           const long long* __restrict__ off,
                                           const double* __restrict__ D,
@@ -320,9 +398,9 @@ __device__ __forceinline__ void syrk_jobs(const TIn* __restrict__ Gam,
     const TIn* __restrict__ base = Gam + off[job.t - 1];
     const double* __restrict__ Dt = D + (long long)(job.t - 1) * ns;
     if constexpr (sizeof(TIn) == 2)
-      syrk_rows_bf16<DIAG>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
+      syrk_rows_bf16<DIAG, NIB>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
     else
-      syrk_rows<TIn, DIAG>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
+      syrk_rows<TIn, DIAG, NIB>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
     if (job.slot >= 0) {
       __syncthreads();
       for (int w = 0; w < 4; ++w) {
@@ -361,12 +439,35 @@ __device__ __forceinline__ void syrk_splitk_body(int bid,
   if (lowflag != nullptr && *lowflag != want_low) return;
   const int j0 = wg_begin[bid], j1 = wg_begin[bid + 1];
   if (j0 >= j1) return;
-  // every job of a workgroup is on the same tile (the planner cuts pieces per tile)
-  const int2 tl = tiles[jobs[j0].tile];
-  if (tl.x == tl.y)
-    syrk_jobs<TIn, true>(Gam, off, D, jobs, j0, j1, tiles, partials, ns, nu, red);
-  else
-    syrk_jobs<TIn, false>(Gam, off, D, jobs, j0, j1, tiles, partials, ns, nu, red);
+  // A workgroup runs one or more pieces, each ending at a job that carries a slot.  Every
+  // job of a piece is on the same tile and reaches the same number of the tile's row blocks
+  // (the planner cuts pieces per tile and where that number changes), so one specialised
+  // loop serves the whole piece.
+  for (int pj = j0; pj < j1;) {
+    int pe = pj;
+    while (pe < j1 - 1 && jobs[pe].slot < 0) ++pe;
+    const int2 tl = tiles[jobs[pj].tile];
+    const int nib = min(4, (jobs[pj].t * nu - 64 * tl.x + 15) >> 4);  // >= 1 (t nu > 64 I)
+#define CMPC_SYRK_JOBS(DIAG, NIB) \
+  syrk_jobs<TIn, DIAG, NIB>(Gam, off, D, jobs, pj, pe + 1, tiles, partials, ns, nu, red)
+    if (tl.x == tl.y) {
+      switch (nib) {
+        case 1: CMPC_SYRK_JOBS(true, 1); break;
+        case 2: CMPC_SYRK_JOBS(true, 2); break;
+        case 3: CMPC_SYRK_JOBS(true, 3); break;
+        default: CMPC_SYRK_JOBS(true, 4); break;
+      }
+    } else {
+      switch (nib) {
+        case 1: CMPC_SYRK_JOBS(false, 1); break;
+        case 2: CMPC_SYRK_JOBS(false, 2); break;
+        case 3: CMPC_SYRK_JOBS(false, 3); break;
+        default: CMPC_SYRK_JOBS(false, 4); break;
+      }
+    }
+    pj = pe + 1;
+  }
+#undef CMPC_SYRK_JOBS
 }
 
 template <typename TIn>
