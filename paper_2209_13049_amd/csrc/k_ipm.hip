@@ -37,13 +37,13 @@ int ipm_alloc_work(Problem& p) {
   p.n_step_blocks = p.n_prep_blocks;
   CMPC_HIP(hipMalloc(&p.norm_part, sizeof(double) * 5 * p.n_prep_blocks));
   CMPC_HIP(hipMalloc(&p.alpha_part, sizeof(double) * 2 * p.n_step_blocks));
-  // Gamma' passes: chunks of rc rows of one row block, enough of them to keep every CU
-  // streaming (64-row chunks unless that makes more than 4096)
+  // Gamma' passes: chunks of rc rows of one row block and one 64-column block, 64-row
+  // chunks unless that makes more than 1024 of them
   int rc = 64;
-  while ((long long)ceil_div(p.ns, rc) * p.N > 4096 && rc < 4096) rc *= 2;
+  while (gt_chunk_count(p.ns, p.nu, p.N, n, rc) > 1024 && rc < 4096) rc *= 2;
   p.gt_rows = rc;
-  p.gt_chunks = ceil_div(p.ns, rc) * p.N;
-  CMPC_HIP(hipMalloc(&p.gt_part, sizeof(double) * 3 * n * (size_t)p.gt_chunks));
+  p.gt_chunks = gt_chunk_count(p.ns, p.nu, p.N, n, rc);
+  CMPC_HIP(hipMalloc(&p.gt_part, sizeof(double) * 3 * 64 * (size_t)p.gt_chunks));
   CMPC_HIP(hipMalloc(&p.red_part, sizeof(double) * 1024));
   CMPC_HIP(hipMalloc(&p.Wdiag, sizeof(double) * 4096 * (size_t)ceil_div(p.n, 64)));
   CMPC_HIP(hipMalloc(&p.st, sizeof(IpmState)));
@@ -52,49 +52,55 @@ int ipm_alloc_work(Problem& p) {
 }
 
 // ---------------------------------------------------------------- Gamma' W  (NV vectors)
-// Partial sums of chunk (t, q): rows [q rc, (q+1) rc) of row block t, columns a < t nu.
-// Threads form TPC columns x RG row groups (TPC = 64, 128 or 256 by the row length), so
-// short rows of early blocks still keep every lane busy; row groups are summed in LDS.
+// out[k][a] = sum_t sum_r Gamma_t[r][a] W[k][t][r] over the row blocks t that reach column a
+// (t nu > a).  Chunk (cb, t, q): column block cb (64 columns), row block t >= gt_tmin(cb),
+// rows [q rc, (q+1) rc); chunks are numbered column block by column block, t ascending,
+// q ascending.  Each chunk writes a partial of 64 columns; a second pass adds the chunks
+// of each column block in a fixed order.
+//
+// In a chunk, lane = column (one 512-byte row segment per wavefront load) and the 4
+// wavefronts take consecutive quarters of the rows, so the weights W[k][t][r] are
+// wavefront-uniform and come through the scalar cache.
 template <int NV>
 __device__ __forceinline__ void gamma_t_partial_body(int bid, 
     const double* __restrict__ Gam, const long long* __restrict__ off,
     const double* __restrict__ W, long long wstride, double* __restrict__ part, int ns, int nu,
-    int n, int rc, int cpb, const int* __restrict__ done) {
-  __shared__ double red[NV][256];
+    int N, int rc, int cpb, const int* __restrict__ done) {
+  __shared__ double red[4][NV][64];
   if (done != nullptr && *done) return;
-  const int chunk = bid;
-  const int t = chunk / cpb + 1, q = chunk - (t - 1) * cpb;
+  int c = bid, cb = 0;
+  for (;; ++cb) {
+    const int cnt = (N - gt_tmin(cb, nu) + 1) * cpb;
+    if (c < cnt) break;
+    c -= cnt;
+  }
+  const int t = gt_tmin(cb, nu) + c / cpb, q = c - (c / cpb) * cpb;
   const int len = t * nu;
-  const int r0 = q * rc, r1 = min(ns, r0 + rc);
-  const int tpc = len <= 64 ? 64 : (len <= 128 ? 128 : 256);
-  const int rgs = 256 / tpc;
-  const int rg = threadIdx.x / tpc, cc = threadIdx.x - rg * tpc;
-  const double* __restrict__ base = Gam + off[t - 1];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int a = 64 * cb + lane;
+  const int ac = a < len ? a : len - 1;  // lanes past the row load a valid entry (dropped)
+  const int quarter = rc >> 2;
+  const int w0 = q * rc + wave * quarter, w1 = min(ns, w0 + quarter);
+  const double* __restrict__ g = Gam + off[t - 1] + ac;
   const double* __restrict__ wb = W + (long long)(t - 1) * ns;
-  for (int cbase = 0; cbase < len; cbase += tpc) {
-    const int a = cbase + cc;
-    const bool va = a < len;
-    double acc[NV];
+  double acc[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
 #pragma unroll 16
-    for (int r = r0 + rg; r < r1; r += rgs) {
-      const double g = va ? base[(long long)r * len + a] : 0.0;
+  for (int r = w0; r < w1; ++r) {
+    const double x = g[(long long)r * len];
 #pragma unroll
-      for (int k = 0; k < NV; ++k) acc[k] = fma(g, wb[k * wstride + r], acc[k]);
-    }
+    for (int k = 0; k < NV; ++k) acc[k] = fma(x, wb[k * wstride + r], acc[k]);
+  }
 #pragma unroll
-    for (int k = 0; k < NV; ++k) red[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    if (rg == 0 && va) {
+  for (int k = 0; k < NV; ++k) red[wave][k][lane] = acc[k];
+  __syncthreads();
+  if (wave == 0) {  // columns past this row block's length get 0 (the reduction adds all)
 #pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        double sum = red[k][cc];
-        for (int g2 = 1; g2 < rgs; ++g2) sum += red[k][g2 * tpc + cc];
-        part[((long long)chunk * NV + k) * n + a] = sum;
-      }
-    }
-    __syncthreads();
+    for (int k = 0; k < NV; ++k)
+      part[((long long)bid * NV + k) * 64 + lane] =
+          a < len ? ((red[0][k][lane] + red[1][k][lane]) + red[2][k][lane]) + red[3][k][lane]
+                  : 0.0;
   }
 }
 
@@ -102,32 +108,31 @@ template <int NV>
 __global__ __launch_bounds__(256) void gamma_t_partial_kernel(
     const double* __restrict__ Gam, const long long* __restrict__ off,
     const double* __restrict__ W, long long wstride, double* __restrict__ part, int ns, int nu,
-    int n, int rc, int cpb, const int* __restrict__ done) {
-  gamma_t_partial_body<NV>(blockIdx.x, Gam, off, W, wstride, part, ns, nu, n, rc, cpb, done);
+    int N, int rc, int cpb, const int* __restrict__ done) {
+  gamma_t_partial_body<NV>(blockIdx.x, Gam, off, W, wstride, part, ns, nu, N, rc, cpb, done);
 }
 
-// out[k][a] = sum over chunks whose block covers column a (fixed order): 16 columns x 16
-// chunk groups per workgroup.
+// out[k][a] for 16 columns a per workgroup: the chunks of their column block, 16 chunk
+// phases summed in a fixed order.
 template <int NV>
 __device__ __forceinline__ void gamma_t_reduce_body(int bid, const double* __restrict__ part,
                                                              double* __restrict__ out, int n,
-                                                             int nu, int cpb, int nchunks,
+                                                             int nu, int N, int cpb,
                                                              const int* __restrict__ done) {
   __shared__ double sh[16][NV][16];
   if (done != nullptr && *done) return;
   const int l = threadIdx.x & 15, g = threadIdx.x >> 4;
-  const int a = bid * 16 + l;
+  const int a = bid * 16 + l, cb = bid >> 2;
+  int c0 = 0;
+  for (int c = 0; c < cb; ++c) c0 += (N - gt_tmin(c, nu) + 1) * cpb;
+  const int cnt = (N - gt_tmin(cb, nu) + 1) * cpb;
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-  if (a < n) {
-    const int tmin = a / nu + 1;  // first block with t nu > a
-    const int c0 = (tmin - 1) * cpb;
 #pragma unroll 4
-    for (int ch = c0 + g; ch < nchunks; ch += 16)
+  for (int i = g; i < cnt; i += 16)
 #pragma unroll
-      for (int k = 0; k < NV; ++k) acc[k] += part[((long long)ch * NV + k) * n + a];
-  }
+    for (int k = 0; k < NV; ++k) acc[k] += part[((long long)(c0 + i) * NV + k) * 64 + (a & 63)];
 #pragma unroll
   for (int k = 0; k < NV; ++k) sh[g][k][l] = acc[k];
   __syncthreads();
@@ -144,27 +149,27 @@ __device__ __forceinline__ void gamma_t_reduce_body(int bid, const double* __res
 template <int NV>
 __global__ __launch_bounds__(256) void gamma_t_reduce_kernel(const double* __restrict__ part,
                                                              double* __restrict__ out, int n,
-                                                             int nu, int cpb, int nchunks,
+                                                             int nu, int N, int cpb,
                                                              const int* __restrict__ done) {
-  gamma_t_reduce_body<NV>(blockIdx.x, part, out, n, nu, cpb, nchunks, done);
+  gamma_t_reduce_body<NV>(blockIdx.x, part, out, n, nu, N, cpb, done);
 }
 
 int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int* done) {
   const int cpb = ceil_div(p.ns, p.gt_rows);
   if (nvec == 3) {
     hipLaunchKernelGGL(gamma_t_partial_kernel<3>, dim3(p.gt_chunks), dim3(256), 0, p.stream,
-                       p.Gam, p.goff, w, (long long)p.mx, p.gt_part, p.ns, p.nu, p.n, p.gt_rows,
+                       p.Gam, p.goff, w, (long long)p.mx, p.gt_part, p.ns, p.nu, p.N, p.gt_rows,
                        cpb, done);
     CMPC_LAUNCH_CHECK();
     hipLaunchKernelGGL(gamma_t_reduce_kernel<3>, dim3(ceil_div(p.n, 16)), dim3(256), 0, p.stream,
-                       p.gt_part, out, p.n, p.nu, cpb, p.gt_chunks, done);
+                       p.gt_part, out, p.n, p.nu, p.N, cpb, done);
   } else {
     hipLaunchKernelGGL(gamma_t_partial_kernel<1>, dim3(p.gt_chunks), dim3(256), 0, p.stream,
-                       p.Gam, p.goff, w, (long long)p.mx, p.gt_part, p.ns, p.nu, p.n, p.gt_rows,
+                       p.Gam, p.goff, w, (long long)p.mx, p.gt_part, p.ns, p.nu, p.N, p.gt_rows,
                        cpb, done);
     CMPC_LAUNCH_CHECK();
     hipLaunchKernelGGL(gamma_t_reduce_kernel<1>, dim3(ceil_div(p.n, 16)), dim3(256), 0, p.stream,
-                       p.gt_part, out, p.n, p.nu, cpb, p.gt_chunks, done);
+                       p.gt_part, out, p.n, p.nu, p.N, cpb, done);
   }
   CMPC_LAUNCH_CHECK();
   return 0;
@@ -850,7 +855,7 @@ __global__ __launch_bounds__(256) void gamma_t_partial_batch_kernel(
     const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems) {
   CMPC_ITEMS_BEGIN
   gamma_t_partial_body<NV>(bid, V.Gam, V.goff, NV == 3 ? V.wx : V.gpv, (long long)V.mx,
-                           V.gt_part, V.ns, V.nu, V.n, V.gt_rows, V.gt_cpb,
+                           V.gt_part, V.ns, V.nu, V.N, V.gt_rows, V.gt_cpb,
                            gate_of(V, NV == 3 ? 0 : 1));
   CMPC_ITEMS_END
 }
@@ -859,8 +864,8 @@ template <int NV>
 __global__ __launch_bounds__(256) void gamma_t_reduce_batch_kernel(
     const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems) {
   CMPC_ITEMS_BEGIN
-  gamma_t_reduce_body<NV>(bid, V.gt_part, NV == 3 ? V.gt : V.ref_gt, V.n, V.nu, V.gt_cpb,
-                          V.gt_chunks, gate_of(V, NV == 3 ? 0 : 1));
+  gamma_t_reduce_body<NV>(bid, V.gt_part, NV == 3 ? V.gt : V.ref_gt, V.n, V.nu, V.N, V.gt_cpb,
+                          gate_of(V, NV == 3 ? 0 : 1));
   CMPC_ITEMS_END
 }
 

@@ -126,6 +126,15 @@ struct InstView {
   const int *slot_begin, *slots;
 };
 
+// Chunks of the Gamma' passes: column block cb (64 columns) is reached by row blocks
+// t >= gt_tmin(cb) (t nu > 64 cb); each such block is cut into ceil(ns / rc) row chunks.
+__host__ __device__ inline int gt_tmin(int cb, int nu) { return (64 * cb) / nu + 1; }
+inline int gt_chunk_count(int ns, int nu, int N, int n, int rc) {
+  long long c = 0;
+  for (int cb = 0; 64 * cb < n; ++cb) c += (long long)(N - gt_tmin(cb, nu) + 1) * ((ns + rc - 1) / rc);
+  return (int)c;
+}
+
 // One entry of a work list: block `local` of instance `inst`.
 struct WorkItem {
   int inst, local;
