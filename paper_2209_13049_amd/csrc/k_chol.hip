@@ -91,6 +91,15 @@ __device__ inline d4 mma16(const double* A, const double* B, d4 c, int li, int l
   return c;
 }
 
+// x from another lane of its quad (DPP quad_perm CTRL, no LDS round trip).
+template <int CTRL>
+__device__ inline double quad_perm_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Inverse W = L^-1 of the lower-triangular tile T.  Wavefront b inverts the diagonal 16 x 16
 // block b by forward substitution (4 lanes per column); the blocks below the diagonal follow
 // by block diagonals d = 1, 2, 3:  W_ij = -W_ii (sum_{k=j}^{i-1} L_ik W_kj), as MFMA products.
@@ -112,8 +121,8 @@ __device__ void inv64(const Tile& T, Tile& W, double* rdiag) {
         const double lk = T[o + ii][o + (k < 16 ? k : 15)];
         part = fma(k < ii ? lk : 0.0, wv[kk], part);
       }
-      part += __shfl_xor(part, 1, 64);
-      part += __shfl_xor(part, 2, 64);
+      part += quad_perm_f64<0xB1>(part);  // lane ^ 1 within the quad
+      part += quad_perm_f64<0x4E>(part);  // lane ^ 2
       const double val = (ii >= c) ? (((ii == c) ? 1.0 : 0.0) - part) * rdiag[o + ii] : 0.0;
       if (p == (ii & 3)) wv[ii >> 2] = val;
     }
