@@ -91,9 +91,9 @@ __device__ inline d4 mma16(const double* A, const double* B, d4 c, int li, int l
   return c;
 }
 
-// x from another lane of its quad (DPP quad_perm CTRL, no LDS round trip).
+// x from another lane by the DPP control CTRL (quad_perm, row rotation; no LDS round trip).
 template <int CTRL>
-__device__ inline double quad_perm_f64(double x) {
+__device__ inline double dpp_f64(double x) {
   const long long b = __double_as_longlong(x);
   const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
   const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
@@ -121,8 +121,8 @@ __device__ void inv64(const Tile& T, Tile& W, double* rdiag) {
         const double lk = T[o + ii][o + (k < 16 ? k : 15)];
         part = fma(k < ii ? lk : 0.0, wv[kk], part);
       }
-      part += quad_perm_f64<0xB1>(part);  // lane ^ 1 within the quad
-      part += quad_perm_f64<0x4E>(part);  // lane ^ 2
+      part += dpp_f64<0xB1>(part);  // lane ^ 1 within the quad
+      part += dpp_f64<0x4E>(part);  // lane ^ 2
       const double val = (ii >= c) ? (((ii == c) ? 1.0 : 0.0) - part) * rdiag[o + ii] : 0.0;
       if (p == (ii & 3)) wv[ii >> 2] = val;
     }
@@ -626,10 +626,8 @@ __device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, 
                                                   const double* __restrict__ b,
                                                   double* __restrict__ x,
                                                   const double* __restrict__ eq,
-                                                  const int* __restrict__ gate) {
-  extern __shared__ double ys[];  // n
-  __shared__ double rs[64];
-  __shared__ double red[16][65];
+                                                  const int* __restrict__ gate, double* ys,
+                                                  double* rs, double (*red)[65]) {
   if (gate != nullptr && *gate) return;
   const int t = threadIdx.x;
   for (int i = t; i < n; i += 1024) ys[i] = eq ? eq[i] * b[i] : b[i];
@@ -721,6 +719,131 @@ __device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, 
   for (int i = t; i < n; i += 1024) x[i] = eq ? eq[i] * ys[i] : ys[i];
 }
 
+// The 16 lanes of each DPP row get the sum of the row's values.
+__device__ inline double rowsum16(double x) {
+  x += dpp_f64<0xB1>(x);   // quad_perm: lane ^ 1
+  x += dpp_f64<0x4E>(x);   // quad_perm: lane ^ 2
+  x += dpp_f64<0x124>(x);  // row_ror:4
+  x += dpp_f64<0x128>(x);  // row_ror:8
+  return x;
+}
+
+// The same two substitutions for n <= 64 NT with NT <= 8 block steps, unrolled so that the
+// loads of the next step are issued early: while step k reduces, multiplies by W_k and passes
+// its barriers, the rows of L (forward: row block k+1 left of the diagonal; backward: column
+// block k-1 below it) and then the next W tile are already in flight to registers.  ys holds
+// 64 NT doubles, zero past n, so rows past n contribute nothing.
+template <int NT>
+__device__ __forceinline__ void potrs_pipe_body(const double* __restrict__ L, int ld, int n,
+                                                const double* __restrict__ Wall,
+                                                const double* __restrict__ b,
+                                                double* __restrict__ x,
+                                                const double* __restrict__ eq,
+                                                const int* __restrict__ gate, double* ys,
+                                                double* rs, double (*red)[65]) {
+  if (gate != nullptr && *gate) return;
+  const int t = threadIdx.x;
+  for (int i = t; i < 64 * NT; i += 1024) ys[i] = i < n ? (eq ? eq[i] * b[i] : b[i]) : 0.0;
+  double lr[4 * NT];
+  double wv[4];
+  {  // ---- forward: L y = b, row i of block k on 16 lanes (a DPP row), column phase g
+    const int i = t >> 4, g = t & 15;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wv[q] = Wall[i * 64 + g + 16 * q];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      const int k0 = 64 * k;
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < 4 * k; ++m) acc = fma(lr[m], ys[g + 16 * m], acc);
+      if (k + 1 < NT) {
+        const double* row = L + (long long)min(k0 + 64 + i, n - 1) * ld + g;
+#pragma unroll
+        for (int m = 0; m < 4 * (k + 1); ++m) lr[m] = row[16 * m];
+      }
+      acc = rowsum16(acc);
+      const bool valid = k0 + i < n;
+      if (g == 0) rs[i] = valid ? ys[k0 + i] - acc : 0.0;
+      __syncthreads();
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v = fma(wv[q], rs[g + 16 * q], v);
+      if (k + 1 < NT) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wv[q] = Wall[(long long)(k + 1) * 4096 + i * 64 + g + 16 * q];
+      }
+      v = rowsum16(v);
+      if (g == 0 && valid) ys[k0 + i] = v;
+      __syncthreads();
+    }
+  }
+  {  // ---- backward: L' x = y, column i of block k, row phase g (one wavefront each)
+    const int i = t & 63, g = t >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wv[q] = Wall[(long long)(NT - 1) * 4096 + (g + 16 * q) * 64 + i];
+#pragma unroll
+    for (int kk = 0; kk < NT; ++kk) {
+      const int k = NT - 1 - kk, k0 = 64 * k;
+      double acc = 0.0;  // rows k0 + 64 + g + 16 m below the block
+#pragma unroll
+      for (int m = 0; m < 4 * kk; ++m) acc = fma(lr[m], ys[k0 + 64 + g + 16 * m], acc);
+      if (k > 0) {
+#pragma unroll
+        for (int m = 0; m < 4 * (kk + 1); ++m)
+          lr[m] = L[(long long)min(k0 + g + 16 * m, n - 1) * ld + k0 - 64 + i];
+      }
+      red[g][i] = acc;
+      __syncthreads();
+      if (g == 0) {
+        double sum = 0.0;
+        for (int q = 0; q < 16; ++q) sum += red[q][i];
+        rs[i] = k0 + i < n ? ys[k0 + i] - sum : 0.0;
+      }
+      __syncthreads();
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v = fma(wv[q], rs[g + 16 * q], v);
+      if (k > 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wv[q] = Wall[(long long)(k - 1) * 4096 + (g + 16 * q) * 64 + i];
+      }
+      red[g][i] = v;
+      __syncthreads();
+      if (g == 0 && k0 + i < n) {
+        double sum = 0.0;
+        for (int q = 0; q < 16; ++q) sum += red[q][i];
+        ys[k0 + i] = sum;
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = t; i < n; i += 1024) x[i] = eq ? eq[i] * ys[i] : ys[i];
+}
+
+// One workgroup solves: the pipelined form up to 8 block steps, the looped form beyond.
+__device__ __forceinline__ void potrs_one_body(const double* __restrict__ L, int ld, int n,
+                                               const double* __restrict__ Wall,
+                                               const double* __restrict__ b,
+                                               double* __restrict__ x,
+                                               const double* __restrict__ eq,
+                                               const int* __restrict__ gate) {
+  extern __shared__ double ys[];  // 64 ceil(n / 64)
+  __shared__ double rs[64];
+  __shared__ double red[16][65];
+  switch ((n + 63) >> 6) {
+    case 1: potrs_pipe_body<1>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
+    case 2: potrs_pipe_body<2>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
+    case 3: potrs_pipe_body<3>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
+    case 4: potrs_pipe_body<4>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
+    case 5: potrs_pipe_body<5>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
+    case 6: potrs_pipe_body<6>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
+    case 7: potrs_pipe_body<7>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
+    case 8: potrs_pipe_body<8>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
+    default: potrs_single_body(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
+  }
+}
+
 constexpr int kPotrsSingleMax = 4096;
 
 __global__ __launch_bounds__(1024) void potrs_single_kernel(const double* __restrict__ L, int ld,
@@ -729,7 +852,7 @@ __global__ __launch_bounds__(1024) void potrs_single_kernel(const double* __rest
                                                             double* __restrict__ x,
                                                             const double* __restrict__ eq,
                                                             const int* __restrict__ gate) {
-  potrs_single_body(L, ld, n, Wall, b, x, eq, gate);
+  potrs_one_body(L, ld, n, Wall, b, x, eq, gate);
 }
 
 // x = (L L')^-1 b (eq != NULL: x = S (L L')^-1 S b).  work: n doubles of scratch (the reduced
@@ -738,7 +861,8 @@ __global__ __launch_bounds__(1024) void potrs_single_kernel(const double* __rest
 int launch_potrs(hipStream_t s, const double* L, int n, int ld, const double* Wall,
                  const double* b, double* x, double* work, const int* done, const double* eq) {
   if (n <= kPotrsSingleMax) {
-    hipLaunchKernelGGL(potrs_single_kernel, dim3(1), dim3(1024), sizeof(double) * (size_t)n, s, L,
+    hipLaunchKernelGGL(potrs_single_kernel, dim3(1), dim3(1024),
+                       sizeof(double) * 64 * (size_t)ceil_div(n, 64), s, L,
                        ld, n, Wall, b, x, eq, done);
     CMPC_LAUNCH_CHECK();
     return 0;
@@ -862,14 +986,15 @@ __global__ __launch_bounds__(1024) void potrs_single_batch_kernel(
   if ((int)blockIdx.x >= nitems) return;
   const WorkItem it = items[blockIdx.x];
   const InstView& V = views[it.inst];
-  potrs_single_body(V.K, V.n, V.n, V.Wdiag, which ? V.ref_res : V.rhs, which ? V.ref_dlt : V.pv,
-                    eq ? V.eqs : nullptr, gate_of(V, which));
+  potrs_one_body(V.K, V.n, V.n, V.Wdiag, which ? V.ref_res : V.rhs, which ? V.ref_dlt : V.pv,
+                 eq ? V.eqs : nullptr, gate_of(V, which));
 }
 
 int launch_b_potrs_single(const ListArg& L, int which, int eq, int nmax) {
   if (L.count <= 0) return 0;
   hipLaunchKernelGGL(potrs_single_batch_kernel, dim3(L.count), dim3(1024),
-                     sizeof(double) * (size_t)nmax, L.stream, L.views, L.items, L.count, which, eq);
+                     sizeof(double) * 64 * (size_t)ceil_div(nmax, 64), L.stream, L.views, L.items,
+                     L.count, which, eq);
   CMPC_LAUNCH_CHECK();
   return 0;
 }
