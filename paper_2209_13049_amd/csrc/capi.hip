@@ -388,8 +388,7 @@ int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
     if (!rc) rc = launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info,
                                &p.st->status, e2, e3, mixed ? &p.st->use_low : nullptr);
     if (!rc) rc = launch_step(p, mixed ? o.max_refine : 0);
-    if (!rc) rc = launch_update(p);
-    if (!rc) rc = launch_publish(p, slot);
+    if (!rc) rc = launch_update_publish(p, slot);
   }
   if (rc) return rc;
   CMPC_HIP(hipEventRecord(p.ev1, p.stream));

@@ -493,10 +493,30 @@ __global__ __launch_bounds__(256) void mu_rhs_kernel(
   mu_rhs_body(blockIdx.x, Hv, h, gt, wu, norm_part, nparts, v, rhs, n, st, fixed_mu);
 }
 
+// Gamma' [wx] partial sums (the first gt_chunks workgroups) and Hv = H v (the rest, 4 rows
+// each) in one launch: the two are independent.
+template <int NV>
+__global__ __launch_bounds__(256) void gamma_t_hv_kernel(
+    const double* __restrict__ Gam, const long long* __restrict__ off,
+    const double* __restrict__ W, long long wstride, double* __restrict__ part, int ns, int nu,
+    int N, int rc, int cpb, int nchunks, const double* __restrict__ H,
+    const double* __restrict__ x, double* __restrict__ y, int n, const int* __restrict__ done) {
+  if ((int)blockIdx.x < nchunks)
+    gamma_t_partial_body<NV>(blockIdx.x, Gam, off, W, wstride, part, ns, nu, N, rc, cpb, done);
+  else
+    hv_body(blockIdx.x - nchunks, H, x, y, n, done);
+}
+
 int launch_mu_rhs(Problem& p) {
   const int* done = &p.st->done;
-  if (launch_gamma_t(p, p.wx, 3, p.gt, done)) return CMPC_ERR_HIP;
-  if (launch_hv(p, p.v, p.Hv, done)) return CMPC_ERR_HIP;
+  const int cpb = ceil_div(p.ns, p.gt_rows);
+  hipLaunchKernelGGL(gamma_t_hv_kernel<3>, dim3(p.gt_chunks + ceil_div(p.n, 4)), dim3(256), 0,
+                     p.stream, p.Gam, p.goff, p.wx, (long long)p.mx, p.gt_part, p.ns, p.nu, p.N,
+                     p.gt_rows, cpb, p.gt_chunks, p.H, p.v, p.Hv, p.n, done);
+  CMPC_LAUNCH_CHECK();
+  hipLaunchKernelGGL(gamma_t_reduce_kernel<3>, dim3(ceil_div(p.n, 16)), dim3(256), 0, p.stream,
+                     p.gt_part, p.gt, p.n, p.nu, p.N, cpb, done);
+  CMPC_LAUNCH_CHECK();
   hipLaunchKernelGGL(mu_rhs_kernel, dim3(1), dim3(256), 0, p.stream, p.Hv, p.h, p.gt, p.wu,
                      p.norm_part, p.n_prep_blocks, p.v, p.rhs, p.n, p.st, 0);
   CMPC_LAUNCH_CHECK();
@@ -655,19 +675,19 @@ __global__ void publish_kernel(IpmState* st, int* flag) {
   __hip_atomic_store(flag, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-int launch_publish(Problem& p, int slot) {
+// The update and the host flag of ring slot `slot` (two launches: the flag needs every
+// workgroup of the update finished, which a last-workgroup tail could only see through a
+// device-scope fence per workgroup, an L2 write-back each, measured slower).
+int launch_update_publish(Problem& p, int slot) {
+  hipLaunchKernelGGL(update_kernel, dim3(p.n_step_blocks), dim3(256), 0, p.stream, p.d, p.s,
+                     p.lam, p.z, p.gv, p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part,
+                     p.n_step_blocks, p.mx, p.n, p.st, 1);
+  CMPC_LAUNCH_CHECK();
   hipLaunchKernelGGL(publish_kernel, dim3(1), dim3(1), 0, p.stream, p.st, p.dflags + slot);
   CMPC_LAUNCH_CHECK();
   return 0;
 }
 
-int launch_update(Problem& p) {
-  hipLaunchKernelGGL(update_kernel, dim3(p.n_step_blocks), dim3(256), 0, p.stream, p.d, p.s,
-                     p.lam, p.z, p.gv, p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part,
-                     p.n_step_blocks, p.mx, p.n, p.st, 1);
-  CMPC_LAUNCH_CHECK();
-  return 0;
-}
 
 // ---------------------------------------------------------------- sigma folding (testing)
 __global__ void sigma_fold_kernel(const double* __restrict__ sigma, const double* __restrict__ xl,

@@ -267,8 +267,7 @@ int launch_ipm_init(Problem& p, const cmpc_options& o);
 int launch_prep(Problem& p);
 int launch_mu_rhs(Problem& p);
 int launch_step(Problem& p, int refine);  // refine: refinement steps queued (mixed modes)
-int launch_update(Problem& p);
-int launch_publish(Problem& p, int slot);
+int launch_update_publish(Problem& p, int slot);  // update + the host flag of ring slot `slot`
 int launch_refine_step(Problem& p);
 int launch_sigma_fold(Problem& p, const double* sigma);
 int launch_step_given(Problem& p, const double* v, const double* s, const double* lam,
