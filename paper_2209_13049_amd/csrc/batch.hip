@@ -235,10 +235,12 @@ static int build_lists(Batch& b) {
   for (int k = 0; k < b.ntmax; ++k) {
     // the launch sequence of one instance: chol_step k for k < nt when nt > 1, with
     // npanel + rows (rows + 1) / 2 workgroups; trsv steps with max(1, nt-k-1) / max(1, k)
-    add(b.chol[k], [k](const InstView& v) {
+    // (+ 1 where the fused forward substitution has a block: one-workgroup solves)
+    const bool fused = b.nmax <= kPotrsSingleMax;
+    add(b.chol[k], [k, fused](const InstView& v) {
       if (v.nt <= 1 || k >= v.nt) return 0;
       const int npanel = k >= 1 ? v.nt - k : 0, rows = v.nt - 1 - k;
-      return npanel + rows * (rows + 1) / 2;
+      return npanel + rows * (rows + 1) / 2 + (fused && fwd_block_at(k, v.nt) >= 0 ? 1 : 0);
     });
     add(b.fwd[k], [k](const InstView& v) { return k < v.nt ? std::max(1, v.nt - k - 1) : 0; });
     add(b.bwd[k], [k](const InstView& v) { return k < v.nt ? std::max(1, k) : 0; });
@@ -261,7 +263,8 @@ static ListArg arg(const Batch& b, const List& L) {
 // (L L')^-1 applied to rhs -> pv (which = 0) or ref_res -> ref_dlt (which = 1); eq: the
 // factor is that of the equilibrated S K S.
 static int enqueue_potrs(Batch& b, int which, int eq) {
-  if (b.nmax <= 4096) return launch_b_potrs_single(arg(b, b.one), which, eq, b.nmax);
+  if (b.nmax <= kPotrsSingleMax)  // which = 0 follows the factorisation's fused forward pass
+    return launch_b_potrs_single(arg(b, b.one), which, eq, b.nmax, 1);
   if (launch_b_potrs_copy(arg(b, b.n256), which, 0, eq)) return CMPC_ERR_HIP;
   for (int k = 0; k < b.ntmax; ++k)
     if (launch_b_trsv_fwd(arg(b, b.fwd[k]), k, which)) return CMPC_ERR_HIP;
@@ -295,7 +298,8 @@ static int enqueue_iteration(Batch& b, int mixed, int refine, int eq) {
   if (eq && launch_b_equilibrate(arg(b, b.n256), arg(b, b.n4))) return CMPC_ERR_HIP;
   if (launch_b_chol_first(arg(b, b.one), mixed)) return CMPC_ERR_HIP;
   for (int k = 0; k < b.ntmax; ++k)
-    if (launch_b_chol_step(arg(b, b.chol[k]), k, mixed)) return CMPC_ERR_HIP;
+    if (launch_b_chol_step(arg(b, b.chol[k]), k, mixed, b.nmax <= kPotrsSingleMax, eq))
+      return CMPC_ERR_HIP;
   if (enqueue_potrs(b, 0, eq)) return CMPC_ERR_HIP;
   for (int r = 0; r < refine; ++r) {
     if (launch_b_gamma_mv(arg(b, b.mx4), 1)) return CMPC_ERR_HIP;

@@ -386,7 +386,8 @@ int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
     if (!rc) rc = launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K, e0, e1, mixed);
     if (!rc && p.eq_on) rc = launch_equilibrate(p.stream, p.K, p.n, p.n, p.eqs, &p.st->done);
     if (!rc) rc = launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info,
-                               &p.st->status, e2, e3, mixed ? &p.st->use_low : nullptr);
+                               &p.st->status, e2, e3, mixed ? &p.st->use_low : nullptr, p.rhs,
+                               p.eq_on ? p.eqs : nullptr, p.tmpn);
     if (!rc) rc = launch_step(p, mixed ? o.max_refine : 0);
     if (!rc) rc = launch_update_publish(p, slot);
   }

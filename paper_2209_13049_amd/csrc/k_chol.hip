@@ -319,17 +319,64 @@ __global__ __launch_bounds__(256) void chol_first_kernel(double* __restrict__ K,
   chol_first_body(blockIdx.x, K, ld, n, Wall, done, info, status, lowflag);
 }
 
+// Forward substitution for row block j on one 256-thread workgroup (4 lanes per row):
+// y_j = W_j (S b_j - sum_{m<j} L_jm y_m), the y_m of earlier blocks read from y.
+__device__ __forceinline__ void fwd_block_body(int j, const double* __restrict__ L, int ld, int n,
+                                               const double* __restrict__ Wall,
+                                               const double* __restrict__ b,
+                                               const double* __restrict__ eq,
+                                               double* __restrict__ y) {
+  __shared__ double rs[64];
+  const int t = threadIdx.x, i = t >> 2, g = t & 3;
+  const int j0 = 64 * j, rows = min(64, n - j0);
+  double acc = 0.0;
+  if (i < rows) {
+    const double* row = L + (long long)(j0 + i) * ld;
+    double acc2 = 0.0;
+    int c = g;
+#pragma unroll 4
+    for (; c + 4 < j0; c += 8) {
+      acc = fma(row[c], y[c], acc);
+      acc2 = fma(row[c + 4], y[c + 4], acc2);
+    }
+    if (c < j0) acc = fma(row[c], y[c], acc);
+    acc += acc2;
+  }
+  acc += dpp_f64<0xB1>(acc);  // quad sum
+  acc += dpp_f64<0x4E>(acc);
+  if (g == 0) rs[i] = i < rows ? (eq ? eq[j0 + i] * b[j0 + i] : b[j0 + i]) - acc : 0.0;
+  __syncthreads();
+  const double* W = Wall + (long long)j * 4096 + i * 64;
+  double v = 0.0;
+#pragma unroll
+  for (int q = g; q < 64; q += 4) v = fma(W[q], rs[q], v);
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  if (g == 0 && i < rows) y[j0 + i] = v;
+}
+
 // Launch k: (A) the panel of block column k-1, L_i,k-1 = A_i,k-1 W_k-1' for i >= k, written
 // now because launch k-1 still read A_i,k-1 while forming its updates; (B) for k <= nt-2 the
 // trailing update with block column k, and the factorisation of the next pivot tile.
+// (C) with fb != NULL, the workgroup after the tiles (launched when fwd_block_at(k, nt) >= 0)
+// runs the forward substitution of that row block, whose row of L the earlier launches
+// completed.
 __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, int ld, int n,
                                                         int k, int nt, double* __restrict__ Wall,
                                                         int* done, int* info, int* status,
-                                                        int* lowflag) {
+                                                        int* lowflag, const double* fb,
+                                                        const double* feq, double* fy) {
   __shared__ Tile Wt, Xi, Xj;
   __shared__ double colb[128], piv[64];
   __shared__ int bad;
   if (*done) return;
+  if (fb != nullptr) {
+    const int rows_t = nt - 1 - k;
+    if (bid == (k >= 1 ? nt - k : 0) + rows_t * (rows_t + 1) / 2) {
+      fwd_block_body(fwd_block_at(k, nt), K, ld, n, Wall, fb, feq, fy);
+      return;
+    }
+  }
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
   const int wr = wave >> 1, wc = wave & 1;
   int b = bid;
@@ -417,12 +464,15 @@ __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, 
 __global__ __launch_bounds__(256) void chol_step_kernel(double* __restrict__ K, int ld, int n,
                                                         int k, int nt, double* __restrict__ Wall,
                                                         int* done, int* info, int* status,
-                                                        int* lowflag) {
-  chol_step_body(blockIdx.x, K, ld, n, k, nt, Wall, done, info, status, lowflag);
+                                                        int* lowflag, const double* fb,
+                                                        const double* feq, double* fy) {
+  chol_step_body(blockIdx.x, K, ld, n, k, nt, Wall, done, info, status, lowflag, fb, feq, fy);
 }
 
 int launch_potrf(hipStream_t s, double* K, int n, int ld, double* Wall, int* done, int* info,
-                 int* status, hipEvent_t ev_start, hipEvent_t ev_stop, int* lowflag) {
+                 int* status, hipEvent_t ev_start, hipEvent_t ev_stop, int* lowflag,
+                 const double* fb, const double* feq, double* fy) {
+  if (n > kPotrsSingleMax) fb = nullptr;
   const int nt = ceil_div(n, 64);
   hipExtLaunchKernelGGL(chol_first_kernel, dim3(1), dim3(256), 0, s, ev_start,
                         nt == 1 ? ev_stop : nullptr, 0, K, ld, n, Wall, done, info, status,
@@ -431,10 +481,10 @@ int launch_potrf(hipStream_t s, double* K, int n, int ld, double* Wall, int* don
   for (int k = 0; k < nt && nt > 1; ++k) {
     const int npanel = k >= 1 ? nt - k : 0;
     const int rows = nt - 1 - k;
-    const int tiles = npanel + rows * (rows + 1) / 2;
+    const int tiles = npanel + rows * (rows + 1) / 2 + (fb != nullptr && fwd_block_at(k, nt) >= 0);
     hipExtLaunchKernelGGL(chol_step_kernel, dim3(tiles), dim3(256), 0, s, (hipEvent_t) nullptr,
                           k == nt - 1 ? ev_stop : nullptr, 0, K, ld, n, k, nt, Wall, done, info,
-                          status, lowflag);
+                          status, lowflag, fb, feq, fy);
     CMPC_LAUNCH_CHECK();
   }
   return 0;
@@ -627,16 +677,18 @@ __device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, 
                                                   double* __restrict__ x,
                                                   const double* __restrict__ eq,
                                                   const int* __restrict__ gate, double* ys,
-                                                  double* rs, double (*red)[65]) {
+                                                  double* rs, double (*red)[65],
+                                                  const double* __restrict__ yf) {
   if (gate != nullptr && *gate) return;
   const int t = threadIdx.x;
-  for (int i = t; i < n; i += 1024) ys[i] = eq ? eq[i] * b[i] : b[i];
-  __syncthreads();
   const int nt = (n + 63) >> 6;
+  const int kf = yf ? max(0, nt - 2) : 0;  // blocks whose y the fused forward pass computed
+  for (int i = t; i < n; i += 1024) ys[i] = i < 64 * kf ? yf[i] : (eq ? eq[i] * b[i] : b[i]);
+  __syncthreads();
   // ---- forward: L y = b
   {
     const int i = t >> 4, g = t & 15;  // row of the block, column phase
-    for (int k = 0; k < nt; ++k) {
+    for (int k = kf; k < nt; ++k) {
       const int k0 = 64 * k;
       const int rows = min(64, n - k0);
       const double* W = Wall + (long long)k * 4096;
@@ -740,13 +792,17 @@ __device__ __forceinline__ void potrs_pipe_body(const double* __restrict__ L, in
                                                 double* __restrict__ x,
                                                 const double* __restrict__ eq,
                                                 const int* __restrict__ gate, double* ys,
-                                                double* rs, double (*red)[65]) {
+                                                double* rs, double (*red)[65],
+                                                const double* __restrict__ yf) {
   if (gate != nullptr && *gate) return;
   const int t = threadIdx.x;
-  for (int i = t; i < 64 * NT; i += 1024) ys[i] = i < n ? (eq ? eq[i] * b[i] : b[i]) : 0.0;
+  const int kf = yf ? (NT > 2 ? NT - 2 : 0) : 0;  // blocks done by the fused forward pass
+  for (int i = t; i < 64 * NT; i += 1024)
+    ys[i] = i < 64 * kf ? yf[i] : (i < n ? (eq ? eq[i] * b[i] : b[i]) : 0.0);
   double lr[4 * NT];
   double wv[4];
-  {  // ---- forward: L y = b, row i of block k on 16 lanes (a DPP row), column phase g
+  {  // ---- forward: L y = b, row i of block k on 16 lanes (a DPP row), column phase g; with
+     // yf only the blocks from kf on (their loads still issued one step ahead)
     const int i = t >> 4, g = t & 15;
 #pragma unroll
     for (int q = 0; q < 4; ++q) wv[q] = Wall[i * 64 + g + 16 * q];
@@ -754,28 +810,36 @@ __device__ __forceinline__ void potrs_pipe_body(const double* __restrict__ L, in
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
       const int k0 = 64 * k;
+      const bool run = k >= kf;  // uniform
+      const bool next = k + 1 < NT && k + 1 >= kf;
       double acc = 0.0;
+      if (run) {
 #pragma unroll
-      for (int m = 0; m < 4 * k; ++m) acc = fma(lr[m], ys[g + 16 * m], acc);
-      if (k + 1 < NT) {
+        for (int m = 0; m < 4 * k; ++m) acc = fma(lr[m], ys[g + 16 * m], acc);
+      }
+      if (next) {
         const double* row = L + (long long)min(k0 + 64 + i, n - 1) * ld + g;
 #pragma unroll
         for (int m = 0; m < 4 * (k + 1); ++m) lr[m] = row[16 * m];
       }
-      acc = rowsum16(acc);
-      const bool valid = k0 + i < n;
-      if (g == 0) rs[i] = valid ? ys[k0 + i] - acc : 0.0;
-      __syncthreads();
       double v = 0.0;
+      const bool valid = k0 + i < n;
+      if (run) {
+        acc = rowsum16(acc);
+        if (g == 0) rs[i] = valid ? ys[k0 + i] - acc : 0.0;
+        __syncthreads();
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v = fma(wv[q], rs[g + 16 * q], v);
-      if (k + 1 < NT) {
+        for (int q = 0; q < 4; ++q) v = fma(wv[q], rs[g + 16 * q], v);
+      }
+      if (next) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) wv[q] = Wall[(long long)(k + 1) * 4096 + i * 64 + g + 16 * q];
       }
-      v = rowsum16(v);
-      if (g == 0 && valid) ys[k0 + i] = v;
-      __syncthreads();
+      if (run) {
+        v = rowsum16(v);
+        if (g == 0 && valid) ys[k0 + i] = v;
+        __syncthreads();
+      }
     }
   }
   {  // ---- backward: L' x = y, column i of block k, row phase g (one wavefront each)
@@ -827,43 +891,44 @@ __device__ __forceinline__ void potrs_one_body(const double* __restrict__ L, int
                                                const double* __restrict__ b,
                                                double* __restrict__ x,
                                                const double* __restrict__ eq,
-                                               const int* __restrict__ gate) {
+                                               const int* __restrict__ gate,
+                                               const double* __restrict__ yf) {
   extern __shared__ double ys[];  // 64 ceil(n / 64)
   __shared__ double rs[64];
   __shared__ double red[16][65];
   switch ((n + 63) >> 6) {
-    case 1: potrs_pipe_body<1>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
-    case 2: potrs_pipe_body<2>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
-    case 3: potrs_pipe_body<3>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
-    case 4: potrs_pipe_body<4>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
-    case 5: potrs_pipe_body<5>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
-    case 6: potrs_pipe_body<6>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
-    case 7: potrs_pipe_body<7>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
-    case 8: potrs_pipe_body<8>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
-    default: potrs_single_body(L, ld, n, Wall, b, x, eq, gate, ys, rs, red); break;
+    case 1: potrs_pipe_body<1>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
+    case 2: potrs_pipe_body<2>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
+    case 3: potrs_pipe_body<3>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
+    case 4: potrs_pipe_body<4>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
+    case 5: potrs_pipe_body<5>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
+    case 6: potrs_pipe_body<6>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
+    case 7: potrs_pipe_body<7>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
+    case 8: potrs_pipe_body<8>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
+    default: potrs_single_body(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
   }
 }
-
-constexpr int kPotrsSingleMax = 4096;
 
 __global__ __launch_bounds__(1024) void potrs_single_kernel(const double* __restrict__ L, int ld,
                                                             int n, const double* __restrict__ Wall,
                                                             const double* __restrict__ b,
                                                             double* __restrict__ x,
                                                             const double* __restrict__ eq,
-                                                            const int* __restrict__ gate) {
-  potrs_one_body(L, ld, n, Wall, b, x, eq, gate);
+                                                            const int* __restrict__ gate,
+                                                            const double* __restrict__ yf) {
+  potrs_one_body(L, ld, n, Wall, b, x, eq, gate, yf);
 }
 
 // x = (L L')^-1 b (eq != NULL: x = S (L L')^-1 S b).  work: n doubles of scratch (the reduced
 // right-hand side) for the block-step form; x may alias b.  n <= 4096 takes the one-launch
 // form (the vector in LDS, at most 32 KB).
 int launch_potrs(hipStream_t s, const double* L, int n, int ld, const double* Wall,
-                 const double* b, double* x, double* work, const int* done, const double* eq) {
+                 const double* b, double* x, double* work, const int* done, const double* eq,
+                 const double* yf) {
   if (n <= kPotrsSingleMax) {
     hipLaunchKernelGGL(potrs_single_kernel, dim3(1), dim3(1024),
                        sizeof(double) * 64 * (size_t)ceil_div(n, 64), s, L,
-                       ld, n, Wall, b, x, eq, done);
+                       ld, n, Wall, b, x, eq, done, yf);
     CMPC_LAUNCH_CHECK();
     return 0;
   }
@@ -905,14 +970,18 @@ __global__ __launch_bounds__(256) void chol_first_batch_kernel(const InstView* _
                   mixed ? &V.st->use_low : nullptr);
 }
 
+// fused: the list holds one more item per instance where fwd_block_at(k, nt) >= 0: the
+// forward substitution of that row block of L y = S rhs into tmpn.
 __global__ __launch_bounds__(256) void chol_step_batch_kernel(const InstView* __restrict__ views,
                                                               const WorkItem* __restrict__ items,
-                                                              int nitems, int k, int mixed) {
+                                                              int nitems, int k, int mixed,
+                                                              int fused, int eq) {
   if ((int)blockIdx.x >= nitems) return;
   const WorkItem it = items[blockIdx.x];
   const InstView& V = views[it.inst];
   chol_step_body(it.local, V.K, V.n, V.n, k, V.nt, V.Wdiag, &V.st->done, &V.st->info,
-                 &V.st->status, mixed ? &V.st->use_low : nullptr);
+                 &V.st->status, mixed ? &V.st->use_low : nullptr, fused ? V.rhs : nullptr,
+                 eq ? V.eqs : nullptr, V.tmpn);
 }
 
 // dir 0: tmpn = b (b = rhs or ref_res); dir 1: x = tmpn (x = pv or ref_dlt).  Items over
@@ -974,27 +1043,27 @@ int launch_b_chol_first(const ListArg& L, int mixed) {
   M.persistent = 0;  // one item per workgroup
   CMPC_LAUNCH_LIST(chol_first_batch_kernel, M, mixed);
 }
-int launch_b_chol_step(const ListArg& L, int k, int mixed) {
+int launch_b_chol_step(const ListArg& L, int k, int mixed, int fused, int eq) {
   ListArg M = L;
   M.persistent = 0;
-  CMPC_LAUNCH_LIST(chol_step_batch_kernel, M, k, mixed);
+  CMPC_LAUNCH_LIST(chol_step_batch_kernel, M, k, mixed, fused, eq);
 }
 // Whole solve of one instance per workgroup (1024 threads, the instance's vector in LDS).
 __global__ __launch_bounds__(1024) void potrs_single_batch_kernel(
     const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems, int which,
-    int eq) {
+    int eq, int fused) {
   if ((int)blockIdx.x >= nitems) return;
   const WorkItem it = items[blockIdx.x];
   const InstView& V = views[it.inst];
   potrs_one_body(V.K, V.n, V.n, V.Wdiag, which ? V.ref_res : V.rhs, which ? V.ref_dlt : V.pv,
-                 eq ? V.eqs : nullptr, gate_of(V, which));
+                 eq ? V.eqs : nullptr, gate_of(V, which), fused && !which ? V.tmpn : nullptr);
 }
 
-int launch_b_potrs_single(const ListArg& L, int which, int eq, int nmax) {
+int launch_b_potrs_single(const ListArg& L, int which, int eq, int nmax, int fused) {
   if (L.count <= 0) return 0;
   hipLaunchKernelGGL(potrs_single_batch_kernel, dim3(L.count), dim3(1024),
                      sizeof(double) * 64 * (size_t)ceil_div(nmax, 64), L.stream, L.views, L.items,
-                     L.count, which, eq);
+                     L.count, which, eq, fused);
   CMPC_LAUNCH_CHECK();
   return 0;
 }

@@ -583,8 +583,9 @@ __global__ __launch_bounds__(256) void step_kernel(
 
 int launch_step(Problem& p, int refine) {
   const int* done = &p.st->done;
+  // the factorisation ran the forward substitution of rhs into tmpn (one-workgroup sizes)
   if (launch_potrs(p.stream, p.K, p.n, p.n, p.Wdiag, p.rhs, p.pv, p.tmpn, done,
-                   p.eq_on ? p.eqs : nullptr))
+                   p.eq_on ? p.eqs : nullptr, p.n <= kPotrsSingleMax ? p.tmpn : nullptr))
     return CMPC_ERR_HIP;
   for (int r = 0; r < refine; ++r)
     if (launch_refine_step(p)) return CMPC_ERR_HIP;
@@ -829,7 +830,8 @@ int launch_step_given(Problem& p, const double* v, const double* s, const double
                      p.norm_part, p.n_prep_blocks, p.v, p.rhs, p.n, p.st, 1);
   CMPC_LAUNCH_CHECK();
   if (launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K)) return CMPC_ERR_HIP;
-  if (launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info, &p.st->status))
+  if (launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info, &p.st->status,
+                   nullptr, nullptr, nullptr, p.rhs, nullptr, p.tmpn))
     return CMPC_ERR_HIP;
   if (launch_step(p, 0)) return CMPC_ERR_HIP;
   hipLaunchKernelGGL(update_kernel, dim3(1), dim3(256), 0, p.stream, p.d, p.s, p.lam, p.z, p.gv,

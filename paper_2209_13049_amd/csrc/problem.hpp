@@ -206,11 +206,11 @@ int launch_b_syrk(const ListArg& L, int fp32, int mixed, int want_low);
 int launch_b_finish(const ListArg& L);
 int launch_b_equilibrate(const ListArg& Ln256, const ListArg& Ln4);
 int launch_b_chol_first(const ListArg& L, int mixed);
-int launch_b_chol_step(const ListArg& L, int k, int mixed);
+int launch_b_chol_step(const ListArg& L, int k, int mixed, int fused, int eq);
 int launch_b_potrs_copy(const ListArg& L, int which, int dir, int eq);
 // the whole solve of each instance of the list (one item per instance) in one workgroup;
 // nmax: the largest n of the batch (LDS size)
-int launch_b_potrs_single(const ListArg& L, int which, int eq, int nmax);
+int launch_b_potrs_single(const ListArg& L, int which, int eq, int nmax, int fused);
 int launch_b_trsv_fwd(const ListArg& L, int k, int which);
 int launch_b_trsv_bwd(const ListArg& L, int k, int which);
 
@@ -247,14 +247,29 @@ int launch_convert_gamma(Problem& p, int precision);
 // ev_start / ev_stop (optional): timing events attached to the first and last dispatch.
 // lowflag (optional): if it is set when a pivot fails, it is cleared and *done = 2 (redo the
 // iteration in FP64) instead of reporting the breakdown.
+// fb != NULL (n <= kPotrsSingleMax): the launches also run the forward substitution
+// L y = S fb (S = diag(feq), or 1) for every row block but the last two, one extra workgroup
+// per launch (fwd_block_at) as soon as the block's row of L is complete, into fy (n doubles);
+// launch_potrs with yf = fy then finishes the last two blocks and the backward substitution.
 int launch_potrf(hipStream_t s, double* K, int n, int ld, double* Wall, int* done, int* info,
                  int* status, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
-                 int* lowflag = nullptr);
+                 int* lowflag = nullptr, const double* fb = nullptr, const double* feq = nullptr,
+                 double* fy = nullptr);
+constexpr int kPotrsSingleMax = 4096;  // one-workgroup solves (and the fused forward) up to here
+// Row block whose forward substitution Cholesky launch k (0 <= k < nt) runs, or -1: row block
+// j's row of L is complete after launch j (panel L_j,j-1), so block 0 runs in launch 0 and
+// block j >= 1 in launch j + 1; the last two blocks are left to the solve kernel.
+__host__ __device__ inline int fwd_block_at(int k, int nt) {
+  const int j = k == 0 ? 0 : k - 1;
+  return (k != 1 && j <= nt - 3) ? j : -1;
+}
 // x = (L L')^-1 b with n doubles of scratch `work` (distinct from b and x); x may alias b.
 // eq != NULL: L is the factor of the equilibrated S K S (S = diag(eq)) and x = S (L L')^-1 S b.
+// yf != NULL (n <= kPotrsSingleMax): y of every row block but the last two is already in yf
+// (launch_potrf's fused forward substitution with the same b and eq).
 int launch_potrs(hipStream_t s, const double* L, int n, int ld, const double* Wall,
                  const double* b, double* x, double* work, const int* done,
-                 const double* eq = nullptr);
+                 const double* eq = nullptr, const double* yf = nullptr);
 // Diagonal equilibration in place: eq_i = K_ii^-1/2, K_ij <- eq_i K_ij eq_j (lower triangle).
 int launch_equilibrate(hipStream_t s, double* K, int n, int ld, double* eq, const int* done);
 int launch_tri_inv(hipStream_t s, const double* L, int n, int ld, double* Wall);
