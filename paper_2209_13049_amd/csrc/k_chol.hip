@@ -48,6 +48,29 @@ __device__ inline void load_tile(const double* __restrict__ K, int ld, int n, in
   }
 }
 
+// Wt <- W_k (64 x 64, contiguous), A <- tile (ra, ca) of K, B <- tile (rb, cb) if wantB (entries
+// past n as 0): all of a thread's loads are issued before its first LDS store.
+__device__ inline void load_w_tiles(const double* __restrict__ Wk, Tile& Wt,
+                                    const double* __restrict__ K, int ld, int n, int ra, int ca,
+                                    Tile& A, bool wantB, int rb, int cb, Tile& B) {
+  double vw[16], va[16], vb[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int i = e >> 6, j = e & 63;
+    vw[q] = Wk[e];
+    va[q] = (ra + i < n && ca + j < n) ? K[(long long)(ra + i) * ld + ca + j] : 0.0;
+    vb[q] = (wantB && rb + i < n && cb + j < n) ? K[(long long)(rb + i) * ld + cb + j] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    Wt[e >> 6][e & 63] = vw[q];
+    A[e >> 6][e & 63] = va[q];
+    if (wantB) B[e >> 6][e & 63] = vb[q];
+  }
+}
+
 // acc (per wavefront: its 32 x 32 quadrant, 2 x 2 blocks of 16 x 16) = A B'
 __device__ inline void mma_abt(const Tile& A, const Tile& B, d4 (&acc)[2][2], int wr, int wc,
                                int li, int lk) {
@@ -216,8 +239,14 @@ __device__ __forceinline__ void chol_panels(double (&r)[16], double* pan /* 2 x 
 // Factor the SPD tile T in place (lower triangle -> L, strict upper -> 0) and write its
 // inverse to W.  Rows >= nvalid are identity padding.  Returns false (uniformly) and the
 // 0-based failing column in *bad if a pivot is not positive and finite.
+__device__ inline void write_tile_lower(double* __restrict__ K, int ld, int n, int r0, int c0,
+                                        const Tile& T, bool diag);
+
+// ... and stores the factor tile to K at (r0, c0) (lower triangle) as soon as it is scaled,
+// so that the stores drain while the inverse is formed.
 __device__ __forceinline__ bool chol_inv64(Tile& T, Tile& W, double* colb, double* piv, int nvalid,
-                                           int* bad) {
+                                           int* bad, double* __restrict__ K, int ld, int n, int r0,
+                                           int c0) {
   __shared__ double pan[512], pinv[8];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   // ---- factorisation: wavefront w holds columns 16w..16w+15 of row `lane` in registers
@@ -255,6 +284,7 @@ __device__ __forceinline__ bool chol_inv64(Tile& T, Tile& W, double* colb, doubl
     T[i][k] = (k <= i) ? r[kk] * colb[k] : 0.0;
   }
   __syncthreads();
+  write_tile_lower(K, ld, n, r0, c0, T, true);
   inv64(T, W, piv);
   return true;
 }
@@ -305,11 +335,10 @@ __device__ __forceinline__ void chol_first_body(int bid, double* __restrict__ K,
   load_tile(K, ld, n, 0, 0, T);
   __syncthreads();
   const int nvalid = n < 64 ? n : 64;
-  if (!chol_inv64(T, W, colb, piv, nvalid, &bad)) {
+  if (!chol_inv64(T, W, colb, piv, nvalid, &bad, K, ld, n, 0, 0)) {
     if (threadIdx.x == 0) chol_fail(bad + 1, done, info, status, lowflag);
     return;
   }
-  write_tile_lower(K, ld, n, 0, 0, T, true);
   write_w(Wall, W);
 }
 
@@ -403,9 +432,11 @@ __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, 
   const int ti = k + 1 + I, tj = k + 1 + J;
   const int r0 = 64 * ti, c0 = 64 * tj, k0 = 64 * k;
   const bool diag = ti == tj;
-  load_w(Wall + (long long)k * 4096, Wt);
-  load_tile(K, ld, n, r0, k0, Xi);
-  if (!diag) load_tile(K, ld, n, c0, k0, Xj);
+  const bool pivot = diag && ti == k + 1;
+  // Xj: tile (tj, k) for an off-diagonal tile; for the next pivot tile its own A_ij, loaded
+  // now with the rest (a diagonal tile's product uses Xi twice)
+  load_w_tiles(Wall + (long long)k * 4096, Wt, K, ld, n, r0, k0, Xi, !diag || pivot,
+               diag ? r0 : c0, diag ? c0 : k0, Xj);
   __syncthreads();
   mma_abt(Xi, Wt, acc, wr, wc, li, lk);  // X_i = A_ik W_k'
   d4 accj[2][2];
@@ -416,7 +447,7 @@ __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, 
   __syncthreads();
   mma_abt(Xi, diag ? Xi : Xj, acc, wr, wc, li, lk);  // X_i X_j'
   __syncthreads();
-  if (!(diag && ti == k + 1)) {
+  if (!pivot) {
     if (diag && wc > wr) return;
     double old[2][2][4];
 #pragma unroll
@@ -441,9 +472,7 @@ __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, 
         }
     return;
   }
-  // the next pivot tile: update in LDS, factor, invert, publish
-  load_tile(K, ld, n, r0, c0, Xj);
-  __syncthreads();
+  // the next pivot tile (already in Xj): update in LDS, factor, invert, publish
 #pragma unroll
   for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
@@ -453,11 +482,10 @@ __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, 
         Xj[32 * wr + 16 * ib + lk + 4 * v][32 * wc + 16 * jb + li] -= acc[ib][jb][v];
   __syncthreads();
   const int nvalid = n - r0 < 64 ? n - r0 : 64;
-  if (!chol_inv64(Xj, Xi, colb, piv, nvalid, &bad)) {
+  if (!chol_inv64(Xj, Xi, colb, piv, nvalid, &bad, K, ld, n, r0, c0)) {
     if (threadIdx.x == 0) chol_fail(r0 + bad + 1, done, info, status, lowflag);
     return;
   }
-  write_tile_lower(K, ld, n, r0, c0, Xj, true);
   write_w(Wall + (long long)(k + 1) * 4096, Xi);
 }
 
