@@ -183,6 +183,28 @@ def test_full_solve(problems, name):
     assert abs(res["gap"] - ref.gap) <= 1e-6 * max(ref.gap, 1e-12) + 1e-12
 
 
+@pytest.mark.parametrize("dims", [(40, 8, 40), (30, 10, 60), (20, 13, 50)])
+def test_full_solve_many_tiles(lib, dims):
+    """Solves whose K spans 5, 10 and 11 (ragged) 64-row tiles: the factorisation's fused
+    forward substitution (blocks up to nt-3 inside the Cholesky launches) followed by the
+    unrolled (nt <= 8) and the looped (nt > 8) one-workgroup solve, against the oracle."""
+    ns, nu, N = dims
+    p = W.heat1d(ns, nu, N, seed=(17, ns))
+    gp = condmpc.Problem(p)
+    gp.set_x0(p.x0)
+    ref = oracle.solve(p)
+    res = gp.solve()
+    u, x = gp.solution()
+    gp.close()
+    print(f"[parity] n={nu * N}: gpu iters {res['iters']} obj {res['obj']:.12e} | "
+          f"oracle iters {ref.iters} obj {ref.obj:.12e}", flush=True)
+    assert res["status"] == condmpc.OK == ref.status
+    assert res["iters"] == ref.iters
+    assert abs(res["obj"] - ref.obj) <= 1e-8 * max(1.0, abs(ref.obj))
+    assert res["primal_res"] <= 1e-8 and res["dual_res"] <= 1e-8 and res["compl_res"] <= 1e-8
+    assert rel_err(u, ref.v) <= 1e-6
+
+
 def test_repeat_solve_is_deterministic(problems):
     p, gp, red = problems["wide"]
     r1 = gp.solve()
