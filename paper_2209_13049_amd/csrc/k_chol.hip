@@ -30,6 +30,13 @@ __device__ inline double recip(double x) {
   return fma(r, e, r);
 }
 
+// 1/x from the hardware estimate and one Newton-Raphson step (relative error ~2^-52: the
+// elimination's pivot reciprocals, whose columns are rescaled exactly at the end).
+__device__ inline double recip1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // All 16 loads of a thread are issued before the first LDS store, so their latencies overlap
 // (a load-store-load loop waits for each load in turn).
 __device__ inline void load_tile(const double* __restrict__ K, int ld, int n, int r0, int c0,
@@ -179,60 +186,83 @@ __device__ inline double readlane_f64(double x, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Right-looking factorisation of the tile, 4 columns per barrier, for the wavefront holding
-// columns 16 W .. 16 W + 15 of row i (lane i).  The wavefront owning a 4-column panel
-// eliminates it in registers (pivots and panel entries broadcast by readlane), publishes
-// the 4 unscaled columns and pivot reciprocals in LDS, and every wavefront applies the
-// rank-4 update to its later columns.  Entries above the diagonal are updated too (they
-// never feed an entry on or below it and are discarded), so the only tests are static.
+// Right-looking factorisation of the tile in 16 panels of 4 columns, one barrier per panel.
+// Panels are dealt round robin: wavefront W holds panels W, W+4, W+8, W+12 (local panel m =
+// global panel 4m + W, columns 16m + 4W .. 16m + 4W + 3) of row i (lane i) in registers, so
+// consecutive panels have different owners.  Between barriers P and P+1 (panel P published
+// in LDS): the owner of panel P+1 applies panel P to that panel only, eliminates it
+// (pivots and panel entries broadcast by readlane) and publishes it; its update of its other
+// columns by panel P waits for the next interval, where it is not the owner; every other
+// wavefront applies panel P (and a panel it deferred) to its later columns meanwhile.  The
+// critical path per panel is one 4-column update, the elimination and the barrier.  Panels
+// are published unscaled with their pivot reciprocals (LDL'-like updates, the scaling by
+// 1/sqrt(pivot) follows at the end); entries above the diagonal are updated too (they never
+// feed an entry on or below it and are discarded), so the only tests are static.
 template <int W>
-__device__ __forceinline__ void chol_panels(double (&r)[16], double* pan /* 2 x 64 x 4 */,
-                                            double* pinv /* 2 x 4 */, double* piv, int i,
+__device__ __forceinline__ void chol_panels(double (&r)[16], double* pan /* 3 x 64 x 4 */,
+                                            double* pinv /* 3 x 4 */, double* piv, int i,
                                             int t) {
+  // eliminate global panel P (owned by this wavefront: P % 4 == W)
+  auto eliminate = [&](int P) {
+    const int m = P >> 2;
+    double* pb = pan + (P % 3) * 256;
+    double* ib = pinv + (P % 3) * 4;
+    double pv[4], ipv[4];
 #pragma unroll
-  for (int P = 0; P < 16; ++P) {
-    double* pb = pan + (P & 1) * 256;
-    double* ib = pinv + (P & 1) * 4;
-    if (W == (P >> 2)) {
-      const int c0 = 4 * (P & 3);
+    for (int jj = 0; jj < 4; ++jj) {
+      const double p = readlane_f64(r[4 * m + jj], 4 * P + jj);
+      const double ip = recip1(p);
+      const double lij = r[4 * m + jj] * ip;
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int j = 4 * P + jj;
-        const double p = readlane_f64(r[c0 + jj], j);
-        const double ip = recip(p);
-        const double lij = r[c0 + jj] * ip;
-#pragma unroll
-        for (int kk = jj + 1; kk < 4; ++kk)
-          r[c0 + kk] = fma(-lij, readlane_f64(r[c0 + jj], 4 * P + kk), r[c0 + kk]);
-        if (t == 64 * W) {
-          piv[j] = p;
-          ib[jj] = ip;
-        }
-      }
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) pb[4 * i + jj] = r[c0 + jj];
+      for (int kk = jj + 1; kk < 4; ++kk)
+        r[4 * m + kk] = fma(-lij, readlane_f64(r[4 * m + jj], 4 * P + kk), r[4 * m + kk]);
+      pv[jj] = p;
+      ipv[jj] = ip;
     }
-    __syncthreads();
-    if (16 * W + 15 > 4 * P + 3) {
-      double li[4], ipv[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) pb[4 * i + jj] = r[4 * m + jj];
+    if (t == 64 * W) {
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
-        li[jj] = pb[4 * i + jj];
-        ipv[jj] = ib[jj];
+        piv[4 * P + jj] = pv[jj];
+        ib[jj] = ipv[jj];
       }
+    }
+  };
+  // apply published panel Q to this wavefront's panels g with lo <= g <= hi (global indices)
+  auto apply = [&](int Q, int lo, int hi) {
+    const double* pb = pan + (Q % 3) * 256;
+    const double* ib = pinv + (Q % 3) * 4;
+    double li[4];
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) li[jj] *= ipv[jj];
+    for (int jj = 0; jj < 4; ++jj) li[jj] = pb[4 * i + jj] * ib[jj];
 #pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        if (16 * W + kk > 4 * P + 3) {
-          const double* pk = pb + 4 * (16 * W + kk);
-          double acc = r[kk];
+    for (int m = 0; m < 4; ++m) {
+      const int g = 4 * m + W;
+      if (g >= lo && g <= hi) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double* pk = pb + 4 * (4 * g + c);
+          double acc = r[4 * m + c];
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj) acc = fma(-li[jj], pk[jj], acc);
-          r[kk] = acc;
+          r[4 * m + c] = acc;
         }
       }
     }
+  };
+  if (W == 0) eliminate(0);
+  __syncthreads();
+#pragma unroll
+  for (int P = 0; P < 15; ++P) {
+    if (W == (P + 1) % 4) {  // owner of panel P+1
+      apply(P, P + 1, P + 1);
+      eliminate(P + 1);
+    } else {
+      if (P >= 1 && W == P % 4) apply(P - 1, P + 1, 15);  // deferred while owning panel P
+      apply(P, P + 1, 15);
+    }
+    __syncthreads();
   }
 }
 
@@ -247,14 +277,15 @@ __device__ inline void write_tile_lower(double* __restrict__ K, int ld, int n, i
 __device__ __forceinline__ bool chol_inv64(Tile& T, Tile& W, double* colb, double* piv, int nvalid,
                                            int* bad, double* __restrict__ K, int ld, int n, int r0,
                                            int c0) {
-  __shared__ double pan[512], pinv[8];
+  __shared__ double pan[768], pinv[12];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  // ---- factorisation: wavefront w holds columns 16w..16w+15 of row `lane` in registers
+  // ---- factorisation: wavefront w holds panels w, w+4, w+8, w+12 of row `lane` in
+  // registers (r[4m + c]: column 16m + 4w + c)
   const int i = lane;
   double r[16];
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
-    const int k = 16 * w + kk;
+    const int k = 16 * (kk >> 2) + 4 * w + (kk & 3);
     double x = (k <= i) ? T[i][k] : 0.0;
     if (i >= nvalid) x = (k == i) ? 1.0 : 0.0;
     r[kk] = x;
@@ -280,7 +311,7 @@ __device__ __forceinline__ bool chol_inv64(Tile& T, Tile& W, double* colb, doubl
   if (*bad < 64) return false;
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
-    const int k = 16 * w + kk;
+    const int k = 16 * (kk >> 2) + 4 * w + (kk & 3);
     T[i][k] = (k <= i) ? r[kk] * colb[k] : 0.0;
   }
   __syncthreads();
