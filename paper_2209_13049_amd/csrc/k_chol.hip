@@ -188,8 +188,8 @@ __device__ inline double readlane_f64(double x, int lane) {
 
 // Right-looking factorisation of the tile in 16 panels of 4 columns, one barrier per panel.
 // Panels are dealt round robin: wavefront W holds panels W, W+4, W+8, W+12 (local panel m =
-// global panel 4m + W, columns 16m + 4W .. 16m + 4W + 3) of row i (lane i) in registers, so
-// consecutive panels have different owners.  Between barriers P and P+1 (panel P published
+// global panel 4m + W, columns 16m + 4W .. 16m + 4W + 3) of row i (lane i) in registers
+// (r[4m + c]), so consecutive panels have different owners.  Between barriers P and P+1 (panel P published
 // in LDS): the owner of panel P+1 applies panel P to that panel only, eliminates it
 // (pivots and panel entries broadcast by readlane) and publishes it; its update of its other
 // columns by panel P waits for the next interval, where it is not the owner; every other
@@ -198,55 +198,59 @@ __device__ inline double readlane_f64(double x, int lane) {
 // are published unscaled with their pivot reciprocals (LDL'-like updates, the scaling by
 // 1/sqrt(pivot) follows at the end); entries above the diagonal are updated too (they never
 // feed an entry on or below it and are discarded), so the only tests are static.
+constexpr int kPW = 4;        // panel width (8 measured slower: longer eliminations)
+constexpr int kNP = 64 / kPW;  // panels per tile
+constexpr int kLP = kNP / 4;   // panels per wavefront
 template <int W>
-__device__ __forceinline__ void chol_panels(double (&r)[16], double* pan /* 3 x 64 x 4 */,
-                                            double* pinv /* 3 x 4 */, double* piv, int i,
+__device__ __forceinline__ void chol_panels(double (&r)[16], double* pan /* 3 x 64 x PW */,
+                                            double* pinv /* 3 x PW */, double* piv, int i,
                                             int t) {
   // eliminate global panel P (owned by this wavefront: P % 4 == W)
   auto eliminate = [&](int P) {
     const int m = P >> 2;
-    double* pb = pan + (P % 3) * 256;
-    double* ib = pinv + (P % 3) * 4;
-    double pv[4], ipv[4];
+    double* pb = pan + (P % 3) * 64 * kPW;
+    double* ib = pinv + (P % 3) * kPW;
+    double pv[kPW], ipv[kPW];
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const double p = readlane_f64(r[4 * m + jj], 4 * P + jj);
+    for (int jj = 0; jj < kPW; ++jj) {
+      const double p = readlane_f64(r[kPW * m + jj], kPW * P + jj);
       const double ip = recip1(p);
-      const double lij = r[4 * m + jj] * ip;
+      const double lij = r[kPW * m + jj] * ip;
 #pragma unroll
-      for (int kk = jj + 1; kk < 4; ++kk)
-        r[4 * m + kk] = fma(-lij, readlane_f64(r[4 * m + jj], 4 * P + kk), r[4 * m + kk]);
+      for (int kk = jj + 1; kk < kPW; ++kk)
+        r[kPW * m + kk] =
+            fma(-lij, readlane_f64(r[kPW * m + jj], kPW * P + kk), r[kPW * m + kk]);
       pv[jj] = p;
       ipv[jj] = ip;
     }
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) pb[4 * i + jj] = r[4 * m + jj];
+    for (int jj = 0; jj < kPW; ++jj) pb[kPW * i + jj] = r[kPW * m + jj];
     if (t == 64 * W) {
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        piv[4 * P + jj] = pv[jj];
+      for (int jj = 0; jj < kPW; ++jj) {
+        piv[kPW * P + jj] = pv[jj];
         ib[jj] = ipv[jj];
       }
     }
   };
   // apply published panel Q to this wavefront's panels g with lo <= g <= hi (global indices)
   auto apply = [&](int Q, int lo, int hi) {
-    const double* pb = pan + (Q % 3) * 256;
-    const double* ib = pinv + (Q % 3) * 4;
-    double li[4];
+    const double* pb = pan + (Q % 3) * 64 * kPW;
+    const double* ib = pinv + (Q % 3) * kPW;
+    double li[kPW];
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) li[jj] = pb[4 * i + jj] * ib[jj];
+    for (int jj = 0; jj < kPW; ++jj) li[jj] = pb[kPW * i + jj] * ib[jj];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < kLP; ++m) {
       const int g = 4 * m + W;
       if (g >= lo && g <= hi) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double* pk = pb + 4 * (4 * g + c);
-          double acc = r[4 * m + c];
+        for (int c = 0; c < kPW; ++c) {
+          const double* pk = pb + kPW * (kPW * g + c);
+          double acc = r[kPW * m + c];
 #pragma unroll
-          for (int jj = 0; jj < 4; ++jj) acc = fma(-li[jj], pk[jj], acc);
-          r[4 * m + c] = acc;
+          for (int jj = 0; jj < kPW; ++jj) acc = fma(-li[jj], pk[jj], acc);
+          r[kPW * m + c] = acc;
         }
       }
     }
@@ -254,13 +258,13 @@ __device__ __forceinline__ void chol_panels(double (&r)[16], double* pan /* 3 x 
   if (W == 0) eliminate(0);
   __syncthreads();
 #pragma unroll
-  for (int P = 0; P < 15; ++P) {
+  for (int P = 0; P < kNP - 1; ++P) {
     if (W == (P + 1) % 4) {  // owner of panel P+1
       apply(P, P + 1, P + 1);
       eliminate(P + 1);
     } else {
-      if (P >= 1 && W == P % 4) apply(P - 1, P + 1, 15);  // deferred while owning panel P
-      apply(P, P + 1, 15);
+      if (P >= 1 && W == P % 4) apply(P - 1, P + 1, kNP - 1);  // deferred while owning panel P
+      apply(P, P + 1, kNP - 1);
     }
     __syncthreads();
   }
@@ -277,15 +281,15 @@ __device__ inline void write_tile_lower(double* __restrict__ K, int ld, int n, i
 __device__ __forceinline__ bool chol_inv64(Tile& T, Tile& W, double* colb, double* piv, int nvalid,
                                            int* bad, double* __restrict__ K, int ld, int n, int r0,
                                            int c0) {
-  __shared__ double pan[768], pinv[12];
+  __shared__ double pan[3 * 64 * kPW], pinv[3 * kPW];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  // ---- factorisation: wavefront w holds panels w, w+4, w+8, w+12 of row `lane` in
-  // registers (r[4m + c]: column 16m + 4w + c)
+  // ---- factorisation: wavefront w holds panels w, w+4, ... of row `lane` in registers
+  // (r[PW m + c]: column 4 PW m + PW w + c)
   const int i = lane;
   double r[16];
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
-    const int k = 16 * (kk >> 2) + 4 * w + (kk & 3);
+    const int k = 4 * kPW * (kk / kPW) + kPW * w + (kk % kPW);
     double x = (k <= i) ? T[i][k] : 0.0;
     if (i >= nvalid) x = (k == i) ? 1.0 : 0.0;
     r[kk] = x;
@@ -311,7 +315,7 @@ __device__ __forceinline__ bool chol_inv64(Tile& T, Tile& W, double* colb, doubl
   if (*bad < 64) return false;
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
-    const int k = 16 * (kk >> 2) + 4 * w + (kk & 3);
+    const int k = 4 * kPW * (kk / kPW) + kPW * w + (kk % kPW);
     T[i][k] = (k <= i) ? r[kk] * colb[k] : 0.0;
   }
   __syncthreads();
