@@ -49,21 +49,43 @@ void set_error(const std::string& msg);
 
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
-// ---- wavefront reductions (64 lanes, fixed butterfly order: deterministic) ----
+// x from another lane by the DPP control CTRL (quad_perm, row rotation; no LDS round trip).
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// x of lane `lane` (a constant or wavefront-uniform index) in every lane.
+__device__ inline double readlane_f64(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ---- wavefront reductions (all 64 lanes active; fixed order: deterministic) ----
+// Within each 16-lane row by DPP (lane ^ 1, lane ^ 2, rotations by 4 and 8: every lane of
+// the row ends with the row's value), then the four rows through scalar reads.
+template <typename Op>
+__device__ inline double wave_reduce(double x, Op op) {
+  x = op(x, dpp_f64<0xB1>(x));
+  x = op(x, dpp_f64<0x4E>(x));
+  x = op(x, dpp_f64<0x124>(x));
+  x = op(x, dpp_f64<0x128>(x));
+  return op(op(readlane_f64(x, 0), readlane_f64(x, 16)),
+            op(readlane_f64(x, 32), readlane_f64(x, 48)));
+}
 __device__ inline double wave_sum(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
+  return wave_reduce(x, [](double a, double b) { return a + b; });
 }
 __device__ inline double wave_max(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, kWave));
-  return x;
+  return wave_reduce(x, [](double a, double b) { return fmax(a, b); });
 }
 __device__ inline double wave_min(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, kWave));
-  return x;
+  return wave_reduce(x, [](double a, double b) { return fmin(a, b); });
 }
 
 // Block reductions for blockDim.x == 256 (4 waves); result valid in every thread.

@@ -121,14 +121,6 @@ __device__ inline d4 mma16(const double* A, const double* B, d4 c, int li, int l
   return c;
 }
 
-// x from another lane by the DPP control CTRL (quad_perm, row rotation; no LDS round trip).
-template <int CTRL>
-__device__ inline double dpp_f64(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // Inverse W = L^-1 of the lower-triangular tile T.  Wavefront b inverts the diagonal 16 x 16
 // block b by forward substitution (4 lanes per column); the blocks below the diagonal follow
@@ -179,12 +171,6 @@ __device__ void inv64(const Tile& T, Tile& W, double* rdiag) {
   }
 }
 
-__device__ inline double readlane_f64(double x, int lane) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // Right-looking factorisation of the tile in 16 panels of 4 columns, one barrier per panel.
 // Panels are dealt round robin: wavefront W holds panels W, W+4, W+8, W+12 (local panel m =
