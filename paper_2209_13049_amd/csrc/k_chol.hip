@@ -122,15 +122,15 @@ __device__ inline d4 mma16(const double* A, const double* B, d4 c, int li, int l
 }
 
 
-// Inverse W = L^-1 of the lower-triangular tile T.  Wavefront b inverts the diagonal 16 x 16
-// block b by forward substitution (4 lanes per column); the blocks below the diagonal follow
-// by block diagonals d = 1, 2, 3:  W_ij = -W_ii (sum_{k=j}^{i-1} L_ik W_kj), as MFMA products.
-__device__ void inv64(const Tile& T, Tile& W, double* rdiag) {
+// Inverse W = L^-1 of the lower-triangular tile T, given rdiag[j] = 1 / T[j][j] (T and rdiag
+// visible to the whole workgroup).  Wavefront b inverts the diagonal 16 x 16 block b by
+// forward substitution (4 lanes per column); after one barrier it forms the blocks below in
+// its column, W_ib = -W_ii (sum_{k=b}^{i-1} L_ik W_kb) for i = b+1, b+2, ..., as MFMA products,
+// which need the diagonal inverses and only its own earlier blocks (no further barrier).  The
+// blocks above the diagonal are not written (write_w emits them as zeros).
+__device__ void inv64(const Tile& T, Tile& W, const double* rdiag) {
   __shared__ double S[4][16 * 65];  // per-wavefront 16 x 16 scratch
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  if (t < 64) rdiag[t] = recip(T[t][t]);
-  for (int e = t; e < 4096; e += 256) W[e >> 6][e & 63] = 0.0;
-  __syncthreads();
+  const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
   {  // diagonal block w
     const int c = lane >> 2, p = lane & 3, o = 16 * w;
     double wv[4] = {0.0, 0.0, 0.0, 0.0};
@@ -154,21 +154,21 @@ __device__ void inv64(const Tile& T, Tile& W, double* rdiag) {
   __syncthreads();
   const int li = lane & 15, lk = lane >> 4;
   double* Sw = S[w];
-  for (int d = 1; d < 4; ++d) {
-    const int j = w, ii = w + d;  // block (ii, j) handled by wavefront w
-    if (ii < 4) {
-      d4 acc = d4{0, 0, 0, 0};
-      for (int k = j; k < ii; ++k) acc = mma16(&T[16 * ii][16 * k], &W[16 * k][16 * j], acc, li, lk);
+  const int j = w;
+  for (int ii = j + 1; ii < 4; ++ii) {  // block (ii, j), after (ii - 1, j)
+    d4 acc = d4{0, 0, 0, 0};
+    for (int k = j; k < ii; ++k) acc = mma16(&T[16 * ii][16 * k], &W[16 * k][16 * j], acc, li, lk);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Sw[(lk + 4 * v) * 65 + li] = acc[v];
-      __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
-      acc = mma16(&W[16 * ii][16 * ii], Sw, d4{0, 0, 0, 0}, li, lk);
+    for (int v = 0; v < 4; ++v) Sw[(lk + 4 * v) * 65 + li] = acc[v];
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    acc = mma16(&W[16 * ii][16 * ii], Sw, d4{0, 0, 0, 0}, li, lk);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) W[16 * ii + lk + 4 * v][16 * j + li] = -acc[v];
-    }
-    __syncthreads();
+    for (int v = 0; v < 4; ++v) W[16 * ii + lk + 4 * v][16 * j + li] = -acc[v];
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
   }
+  __syncthreads();
 }
 
 
@@ -268,9 +268,10 @@ __device__ __forceinline__ bool chol_inv64(Tile& T, Tile& W, double* colb, doubl
                                            int* bad, double* __restrict__ K, int ld, int n, int r0,
                                            int c0) {
   __shared__ double pan[3 * 64 * kPW], pinv[3 * kPW];
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
   // ---- factorisation: wavefront w holds panels w, w+4, ... of row `lane` in registers
-  // (r[PW m + c]: column 4 PW m + PW w + c)
+  // (r[PW m + c]: column 4 PW m + PW w + c).  T is not written again before the panel
+  // loop's barriers, so the loads need no barrier of their own.
   const int i = lane;
   double r[16];
 #pragma unroll
@@ -280,46 +281,64 @@ __device__ __forceinline__ bool chol_inv64(Tile& T, Tile& W, double* colb, doubl
     if (i >= nvalid) x = (k == i) ? 1.0 : 0.0;
     r[kk] = x;
   }
-  __syncthreads();
   switch (w) {  // wavefront-uniform: column indices become compile-time constants
     case 0: chol_panels<0>(r, pan, pinv, piv, i, t); break;
     case 1: chol_panels<1>(r, pan, pinv, piv, i, t); break;
     case 2: chol_panels<2>(r, pan, pinv, piv, i, t); break;
     default: chol_panels<3>(r, pan, pinv, piv, i, t); break;
   }
-  __syncthreads();
+  // (the panel loop ends with a barrier: every pivot is in piv)
   // A pivot that is not positive and finite leaves garbage behind it; it is reported here
-  // (the first such column), after the loop, so the loop itself carries no test.
-  if (t == 0) *bad = 64;
-  __syncthreads();
-  if (t < 64) {
-    const double pj = piv[t];
-    if (!(pj > 0.0) || !isfinite(pj)) atomicMin(bad, t);
-    colb[t] = recip(sqrt(pj));  // 1 / L_jj
+  // (the first such column), after the loop, so the loop itself carries no test.  Every
+  // wavefront tests all 64 pivots, so the outcome is uniform without a barrier.
+  const double pj = piv[lane];
+  const unsigned long long badm = __ballot(!(pj > 0.0) || !isfinite(pj));
+  if (badm != 0ull) {
+    if (t == 0) *bad = __ffsll((long long)badm) - 1;
+    return false;
   }
-  __syncthreads();
-  if (*bad < 64) return false;
+  const double cb = recip(sqrt(pj));  // 1 / L_jj of column `lane`
+  if (w == 0) colb[lane] = cb;
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
     const int k = 4 * kPW * (kk / kPW) + kPW * w + (kk % kPW);
-    T[i][k] = (k <= i) ? r[kk] * colb[k] : 0.0;
+    T[i][k] = (k <= i) ? r[kk] * readlane_f64(cb, k) : 0.0;
   }
   __syncthreads();
   write_tile_lower(K, ld, n, r0, c0, T, true);
-  inv64(T, W, piv);
+  inv64(T, W, colb);
   return true;
 }
 
+// All 16 LDS reads of a thread are issued before its first store.
 __device__ inline void write_tile_lower(double* __restrict__ K, int ld, int n, int r0, int c0,
                                         const Tile& T, bool diag) {
-  for (int e = threadIdx.x; e < 4096; e += 256) {
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    v[q] = T[e >> 6][e & 63];
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
     const int i = e >> 6, j = e & 63;
-    if (r0 + i < n && c0 + j < n && (!diag || j <= i)) K[(long long)(r0 + i) * ld + c0 + j] = T[i][j];
+    if (r0 + i < n && c0 + j < n && (!diag || j <= i)) K[(long long)(r0 + i) * ld + c0 + j] = v[q];
   }
 }
 
+// W_k to global memory; its 16 x 16 blocks above the diagonal are zero by definition and are
+// written as zeros without being read.
 __device__ inline void write_w(double* __restrict__ Wk, const Tile& W) {
-  for (int e = threadIdx.x; e < 4096; e += 256) Wk[e] = W[e >> 6][e & 63];
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int i = e >> 6, j = e & 63;
+    v[q] = (j >> 4) <= (i >> 4) ? W[i][j] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) Wk[threadIdx.x + 256 * q] = v[q];
 }
 
 __device__ inline void load_w(const double* __restrict__ Wk, Tile& W) {
@@ -547,13 +566,15 @@ __global__ __launch_bounds__(256) void tri_inv_kernel(const double* __restrict__
   const int nvalid = n - r0 < 64 ? n - r0 : 64;
   load_tile(L, ld, n, r0, r0, T);
   __syncthreads();
+  __shared__ double rdiag[64];
   for (int e = threadIdx.x; e < 4096; e += 256) {
     const int i = e >> 6, j = e & 63;
     if (j > i) T[i][j] = 0.0;
     if (i >= nvalid) T[i][j] = (i == j) ? 1.0 : 0.0;
   }
+  // the diagonal entries of valid rows are not rewritten above
+  if (threadIdx.x < 64) rdiag[threadIdx.x] = threadIdx.x < nvalid ? recip(T[threadIdx.x][threadIdx.x]) : 1.0;
   __syncthreads();
-  __shared__ double rdiag[64];
   inv64(T, W, rdiag);
   write_w(Wall + (long long)blockIdx.x * 4096, W);
 }
