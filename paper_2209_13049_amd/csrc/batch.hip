@@ -98,7 +98,7 @@ struct Batch {
   InstView* views = nullptr;
   WorkItem* items = nullptr;
   size_t items_cap = 0;
-  List init, blk, gt, n16, n4, one, syrk, fin, n256, mx4, mx256;
+  List init, blk, gt, n16, n4, one, syrk, fin, n256, gmv, mx256;
   std::vector<List> chol, fwd, bwd;
   int ntmax = 0, nmax = 0;
   bool lists_valid = false;
@@ -154,6 +154,7 @@ static InstView view_of(const Problem& p) {
   v.nt = ceil_div(p.n, 64);
   v.syrk_nwg = p.syrk.nwg;
   v.Gam = p.Gam;
+  v.Gt = p.Gt;
   v.Gam32 = p.Gam32;
   v.Gam16 = (const bf16_t*)p.Gam16;
   v.goff = p.goff;
@@ -221,7 +222,7 @@ static int build_lists(Batch& b) {
   add(b.syrk, [](const InstView& v) { return v.syrk_nwg; });
   add(b.fin, [&](const InstView& v) { return v.nt * (v.nt + 1) / 2 * 16; });
   add(b.n256, [](const InstView& v) { return ceil_div(v.n, 256); });
-  add(b.mx4, [](const InstView& v) { return ceil_div(v.mx, 4); });
+  add(b.gmv, [](const InstView& v) { return gmv_blocks(v.ns, v.N); });
   add(b.mx256, [](const InstView& v) { return ceil_div(v.mx, 256); });
   b.ntmax = 0;
   b.nmax = 0;
@@ -302,7 +303,7 @@ static int enqueue_iteration(Batch& b, int mixed, int refine, int eq) {
       return CMPC_ERR_HIP;
   if (enqueue_potrs(b, 0, eq)) return CMPC_ERR_HIP;
   for (int r = 0; r < refine; ++r) {
-    if (launch_b_gamma_mv(arg(b, b.mx4), 1)) return CMPC_ERR_HIP;
+    if (launch_b_gamma_mv(arg(b, b.gmv), 1)) return CMPC_ERR_HIP;
     if (launch_b_scale_by(arg(b, b.mx256))) return CMPC_ERR_HIP;
     if (launch_b_gamma_t_partial(arg(b, b.gt), 1)) return CMPC_ERR_HIP;
     if (launch_b_gamma_t_reduce(arg(b, b.n16), 1)) return CMPC_ERR_HIP;
@@ -311,7 +312,7 @@ static int enqueue_iteration(Batch& b, int mixed, int refine, int eq) {
     if (enqueue_potrs(b, 1, eq)) return CMPC_ERR_HIP;
     if (launch_b_axpy(arg(b, b.n256))) return CMPC_ERR_HIP;
   }
-  if (launch_b_gamma_mv(arg(b, b.mx4), 0)) return CMPC_ERR_HIP;
+  if (launch_b_gamma_mv(arg(b, b.gmv), 0)) return CMPC_ERR_HIP;
   if (launch_b_step(arg(b, b.blk))) return CMPC_ERR_HIP;
   if (launch_b_update(arg(b, b.blk))) return CMPC_ERR_HIP;
   return launch_b_publish(b.stream, b.views, b.count, b.d_iter, b.dflags, kRing);

@@ -23,7 +23,7 @@ void free_problem(Problem* p) {
   if (p->stream) hipStreamSynchronize(p->stream);
   else hipDeviceSynchronize();
   double** bufs[] = {&p->A,  &p->B,   &p->Q,    &p->Qf,    &p->R,    &p->xl,   &p->xu,
-                     &p->ul, &p->uu,  &p->qdiag, &p->G,    &p->Gam,  &p->H,    &p->K,
+                     &p->ul, &p->uu,  &p->qdiag, &p->G,    &p->Gt,   &p->Gam,  &p->H,    &p->K,
                      &p->x0, &p->c,   &p->qc,   &p->h,     &p->d,    &p->v,    &p->s,
                      &p->lam, &p->z,  &p->gv,   &p->pv,    &p->ps,   &p->plam, &p->pz,
                      &p->gpv, &p->rhs, &p->Dx,  &p->Du,    &p->wx,   &p->wu,   &p->gt,
@@ -213,6 +213,12 @@ int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
   for (int k = 1; k < N; ++k)
     TRY(launch_gemm_f64(stream, ns, nu, ns, 1.0, p->A, ns, 1, p->G + (size_t)(k - 1) * ns * nu,
                         nu, 1, 0.0, p->G + (size_t)k * ns * nu, nu));
+  if (hipMalloc(&p->Gt, sizeof(double) * (size_t)N * ns * nu) != hipSuccess) {
+    set_error("out of device memory (Gt)");
+    free_problem(p);
+    return CMPC_ERR_NOMEM;
+  }
+  TRY(launch_transpose_g(*p));
   // packed Gamma
   p->off.resize(N + 1);
   for (int t = 1; t <= N + 1; ++t) p->off[t - 1] = (long long)ns * nu * (long long)t * (t - 1) / 2;
@@ -465,7 +471,7 @@ int cmpc_problem_info(const cmpc_problem* h, cmpc_info* info) {
   info->syrk_partial_slots = p.syrk.nslots;
   double b = 8.0 * (double)p.off[p.N];
   if (p.Gam32) b += 4.0 * (double)p.off[p.N];
-  b += 8.0 * (2.0 * p.n * p.n + (double)p.N * p.ns * p.nu + 2.0 * p.ns * p.ns);
+  b += 8.0 * (2.0 * p.n * p.n + 2.0 * p.N * p.ns * p.nu + 2.0 * p.ns * p.ns);
   b += 8.0 * 4096.0 * p.syrk.nslots + 8.0 * 3.0 * 64.0 * (double)p.gt_chunks;
   b += 8.0 * (7.0 * p.m + 12.0 * p.mx + 16.0 * p.n);
   info->device_bytes = b;

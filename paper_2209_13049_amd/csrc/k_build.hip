@@ -69,6 +69,24 @@ int launch_pack_gamma(Problem& p) {
   return 0;
 }
 
+// Gt[(m nu + k) ns + i] = G[(m ns + i) nu + k]: the blocks of Gamma with the state index
+// fastest, so that the Gamma products read them in coalesced rows.
+__global__ void transpose_g_kernel(const double* __restrict__ G, double* __restrict__ Gt, int ns,
+                                   int nu) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // index into Gt
+  const int m = blockIdx.y;
+  if (e >= (long long)ns * nu) return;
+  const int k = (int)(e / ns), i = (int)(e - (long long)k * ns);
+  Gt[(long long)m * ns * nu + e] = G[((long long)m * ns + i) * nu + k];
+}
+
+int launch_transpose_g(Problem& p) {
+  dim3 grid(ceil_div((long long)p.ns * p.nu, 256), p.N);
+  hipLaunchKernelGGL(transpose_g_kernel, grid, dim3(256), 0, p.stream, p.G, p.Gt, p.ns, p.nu);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
 // y = A x (A rows x cols, row-major): one wavefront per row, lanes stride the row.
 __global__ __launch_bounds__(256) void gemv_kernel(const double* __restrict__ A,
                                                    const double* __restrict__ x,

@@ -176,35 +176,80 @@ int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int
 }
 
 // ---------------------------------------------------------------- y = Gamma x
-__device__ __forceinline__ void gamma_mv_body(int bid, const double* __restrict__ Gam,
-                                                       const long long* __restrict__ off,
-                                                       const double* __restrict__ x,
-                                                       double* __restrict__ y, int ns, int nu,
-                                                       int mx, const int* __restrict__ done) {
+// y[(t-1) ns + i] = sum_{e < t nu} Gt[e][i] x[(t-1-m) nu + k]  (e = m nu + k).  One
+// workgroup per (group of kMvT row blocks t = t_hi, t_hi - 1, ..., larger first; 64 rows):
+// lane = row i (coalesced rows of Gt), wavefront w takes the quarter [w T/4, (w+1) T/4) of e
+// (T = t_hi nu) for every row block of the group, so each row of Gt is read once for the
+// group; the x entries, the same in every lane, come through the scalar cache, issued with
+// the rows (16 e per pass); the four quarters are added in order.
+__device__ __forceinline__ void gamma_mv_body(int bid, const double* __restrict__ Gt,
+                                              const double* __restrict__ x,
+                                              double* __restrict__ y, int ns, int nu, int N,
+                                              const int* __restrict__ done) {
+  __shared__ double red[4][kMvT][64];
   if (done != nullptr && *done) return;
-  const int r = bid * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (r >= mx) return;
-  const int t = r / ns + 1, i = r - (t - 1) * ns;
-  const int len = t * nu;
-  const double* row = Gam + off[t - 1] + (long long)i * len;
-  double acc = 0.0;
-  for (int a = lane; a < len; a += 64) acc = fma(row[a], x[a], acc);
-  acc = wave_sum(acc);
-  if (lane == 0) y[r] = acc;
+  const int nbx = (ns + 63) >> 6;
+  const int tb = bid / nbx, bx = bid - tb * nbx;
+  const int t_hi = N - kMvT * tb;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int i = 64 * bx + lane, ic = i < ns ? i : ns - 1;
+  const int T = t_hi * nu;
+  const int e_begin = (w * T) >> 2, e_end = ((w + 1) * T) >> 2;
+  int m = e_begin / nu, k = e_begin - m * nu;
+  double acc[kMvT];
+#pragma unroll
+  for (int u = 0; u < kMvT; ++u) acc[u] = 0.0;
+  for (int e0 = e_begin; e0 < e_end; e0 += 16) {
+    double gv[16], xv[16][kMvT];
+    int mq = m, kq = k;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = e0 + q < e_end ? e0 + q : e_end - 1;
+      gv[q] = Gt[(long long)e * ns + ic];
+#pragma unroll
+      for (int u = 0; u < kMvT; ++u) {
+        const int xi = (t_hi - u - 1 - mq) * nu + kq;
+        xv[q][u] = x[xi > 0 ? xi : 0];
+      }
+      if (++kq == nu) {
+        kq = 0;
+        ++mq;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (e0 + q < e_end) {
+#pragma unroll
+        for (int u = 0; u < kMvT; ++u)
+          if (m < t_hi - u) acc[u] = fma(gv[q], xv[q][u], acc[u]);
+      }
+      if (++k == nu) {
+        k = 0;
+        ++m;
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kMvT; ++u) red[w][u][lane] = acc[u];
+  __syncthreads();
+  if (w < kMvT) {  // wavefront w writes row block t_hi - w
+    const int t = t_hi - w;
+    if (t >= 1 && i < ns)
+      y[(long long)(t - 1) * ns + i] =
+          ((red[0][w][lane] + red[1][w][lane]) + red[2][w][lane]) + red[3][w][lane];
+  }
 }
 
-__global__ __launch_bounds__(256) void gamma_mv_kernel(const double* __restrict__ Gam,
-                                                       const long long* __restrict__ off,
+__global__ __launch_bounds__(256) void gamma_mv_kernel(const double* __restrict__ Gt,
                                                        const double* __restrict__ x,
                                                        double* __restrict__ y, int ns, int nu,
-                                                       int mx, const int* __restrict__ done) {
-  gamma_mv_body(blockIdx.x, Gam, off, x, y, ns, nu, mx, done);
+                                                       int N, const int* __restrict__ done) {
+  gamma_mv_body(blockIdx.x, Gt, x, y, ns, nu, N, done);
 }
 
 int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done) {
-  hipLaunchKernelGGL(gamma_mv_kernel, dim3(ceil_div(p.mx, 4)), dim3(256), 0, p.stream, p.Gam,
-                     p.goff, x, y, p.ns, p.nu, p.mx, done);
+  hipLaunchKernelGGL(gamma_mv_kernel, dim3(gmv_blocks(p.ns, p.N)), dim3(256), 0, p.stream, p.Gt,
+                     x, y, p.ns, p.nu, p.N, done);
   CMPC_LAUNCH_CHECK();
   return 0;
 }
@@ -913,7 +958,7 @@ __global__ __launch_bounds__(256) void gamma_mv_batch_kernel(const InstView* __r
                                                              const WorkItem* __restrict__ items,
                                                              int nitems, int gate) {
   CMPC_ITEMS_BEGIN
-  gamma_mv_body(bid, V.Gam, V.goff, V.pv, V.gpv, V.ns, V.nu, V.mx, gate_of(V, gate));
+  gamma_mv_body(bid, V.Gt, V.pv, V.gpv, V.ns, V.nu, V.N, gate_of(V, gate));
   CMPC_ITEMS_END
 }
 

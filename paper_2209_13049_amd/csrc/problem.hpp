@@ -58,6 +58,7 @@ struct Problem {
   double *xl = nullptr, *xu = nullptr, *ul = nullptr, *uu = nullptr;
   double *qdiag = nullptr;       // diag(Qbar), length mx (diagonal weights only)
   double *G = nullptr;           // G_k = A^k B, k = 0..N-1: N x ns x nu
+  double *Gt = nullptr;          // Gt[(m nu + k) ns + i] = G_m[i][k]: n x ns (Gamma products)
   double *Gam = nullptr;         // packed Gamma: block t (t = 1..N) is ns x (t nu) row-major
   long long* goff = nullptr;     // device copy of off (N + 1)
   std::vector<long long> off;    // off[t - 1] = start of block t; off[N] = nnz
@@ -109,6 +110,7 @@ struct InstView {
   int nt;                        // ceil(n / 64)
   int syrk_nwg;
   const double* Gam;
+  const double* Gt;
   const float* Gam32;
   const bf16_t* Gam16;
   const long long* goff;
@@ -133,6 +135,15 @@ inline int gt_chunk_count(int ns, int nu, int N, int n, int rc) {
   long long c = 0;
   for (int cb = 0; 64 * cb < n; ++cb) c += (long long)(N - gt_tmin(cb, nu) + 1) * ((ns + rc - 1) / rc);
   return (int)c;
+}
+// Gamma x through the blocks of Gamma: block (t, j) is G_{t-1-j} = A^(t-1-j) B (zero for
+// j >= t), so Gamma is block Toeplitz and (Gamma x)_t = sum_{m<t} G_m x_{t-1-m}, read from Gt
+// (n x ns, rows e = m nu + k).  One workgroup per (kMvT row blocks, 64 rows); groups of 2
+// and 4 row blocks share the rows of Gt but were measured slower (longer chains per
+// wavefront at n = 500).
+constexpr int kMvT = 1;
+__host__ __device__ inline int gmv_blocks(int ns, int N) {
+  return ((ns + 63) / 64) * ((N + kMvT - 1) / kMvT);
 }
 
 // One entry of a work list: block `local` of instance `inst`.
@@ -219,6 +230,7 @@ int launch_gemm_f64(hipStream_t s, int M, int Nc, int Kd, double alpha, const do
                     long long a_i, long long a_k, const double* B, long long b_k, long long b_j,
                     double beta, double* C, long long ldc);
 int launch_pack_gamma(Problem& p);
+int launch_transpose_g(Problem& p);
 int launch_gemv(hipStream_t s, const double* A, const double* x, double* y, int rows, int cols);
 int launch_block_diag_weight(Problem& p, const double* in, double* out);
 int launch_make_d(Problem& p);
