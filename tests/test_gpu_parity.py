@@ -35,8 +35,9 @@ def cases():
     inf.xl[5] = -np.inf
     inf.uu[1] = np.inf
     wide = W.heat1d(50, 7, 21, seed=(8, 2))                       # n = 147: 3 tile rows
+    tall = W.heat1d(130, 17, 6, seed=(5, 3))                       # ns > 64, ragged: 3 row groups
     return {"small": small, "ragged": ragged, "tight": tight, "genq": genq, "inf": inf,
-            "wide": wide}
+            "wide": wide, "tall": tall}
 
 
 CASES = cases()
