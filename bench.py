@@ -193,6 +193,69 @@ def surrogate_leg(ntrain: int, nquery: int, epochs: int, replicas: int = 64):
     return out
 
 
+# The paper's 3-D cube shapes (cube nodes per dimension m, horizon T) with its GPU-dense column
+# (iterations, total and linear-solver seconds; Tables 4, 3 and 2; hardware not stated): context
+# for the shapes, not a target.
+PAPER_SHAPES = [
+    {"m": 4, "T": 50, "paper_gpu_dense": {"table": 4, "iters": 27, "tot_s": 0.09, "lin_s": 0.008}},
+    {"m": 8, "T": 150, "paper_gpu_dense": {"table": 3, "iters": 37, "tot_s": 6.12, "lin_s": 0.034}},
+    {"m": 13, "T": 250, "paper_gpu_dense": {"table": 2, "iters": 39, "tot_s": 76.5, "lin_s": 0.067}},
+]
+
+
+def paper_shapes_leg(solves: int):
+    """FP64 solves of the paper's own workload shapes (heat3d, Table 1 constants, deviation form
+    around a uniform 400 K set point): one untimed solve, `solves` timed ones, one with the
+    SYRK / Cholesky events."""
+    import numpy as np
+    import torch
+    from paper_2209_13049_amd import condmpc
+    from paper_2209_13049_amd import workloads as W
+
+    out = []
+    for shape in PAPER_SHAPES:
+        p = W.heat3d(shape["m"], shape["T"])
+        t0 = time.perf_counter()
+        prob = condmpc.Problem(p)
+        prob.set_x0(torch.from_numpy(p.x0).to("cuda:0"))
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        info = prob.info()
+        res = condmpc.Result()
+
+        def solve(profile):
+            rc = prob.solve_raw(condmpc.default_options(precision=condmpc.FP64, profile=profile),
+                                res)
+            if rc != condmpc.OK:
+                raise RuntimeError(f"heat3d m={shape['m']} T={shape['T']}: solve returned {rc}")
+            return res.iters, res.ms_syrk, res.ms_form, res.ms_potrf, res.obj
+
+        solve(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = 0
+        for _ in range(solves):
+            iters += solve(0)[0]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        it, ms_syrk, ms_form, ms_potrf, obj = solve(1)
+        pg = shape["paper_gpu_dense"]
+        out.append({
+            "workload": f"heat3d_m{shape['m']}_T{shape['T']}", "ns": p.ns, "nu": p.nu,
+            "N": p.N, "n": info["n"], "state_rows": info["mx"], "setup_s": setup_s,
+            "iters_per_solve": iters / solves, "solves_per_s": solves / el,
+            "ms_per_iter": el * 1e3 / max(1, iters),
+            "ms_per_iter_syrk_potrf": (ms_form + ms_potrf) / max(1, it),
+            "syrk_achieved_tflops": info["syrk_flops"] / (ms_syrk / 1e3 / max(1, it)) / 1e12,
+            "obj": obj,
+            "paper_gpu_dense_context": dict(pg, ms_per_iter=pg["tot_s"] * 1e3 / pg["iters"],
+                                            lin_ms_per_iter=pg["lin_s"] * 1e3 / pg["iters"]),
+        })
+        prob.close()
+        del prob
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +274,8 @@ def main():
                     help="IPM-generated training pairs of the surrogate (0 = skip the leg)")
     ap.add_argument("--surrogate-queries", type=int, default=2048)
     ap.add_argument("--surrogate-epochs", type=int, default=200)
+    ap.add_argument("--paper-solves", type=int, default=2,
+                    help="timed FP64 solves per paper 3-D cube shape (0 = skip the leg)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB (reference for the "
                          "hardware byte counters)")
@@ -341,6 +406,8 @@ def main():
             "max_obj_rel_diff": max(rel) if rel else None,
         }
     prob.close()
+    if args.paper_solves > 0:
+        out["paper_shapes"] = paper_shapes_leg(args.paper_solves)
     if args.batch_steps > 0:
         out["batch"] = batch_leg(args.batch_steps)
     if args.surrogate_train > 0:

@@ -22,6 +22,9 @@ __all__ = [
     "LQProblem",
     "heat1d",
     "heat2d",
+    "heat3d",
+    "heat3d_dynamics",
+    "HEAT3D_TABLE1",
     "heat1d_config",
     "batch_instances",
     "smooth_x0",
@@ -157,6 +160,70 @@ def heat2d(g: int = 70, nu_per_edge: int = 5, N: int = 100, seed=(2, 0), *, r: f
                      ul=_f64(np.full(nu, -ub)), uu=_f64(np.full(nu, ub)), x0=_f64(x0),
                      N=int(N), name=name or f"heat2d_{g}x{g}_nu{nu}_N{N}",
                      meta={"seed": list(seed)})
+
+
+# Table 1 of the paper: the copper cube of the 3-D temperature-control problem (Section 4).
+HEAT3D_TABLE1 = dict(dt=0.1, dw=0.02, rho=8960.0, cp=386.0, k=400.0, xl=200.0, xu=550.0,
+                     ul=300.0, uu=500.0, xhat=300.0)
+
+
+def heat3d_dynamics(m: int, dt: float = 0.1, dw: float = 0.02, rho: float = 8960.0,
+                    cp: float = 386.0, k: float = 400.0):
+    """3-D 7-point explicit-Euler heat step on the m^3 interior nodes of a cube (Section 4,
+    eqn. (3DPDE), Table 1): x+ = x + r (sum of the 6 neighbours - 6 x), r = k dt / (rho cp dw^2).
+
+    The 6 faces are the inputs (Dirichlet values, not states): a neighbour that lies on face
+    i contributes r u_i, so B[p, i] = r for each such neighbour (nodes next to an edge or a
+    corner touch 2 or 3 faces).  Faces: 0/1 x = 0/L, 2/3 y = 0/L, 4/5 z = 0/L.
+    """
+    r = k * dt / (rho * cp * dw * dw)
+    ns = m * m * m
+    A = np.zeros((ns, ns))
+    B = np.zeros((ns, 6))
+
+    def node(ix, iy, iz):
+        return (ix * m + iy) * m + iz
+
+    for ix in range(m):
+        for iy in range(m):
+            for iz in range(m):
+                p = node(ix, iy, iz)
+                A[p, p] = 1.0 - 6.0 * r
+                c = (ix, iy, iz)
+                for axis in range(3):
+                    for step, face in ((-1, 2 * axis), (1, 2 * axis + 1)):
+                        nb = list(c)
+                        nb[axis] += step
+                        if 0 <= nb[axis] < m:
+                            A[p, node(*nb)] = r
+                        else:
+                            B[p, face] += r
+    return _f64(A), _f64(B)
+
+
+def heat3d(m: int, N: int, *, setpoint: float = 400.0, name: str = "", **table) -> LQProblem:
+    """The paper's 3-D cube (m interior nodes per dimension, horizon N = the paper's T) with
+    Table 1's constants, written in deviations from a uniform set point d: x - d, u - d.
+
+    The paper's set point is not given; a uniform d is a steady state of the dynamics with every
+    face at d (A 1 + B 1 = 1), so in deviation form the problem has the library's pure
+    quadratic cost: Q = q I (q = 10 dw^2), R = r I (r = dw^2 / 10) penalise the state's
+    distance to d and the inputs' distance to d.  Bounds and the initial state are Table 1's
+    less d.
+    """
+    c = dict(HEAT3D_TABLE1)
+    c.update(table)
+    A, B = heat3d_dynamics(m, c["dt"], c["dw"], c["rho"], c["cp"], c["k"])
+    ns, nu = B.shape
+    q, rw = 10.0 * c["dw"] ** 2, 0.1 * c["dw"] ** 2
+    Q = q * np.eye(ns)
+    return LQProblem(A=A, B=B, Q=_f64(Q), R=_f64(rw * np.eye(nu)), Qf=_f64(Q),
+                     xl=_f64(np.full(ns, c["xl"] - setpoint)),
+                     xu=_f64(np.full(ns, c["xu"] - setpoint)),
+                     ul=_f64(np.full(nu, c["ul"] - setpoint)),
+                     uu=_f64(np.full(nu, c["uu"] - setpoint)),
+                     x0=_f64(np.full(ns, c["xhat"] - setpoint)), N=int(N),
+                     name=name or f"heat3d_m{m}_T{N}", meta={"setpoint": setpoint})
 
 
 # Named workloads (sizes of the benchmark and parity cases).

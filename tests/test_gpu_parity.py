@@ -36,8 +36,9 @@ def cases():
     inf.uu[1] = np.inf
     wide = W.heat1d(50, 7, 21, seed=(8, 2))                       # n = 147: 3 tile rows
     tall = W.heat1d(130, 17, 6, seed=(5, 3))                       # ns > 64, ragged: 3 row groups
+    cube = W.heat3d(3, 8)                                          # the paper's 3-D cube, m = 3
     return {"small": small, "ragged": ragged, "tight": tight, "genq": genq, "inf": inf,
-            "wide": wide, "tall": tall}
+            "wide": wide, "tall": tall, "cube": cube}
 
 
 CASES = cases()

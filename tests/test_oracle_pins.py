@@ -335,3 +335,37 @@ def test_config_1d_no_bound_active_matches_riccati():
     assert np.max(np.abs(u_ric)) < 1.0 and np.max(np.abs(oracle.simulate(p, u_ric))) < 0.5
     assert r.obj >= f_ric - 1e-9 * abs(f_ric)
     assert r.obj - f_ric <= r.gap
+
+
+def test_heat3d_generator_table1():
+    """The 3-D cube of Section 4 with Table 1's constants: r = k dt / (rho cp dw^2); a uniform
+    temperature with every face at that temperature is a steady state (A 1 + B 1 = 1); each face
+    touches m^2 interior nodes; the step is symmetric and stable."""
+    m = 4
+    A, B = W.heat3d_dynamics(m)
+    r = 400.0 * 0.1 / (8960.0 * 386.0 * 0.02 ** 2)
+    ns = m ** 3
+    assert np.allclose(A, A.T, rtol=0, atol=0)
+    assert np.max(np.abs(A @ np.ones(ns) + B @ np.ones(6) - 1.0)) < 1e-14
+    assert np.allclose(B.sum(axis=0), r * m * m, rtol=1e-14)
+    centre = (1 * m + 1) * m + 1  # node (1, 1, 1): all 6 neighbours interior
+    assert np.all(B[centre] == 0.0) and A[centre, centre] == pytest.approx(1.0 - 6.0 * r)
+    corner = 0  # node (0, 0, 0): faces x = 0, y = 0, z = 0
+    assert np.count_nonzero(B[corner]) == 3 and B[corner, 0] == B[corner, 2] == B[corner, 4] == r
+    assert np.max(np.abs(np.linalg.eigvals(A))) < 1.0
+    p = W.heat3d(m, 5)
+    assert np.all(p.x0 == 300.0 - 400.0) and np.all(p.xl == -200.0) and np.all(p.xu == 150.0)
+    assert np.all(p.ul == -100.0) and np.all(p.uu == 100.0)
+    assert p.Q[0, 0] == pytest.approx(10 * 0.02 ** 2) and p.R[0, 0] == pytest.approx(0.1 * 0.02 ** 2)
+
+
+def test_heat3d_solution_has_the_cube_symmetry():
+    """Uniform initial state, set point and bounds: the optimum is invariant under the cube's
+    symmetries, so all six faces get the same input at every step (a misplaced face column of
+    B breaks this); heating from 300 K toward 400 K saturates the inputs at the start."""
+    p = W.heat3d(3, 6)
+    res = ipm.solve(p)
+    assert res.status == 0
+    u = np.asarray(res.v).reshape(p.N, 6)
+    assert np.max(u.max(axis=1) - u.min(axis=1)) < 1e-6
+    assert np.all(u[0] == pytest.approx(100.0, abs=1e-6))
