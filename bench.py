@@ -204,9 +204,10 @@ PAPER_SHAPES = [
 
 
 def paper_shapes_leg(solves: int):
-    """FP64 solves of the paper's own workload shapes (heat3d, Table 1 constants, deviation form
-    around a uniform 400 K set point): one untimed solve, `solves` timed ones, one with the
-    SYRK / Cholesky events."""
+    """Solves of the paper's own workload shapes (heat3d, Table 1 constants, deviation form
+    around a uniform 400 K set point): FP64 (one untimed solve, `solves` timed ones, one with
+    the SYRK / Cholesky events), then the FP32- and BF16-start mixed modes (same count), each
+    against the FP64 solve's time and objective."""
     import numpy as np
     import torch
     from paper_2209_13049_amd import condmpc
@@ -223,22 +224,31 @@ def paper_shapes_leg(solves: int):
         info = prob.info()
         res = condmpc.Result()
 
-        def solve(profile):
-            rc = prob.solve_raw(condmpc.default_options(precision=condmpc.FP64, profile=profile),
+        def solve(profile, precision=condmpc.FP64):
+            rc = prob.solve_raw(condmpc.default_options(precision=precision, profile=profile),
                                 res)
             if rc != condmpc.OK:
                 raise RuntimeError(f"heat3d m={shape['m']} T={shape['T']}: solve returned {rc}")
             return res.iters, res.ms_syrk, res.ms_form, res.ms_potrf, res.obj
 
-        solve(0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        iters = 0
-        for _ in range(solves):
-            iters += solve(0)[0]
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
+        def timed(precision):
+            solve(0, precision)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            iters = 0
+            for _ in range(solves):
+                iters += solve(0, precision)[0]
+            torch.cuda.synchronize()
+            return iters, time.perf_counter() - t0, res.obj
+
+        iters, el, _ = timed(condmpc.FP64)
         it, ms_syrk, ms_form, ms_potrf, obj = solve(1)
+        mixed = {}
+        for name, prec in (("fp32_start", condmpc.FP32_SYRK), ("bf16_start", condmpc.BF16_SYRK)):
+            mi, mel, mobj = timed(prec)
+            mixed[name] = {"iters_per_solve": mi / solves, "solves_per_s": solves / mel,
+                           "ms_per_iter": mel * 1e3 / max(1, mi), "speedup_vs_fp64": el / mel,
+                           "obj_rel_diff": abs(mobj - obj) / max(1.0, abs(obj))}
         pg = shape["paper_gpu_dense"]
         out.append({
             "workload": f"heat3d_m{shape['m']}_T{shape['T']}", "ns": p.ns, "nu": p.nu,
@@ -247,7 +257,7 @@ def paper_shapes_leg(solves: int):
             "ms_per_iter": el * 1e3 / max(1, iters),
             "ms_per_iter_syrk_potrf": (ms_form + ms_potrf) / max(1, it),
             "syrk_achieved_tflops": info["syrk_flops"] / (ms_syrk / 1e3 / max(1, it)) / 1e12,
-            "obj": obj,
+            "obj": obj, "mixed": mixed,
             "paper_gpu_dense_context": dict(pg, ms_per_iter=pg["tot_s"] * 1e3 / pg["iters"],
                                             lin_ms_per_iter=pg["lin_s"] * 1e3 / pg["iters"]),
         })
