@@ -289,8 +289,9 @@ __device__ __forceinline__ void syrk_rows_bf16(f4 (&acc)[4][4], const bf16_t* __
 
 // Rows [r0, r1) of one row block against one tile.  Every wavefront takes every 4th group
 // of 4 rows; operands are loaded straight into the MFMA lane layout (lane l: column l%16 of
-// a 16-column block, row l/16 of the 4-row group) through a PF-deep register ring, so PF-1
-// groups of loads are in flight behind the MFMAs of the current group.  Columns >= t nu
+// a 16-column block, row l/16 of the 4-row group) through a PF-deep register ring (3 groups
+// in FP64, 12 in FP32), so PF-1 groups of loads are in flight behind the MFMAs of the current
+// group.  Columns >= t nu
 // (structural zeros) and rows >= r1 enter as 0.  Only the first NIB row blocks of the tile
 // (those that t nu reaches: NIB = min(4, ceil((t nu - a0) / 16))) are loaded and computed.
 // DIAG (a diagonal tile, a0 == b0): both operands come from the same columns, loaded once,
@@ -301,7 +302,10 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
                                           const double* __restrict__ Dt, int len, int a0, int b0,
                                           int r0, int r1, int wave, int li, int lk) {
   typedef MfmaOps<TIn> Ops;
-  constexpr int PF = 3;
+  // Ring depth: the groups in flight must cover the load latency, and an FP32 group takes half
+  // the MFMA time and half the registers of an FP64 one (measured at K 1500 x 1500, 549,250
+  // rows: FP32 launch 8.7 ms at depth 3, 6.6 at 8, 5.2 at 12; 16 spills; FP64 no better at 4, 5)
+  constexpr int PF = sizeof(TIn) == 8 ? 3 : 12;
   bool va[4], vb[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
