@@ -221,9 +221,12 @@ struct MfmaOps;
 template <>
 struct MfmaOps<double> {
   typedef d4 acc_t;
+  typedef double comp_t, scale_t;
   __device__ static inline acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  __device__ static inline comp_t scaled(double x, double d) { return x * d; }
+  __device__ static inline comp_t plain(double x) { return x; }
   // output element v of lane l sits at row l/16 + 4v, column l%16 of the 16 x 16 block
   __device__ static inline int out_row(int lk, int v) { return lk + 4 * v; }
 };
@@ -231,61 +234,31 @@ struct MfmaOps<double> {
 template <>
 struct MfmaOps<float> {
   typedef f4 acc_t;
+  typedef float comp_t, scale_t;
   __device__ static inline acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  __device__ static inline comp_t scaled(float x, float d) { return x * d; }
+  __device__ static inline comp_t plain(float x) { return x; }
   // output element v of lane l sits at row 4 (l/16) + v, column l%16
   __device__ static inline int out_row(int lk, int v) { return 4 * lk + v; }
 };
 
+// BF16 storage, FP32 MFMA: the operands are widened where they are consumed and the D-scaled
+// one is rounded back to bfloat16, so each product is the exact product of two bfloat16
+// values (as in a bfloat16 MFMA) accumulated in float32; the loads, half the bytes of the
+// FP32 path, go through the same deep ring.
 template <>
 struct MfmaOps<bf16_t> {
   typedef f4 acc_t;
-  // v_mfma_f32_16x16x32_bf16: output element v of lane l sits at row 4 (l/16) + v, column l%16
+  typedef float comp_t, scale_t;
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline comp_t scaled(bf16_t x, float d) { return bf2f(f2bf(bf2f(x) * d)); }
+  __device__ static inline comp_t plain(bf16_t x) { return bf2f(x); }
   __device__ static inline int out_row(int lk, int v) { return 4 * lk + v; }
 };
-
-// BF16 inputs: rows [r0, r1) in groups of 32 per v_mfma_f32_16x16x32_bf16, every wavefront
-// taking every 4th group; lane (li, lk) supplies rows 8 lk .. 8 lk + 7 of the group in
-// column 16 q + li.  The left operand is scaled by D in float32 and rounded to bfloat16,
-// products accumulate in float32.  DIAG and NIB as for syrk_rows below.
-template <bool DIAG, int NIB>
-__device__ __forceinline__ void syrk_rows_bf16(f4 (&acc)[4][4], const bf16_t* __restrict__ base,
-                                               const double* __restrict__ Dt, int len, int a0,
-                                               int b0, int r0, int r1, int wave, int li, int lk) {
-  bool va[4], vb[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    va[q] = a0 + 16 * q + li < len;
-    vb[q] = b0 + 16 * q + li < len;
-  }
-  const int ngroups = (r1 - r0 + 31) >> 5;
-  for (int g = wave; g < ngroups; g += 4) {
-    const int rbase = r0 + 32 * g + 8 * lk;
-    s8 A[4], B[4];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int r = rbase + e;
-      const bool vr = r < r1;
-      const bf16_t* row = base + (long long)(vr ? r : r0) * len;
-      const float d = vr ? (float)Dt[r] : 0.f;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const bf16_t ga = (vr && va[q]) ? row[a0 + 16 * q + li] : (bf16_t)0;
-        const bf16_t gb = DIAG ? ga : ((vr && vb[q]) ? row[b0 + 16 * q + li] : (bf16_t)0);
-        A[q][e] = (short)f2bf(bf2f(ga) * d);
-        B[q][e] = (short)gb;
-      }
-    }
-#pragma unroll
-    for (int ib = 0; ib < NIB; ++ib)
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb)
-        if (!DIAG || jb <= ib)
-          acc[ib][jb] =
-              __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ib], B[jb], acc[ib][jb], 0, 0, 0);
-  }
-}
 
 // Rows [r0, r1) of one row block against one tile.  Every wavefront takes every 4th group
 // of 4 rows; operands are loaded straight into the MFMA lane layout (lane l: column l%16 of
@@ -302,10 +275,13 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
                                           const double* __restrict__ Dt, int len, int a0, int b0,
                                           int r0, int r1, int wave, int li, int lk) {
   typedef MfmaOps<TIn> Ops;
+  typedef typename Ops::comp_t TC;
+  typedef typename Ops::scale_t TS;
   // Ring depth: the groups in flight must cover the load latency, and an FP32 group takes half
   // the MFMA time and half the registers of an FP64 one (measured at K 1500 x 1500, 549,250
-  // rows: FP32 launch 8.7 ms at depth 3, 6.6 at 8, 5.2 at 12; 16 spills; FP64 no better at 4, 5)
-  constexpr int PF = sizeof(TIn) == 8 ? 3 : 12;
+  // rows: FP32 launch 8.7 ms at depth 3, 6.6 at 8, 5.2 at 12; 16 spills; FP64 no better at 4, 5).
+  // BF16 storage needs a few more registers for the conversions: 10 (12 spills in the batch form).
+  constexpr int PF = sizeof(TIn) == 8 ? 3 : (sizeof(TIn) == 4 ? 12 : 10);
   bool va[4], vb[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -313,7 +289,8 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
     vb[q] = b0 + 16 * q + li < len;
   }
   const int nsteps = (r1 - r0 + 15) >> 4;
-  TIn ra[PF][4], rb[PF][4], rd[PF];
+  TIn ra[PF][4], rb[PF][4];
+  TS rd[PF];
   // Every load is issued unconditionally from an in-bounds address (row r0, column 0 for
   // lanes outside the rows or columns), and the ring keeps the raw values; rows and columns
   // outside the piece are zeroed where a group is consumed.  With no branch around a load
@@ -329,11 +306,11 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
   }
   const char* __restrict__ gb = (const char*)base;
   const unsigned rowbytes = (unsigned)len * (unsigned)sizeof(TIn);
-  auto load = [&](int step, TIn (&xa)[4], TIn (&xb)[4], TIn& xd) {
+  auto load = [&](int step, TIn (&xa)[4], TIn (&xb)[4], TS& xd) {
     const int r = r0 + 16 * step + 4 * wave + lk;
     const int rr = r < r1 ? r : r0;
     const unsigned ro = (unsigned)rr * rowbytes;
-    xd = (TIn)Dt[rr];
+    xd = (TS)Dt[rr];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (q < NIB) xa[q] = *(const TIn*)(gb + (ro + ca[q]));
@@ -350,13 +327,13 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const bool vr = r0 + 16 * (step + u) + 4 * wave + lk < r1;
-      const TIn d = vr ? rd[u] : (TIn)0;
-      TIn sa[4], sb[4];
+      const TS d = vr ? rd[u] : (TS)0;
+      TC sa[4], sb[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (q < NIB) sa[q] = va[q] ? ra[u][q] * d : (TIn)0;
-        if (!DIAG) sb[q] = vb[q] ? rb[u][q] : (TIn)0;
-        else if (q < NIB) sb[q] = vb[q] ? ra[u][q] : (TIn)0;
+        if (q < NIB) sa[q] = va[q] ? Ops::scaled(ra[u][q], d) : (TC)0;
+        if (!DIAG) sb[q] = vb[q] ? Ops::plain(rb[u][q]) : (TC)0;
+        else if (q < NIB) sb[q] = vb[q] ? Ops::plain(ra[u][q]) : (TC)0;
       }
 #pragma unroll
       for (int ib = 0; ib < NIB; ++ib)
@@ -401,10 +378,7 @@ __device__ __forceinline__ void syrk_jobs(const TIn* __restrict__ Gam,
     const int len = job.t * nu;
     const TIn* __restrict__ base = Gam + off[job.t - 1];
     const double* __restrict__ Dt = D + (long long)(job.t - 1) * ns;
-    if constexpr (sizeof(TIn) == 2)
-      syrk_rows_bf16<DIAG, NIB>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
-    else
-      syrk_rows<TIn, DIAG, NIB>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
+    syrk_rows<TIn, DIAG, NIB>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
     if (job.slot >= 0) {
       __syncthreads();
       for (int w = 0; w < 4; ++w) {
