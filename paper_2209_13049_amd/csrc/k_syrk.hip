@@ -12,10 +12,11 @@
 //    rows come from HBM once and are re-read from that XCD's L2 by every tile that needs
 //    them.
 //  * Each of the 4 wavefronts of a workgroup accumulates the whole tile over every 4th
-//    group of 4 rows with v_mfma_f64_16x16x4f64 (or the f32 / bf16 variants), operands
-//    loaded straight from memory in the MFMA lane layout through a register prefetch ring
-//    and scaled by D on the fly; structurally zero columns (>= t nu) enter as zeros, and a
-//    diagonal tile computes only its 10 blocks on or below the diagonal.
+//    group of 4 rows with v_mfma_f64_16x16x4f64 (v_mfma_f32_16x16x4f32 for FP32 and for
+//    bfloat16 storage), operands loaded straight from memory in the MFMA lane layout
+//    through a register prefetch ring and scaled by D on the fly; structurally zero columns
+//    (>= t nu) enter as zeros, and a diagonal tile computes only its 10 blocks on or below
+//    the diagonal.
 //  * At the end of its piece a workgroup sums the 4 accumulators in LDS and writes a
 //    partial slot; a second kernel adds the slots of each tile in a fixed order to Hbase
 //    (deterministic, no atomics).
