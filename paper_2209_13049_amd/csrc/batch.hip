@@ -98,7 +98,7 @@ struct Batch {
   InstView* views = nullptr;
   WorkItem* items = nullptr;
   size_t items_cap = 0;
-  List init, blk, gt, n16, n4, one, syrk, fin, n256, gmv, mx256;
+  List init, blk, gt, n4, one, syrk, fin, n256, gmv, mx256;
   std::vector<List> chol, fwd, bwd;
   int ntmax = 0, nmax = 0;
   bool lists_valid = false;
@@ -148,8 +148,6 @@ static InstView view_of(const Problem& p) {
   v.mx = p.mx;
   v.m = p.m;
   v.nblk = p.n_prep_blocks;
-  v.gt_rows = p.gt_rows;
-  v.gt_cpb = ceil_div(p.ns, p.gt_rows);
   v.gt_chunks = p.gt_chunks;
   v.nt = ceil_div(p.n, 64);
   v.syrk_nwg = p.syrk.nwg;
@@ -216,7 +214,6 @@ static int build_lists(Batch& b) {
   add(b.init, [](const InstView& v) { return ceil_div(v.m, 256); });
   add(b.blk, [](const InstView& v) { return v.nblk; });
   add(b.gt, [](const InstView& v) { return v.gt_chunks; });
-  add(b.n16, [](const InstView& v) { return ceil_div(v.n, 16); });
   add(b.n4, [](const InstView& v) { return ceil_div(v.n, 4); });
   add(b.one, [](const InstView&) { return 1; });
   add(b.syrk, [](const InstView& v) { return v.syrk_nwg; });
@@ -292,7 +289,7 @@ static int enqueue_syrk(Batch& b, int mixed) {
 static int enqueue_iteration(Batch& b, int mixed, int refine, int eq) {
   if (launch_b_prep(arg(b, b.blk))) return CMPC_ERR_HIP;
   if (launch_b_gamma_t_partial(arg(b, b.gt), 3)) return CMPC_ERR_HIP;
-  if (launch_b_gamma_t_reduce(arg(b, b.n16), 3)) return CMPC_ERR_HIP;
+  if (launch_b_gamma_t_reduce(arg(b, b.n256), 3)) return CMPC_ERR_HIP;
   if (launch_b_hv(arg(b, b.n4), 0)) return CMPC_ERR_HIP;
   if (launch_b_mu_rhs(arg(b, b.one))) return CMPC_ERR_HIP;
   if (enqueue_syrk(b, mixed)) return CMPC_ERR_HIP;
@@ -306,7 +303,7 @@ static int enqueue_iteration(Batch& b, int mixed, int refine, int eq) {
     if (launch_b_gamma_mv(arg(b, b.gmv), 1)) return CMPC_ERR_HIP;
     if (launch_b_scale_by(arg(b, b.mx256))) return CMPC_ERR_HIP;
     if (launch_b_gamma_t_partial(arg(b, b.gt), 1)) return CMPC_ERR_HIP;
-    if (launch_b_gamma_t_reduce(arg(b, b.n16), 1)) return CMPC_ERR_HIP;
+    if (launch_b_gamma_t_reduce(arg(b, b.n256), 1)) return CMPC_ERR_HIP;
     if (launch_b_hv(arg(b, b.n4), 1)) return CMPC_ERR_HIP;
     if (launch_b_refine_check(arg(b, b.one))) return CMPC_ERR_HIP;
     if (enqueue_potrs(b, 1, eq)) return CMPC_ERR_HIP;

@@ -472,7 +472,7 @@ int cmpc_problem_info(const cmpc_problem* h, cmpc_info* info) {
   double b = 8.0 * (double)p.off[p.N];
   if (p.Gam32) b += 4.0 * (double)p.off[p.N];
   b += 8.0 * (2.0 * p.n * p.n + 2.0 * p.N * p.ns * p.nu + 2.0 * p.ns * p.ns);
-  b += 8.0 * 4096.0 * p.syrk.nslots + 8.0 * 3.0 * 64.0 * (double)p.gt_chunks;
+  b += 8.0 * 4096.0 * p.syrk.nslots + 8.0 * 3.0 * kGtJ * (double)p.gt_chunks;
   b += 8.0 * (7.0 * p.m + 12.0 * p.mx + 16.0 * p.n);
   info->device_bytes = b;
   return 0;

@@ -37,13 +37,8 @@ int ipm_alloc_work(Problem& p) {
   p.n_step_blocks = p.n_prep_blocks;
   CMPC_HIP(hipMalloc(&p.norm_part, sizeof(double) * 5 * p.n_prep_blocks));
   CMPC_HIP(hipMalloc(&p.alpha_part, sizeof(double) * 2 * p.n_step_blocks));
-  // Gamma' passes: chunks of rc rows of one row block and one 64-column block, 64-row
-  // chunks unless that makes more than 1024 of them
-  int rc = 64;
-  while (gt_chunk_count(p.ns, p.nu, p.N, n, rc) > 1024 && rc < 4096) rc *= 2;
-  p.gt_rows = rc;
-  p.gt_chunks = gt_chunk_count(p.ns, p.nu, p.N, n, rc);
-  CMPC_HIP(hipMalloc(&p.gt_part, sizeof(double) * 3 * 64 * (size_t)p.gt_chunks));
+  p.gt_chunks = gt_chunk_count(p.ns, p.nu, p.N);
+  CMPC_HIP(hipMalloc(&p.gt_part, sizeof(double) * 3 * kGtJ * (size_t)p.gt_chunks));
   CMPC_HIP(hipMalloc(&p.red_part, sizeof(double) * 1024));
   CMPC_HIP(hipMalloc(&p.Wdiag, sizeof(double) * 4096 * (size_t)ceil_div(p.n, 64)));
   CMPC_HIP(hipMalloc(&p.st, sizeof(IpmState)));
@@ -52,124 +47,141 @@ int ipm_alloc_work(Problem& p) {
 }
 
 // ---------------------------------------------------------------- Gamma' W  (NV vectors)
-// out[k][a] = sum_t sum_r Gamma_t[r][a] W[k][t][r] over the row blocks t that reach column a
-// (t nu > a).  Chunk (cb, t, q): column block cb (64 columns), row block t >= gt_tmin(cb),
-// rows [q rc, (q+1) rc); chunks are numbered column block by column block, t ascending,
-// q ascending.  Each chunk writes a partial of 64 columns; a second pass adds the chunks
-// of each column block in a fixed order.
-//
-// In a chunk, lane = column (one 512-byte row segment per wavefront load) and the 4
-// wavefronts take consecutive quarters of the rows, so the weights W[k][t][r] are
-// wavefront-uniform and come through the scalar cache.
+// out[v][j nu + k] = sum_{m < N-j} sum_i G_m[i][k] W[v][(m + j) ns + i]  (W[v] = w_1 .. w_N),
+// through Gt: Gamma is block Toeplitz (block (t, j) = G_{t-1-j}).  Workgroup (jr, k, ic): the
+// column blocks j = kGtJ jr .. +kGtJ-1, column k, rows i = 256 ic + thread.  A thread walks m
+// upward; G_m[i][k] is read once for all kGtJ column blocks of the range, and the blocks of W
+// it meets, w_{m+j+1} for j in the range, form a window that slides by one block per m (each
+// block of W read once per range).  kGtJ steps of m are loaded together (the window's
+// earlier blocks are kept in registers, the step's new ones loaded with the Gt entries), then
+// consumed in m order.  The workgroup adds its 256 rows in a fixed pattern (quad sums by DPP,
+// then the 64 quads in order) into its partial; a second pass adds the row chunks in order.
 template <int NV>
-__device__ __forceinline__ void gamma_t_partial_body(int bid, 
-    const double* __restrict__ Gam, const long long* __restrict__ off,
-    const double* __restrict__ W, long long wstride, double* __restrict__ part, int ns, int nu,
-    int N, int rc, int cpb, const int* __restrict__ done) {
-  __shared__ double red[4][NV][64];
+__device__ __forceinline__ void gamma_t_partial_body(int bid, const double* __restrict__ Gt,
+                                                     const double* __restrict__ W,
+                                                     long long wstride, double* __restrict__ part,
+                                                     int ns, int nu, int N,
+                                                     const int* __restrict__ done) {
+  constexpr int J = kGtJ;
+  __shared__ double red[J * NV][65];
   if (done != nullptr && *done) return;
-  int c = bid, cb = 0;
-  for (;; ++cb) {
-    const int cnt = (N - gt_tmin(cb, nu) + 1) * cpb;
-    if (c < cnt) break;
-    c -= cnt;
+  const int nic = gt_row_chunks(ns);
+  const int ic = bid % nic, rest = bid / nic;
+  const int k = rest % nu, jr = rest / nu;
+  const int j0 = J * jr;
+  const int tid = threadIdx.x;
+  const int i = 256 * ic + tid;
+  const int icl = i < ns ? i : ns - 1;
+  const double* __restrict__ wi = W + icl;
+  auto wblock = [&](int s, double (&x)[NV]) {  // w_{s+1}[i] of the NV vectors, s clamped
+    const long long o = (long long)(s < N ? s : N - 1) * ns;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] = wi[v * wstride + o];
+  };
+  double acc[J][NV], old[J - 1][NV];
+#pragma unroll
+  for (int q = 0; q < J; ++q)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[q][v] = 0.0;
+#pragma unroll
+  for (int q = 0; q < J - 1; ++q) wblock(j0 + q, old[q]);
+  const int mend = N - j0;  // m < N - j0 reaches the range's first column block
+  for (int m0 = 0; m0 < mend; m0 += J) {
+    double g[J], nw[J][NV];
+#pragma unroll
+    for (int u = 0; u < J; ++u) {
+      const int mc = m0 + u < mend ? m0 + u : mend - 1;
+      g[u] = Gt[((long long)mc * nu + k) * ns + icl];
+      wblock(m0 + j0 + J - 1 + u, nw[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < J; ++u) {
+      if (m0 + u < mend) {  // uniform
+#pragma unroll
+        for (int jj = 0; jj < J; ++jj) {
+          if (m0 + u + j0 + jj <= N - 1) {  // block m + j within the horizon (uniform)
+            const int q = u + jj;  // window position: block m0 + j0 + q
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+              acc[jj][v] = fma(g[u], q < J - 1 ? old[q < J - 1 ? q : 0][v]
+                                               : nw[q >= J - 1 ? q - (J - 1) : 0][v],
+                               acc[jj][v]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < J - 1; ++q)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) old[q][v] = nw[q + 1][v];
   }
-  const int t = gt_tmin(cb, nu) + c / cpb, q = c - (c / cpb) * cpb;
-  const int len = t * nu;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int a = 64 * cb + lane;
-  const int ac = a < len ? a : len - 1;  // lanes past the row load a valid entry (dropped)
-  const int quarter = rc >> 2;
-  const int w0 = q * rc + wave * quarter, w1 = min(ns, w0 + quarter);
-  const double* __restrict__ g = Gam + off[t - 1] + ac;
-  const double* __restrict__ wb = W + (long long)(t - 1) * ns;
-  double acc[NV];
+  const int lane = tid & 63;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-#pragma unroll 16
-  for (int r = w0; r < w1; ++r) {
-    const double x = g[(long long)r * len];
+  for (int jj = 0; jj < J; ++jj)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = fma(x, wb[k * wstride + r], acc[k]);
-  }
-#pragma unroll
-  for (int k = 0; k < NV; ++k) red[wave][k][lane] = acc[k];
+    for (int v = 0; v < NV; ++v) {
+      double x = i < ns ? acc[jj][v] : 0.0;
+      x += dpp_f64<0xB1>(x);  // lane ^ 1
+      x += dpp_f64<0x4E>(x);  // lane ^ 2: the quad's sum (the same in its 4 lanes)
+      if ((lane & 3) == 0) red[jj * NV + v][tid >> 2] = x;
+    }
   __syncthreads();
-  if (wave == 0) {  // columns past this row block's length get 0 (the reduction adds all)
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-      part[((long long)bid * NV + k) * 64 + lane] =
-          a < len ? ((red[0][k][lane] + red[1][k][lane]) + red[2][k][lane]) + red[3][k][lane]
-                  : 0.0;
+  if (tid < J * NV) {
+    double sum = 0.0;
+#pragma unroll 16
+    for (int q = 0; q < 64; ++q) sum += red[tid][q];
+    part[(long long)bid * J * NV + tid] = sum;
   }
 }
 
 template <int NV>
 __global__ __launch_bounds__(256) void gamma_t_partial_kernel(
-    const double* __restrict__ Gam, const long long* __restrict__ off,
-    const double* __restrict__ W, long long wstride, double* __restrict__ part, int ns, int nu,
-    int N, int rc, int cpb, const int* __restrict__ done) {
-  gamma_t_partial_body<NV>(blockIdx.x, Gam, off, W, wstride, part, ns, nu, N, rc, cpb, done);
+    const double* __restrict__ Gt, const double* __restrict__ W, long long wstride,
+    double* __restrict__ part, int ns, int nu, int N, const int* __restrict__ done) {
+  gamma_t_partial_body<NV>(blockIdx.x, Gt, W, wstride, part, ns, nu, N, done);
 }
 
-// out[k][a] for 16 columns a per workgroup: the chunks of their column block, 16 chunk
-// phases summed in a fixed order.
+// out[v][a] for 256 columns a per workgroup: the row chunks of column a in order.
 template <int NV>
 __device__ __forceinline__ void gamma_t_reduce_body(int bid, const double* __restrict__ part,
-                                                             double* __restrict__ out, int n,
-                                                             int nu, int N, int cpb,
-                                                             const int* __restrict__ done) {
-  __shared__ double sh[16][NV][16];
+                                                    double* __restrict__ out, int n, int ns,
+                                                    int nu, const int* __restrict__ done) {
   if (done != nullptr && *done) return;
-  const int l = threadIdx.x & 15, g = threadIdx.x >> 4;
-  const int a = bid * 16 + l, cb = bid >> 2;
-  int c0 = 0;
-  for (int c = 0; c < cb; ++c) c0 += (N - gt_tmin(c, nu) + 1) * cpb;
-  const int cnt = (N - gt_tmin(cb, nu) + 1) * cpb;
-  double acc[NV];
+  const int a = bid * 256 + threadIdx.x;
+  if (a >= n) return;
+  const int j = a / nu, k = a - j * nu;
+  const int jr = j / kGtJ, jj = j - jr * kGtJ;
+  const int nic = gt_row_chunks(ns);
+  const long long base = ((long long)jr * nu + k) * nic;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-#pragma unroll 4
-  for (int i = g; i < cnt; i += 16)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] += part[((long long)(c0 + i) * NV + k) * 64 + (a & 63)];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) sh[g][k][l] = acc[k];
-  __syncthreads();
-  if (g == 0 && a < n) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double sum = 0.0;
-      for (int g2 = 0; g2 < 16; ++g2) sum += sh[g2][k][l];
-      out[(long long)k * n + a] = sum;
-    }
+  for (int v = 0; v < NV; ++v) {
+    double sum = 0.0;
+    for (int ic = 0; ic < nic; ++ic) sum += part[((base + ic) * kGtJ + jj) * NV + v];
+    out[(long long)v * n + a] = sum;
   }
 }
 
 template <int NV>
 __global__ __launch_bounds__(256) void gamma_t_reduce_kernel(const double* __restrict__ part,
                                                              double* __restrict__ out, int n,
-                                                             int nu, int N, int cpb,
+                                                             int ns, int nu,
                                                              const int* __restrict__ done) {
-  gamma_t_reduce_body<NV>(blockIdx.x, part, out, n, nu, N, cpb, done);
+  gamma_t_reduce_body<NV>(blockIdx.x, part, out, n, ns, nu, done);
 }
 
 int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int* done) {
-  const int cpb = ceil_div(p.ns, p.gt_rows);
   if (nvec == 3) {
     hipLaunchKernelGGL(gamma_t_partial_kernel<3>, dim3(p.gt_chunks), dim3(256), 0, p.stream,
-                       p.Gam, p.goff, w, (long long)p.mx, p.gt_part, p.ns, p.nu, p.N, p.gt_rows,
-                       cpb, done);
+                       p.Gt, w, (long long)p.mx, p.gt_part, p.ns, p.nu, p.N, done);
     CMPC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(gamma_t_reduce_kernel<3>, dim3(ceil_div(p.n, 16)), dim3(256), 0, p.stream,
-                       p.gt_part, out, p.n, p.nu, p.N, cpb, done);
+    hipLaunchKernelGGL(gamma_t_reduce_kernel<3>, dim3(ceil_div(p.n, 256)), dim3(256), 0,
+                       p.stream, p.gt_part, out, p.n, p.ns, p.nu, done);
   } else {
     hipLaunchKernelGGL(gamma_t_partial_kernel<1>, dim3(p.gt_chunks), dim3(256), 0, p.stream,
-                       p.Gam, p.goff, w, (long long)p.mx, p.gt_part, p.ns, p.nu, p.N, p.gt_rows,
-                       cpb, done);
+                       p.Gt, w, (long long)p.mx, p.gt_part, p.ns, p.nu, p.N, done);
     CMPC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(gamma_t_reduce_kernel<1>, dim3(ceil_div(p.n, 16)), dim3(256), 0, p.stream,
-                       p.gt_part, out, p.n, p.nu, p.N, cpb, done);
+    hipLaunchKernelGGL(gamma_t_reduce_kernel<1>, dim3(ceil_div(p.n, 256)), dim3(256), 0,
+                       p.stream, p.gt_part, out, p.n, p.ns, p.nu, done);
   }
   CMPC_LAUNCH_CHECK();
   return 0;
@@ -542,25 +554,23 @@ __global__ __launch_bounds__(256) void mu_rhs_kernel(
 // each) in one launch: the two are independent.
 template <int NV>
 __global__ __launch_bounds__(256) void gamma_t_hv_kernel(
-    const double* __restrict__ Gam, const long long* __restrict__ off,
-    const double* __restrict__ W, long long wstride, double* __restrict__ part, int ns, int nu,
-    int N, int rc, int cpb, int nchunks, const double* __restrict__ H,
+    const double* __restrict__ Gt, const double* __restrict__ W, long long wstride,
+    double* __restrict__ part, int ns, int nu, int N, int nchunks, const double* __restrict__ H,
     const double* __restrict__ x, double* __restrict__ y, int n, const int* __restrict__ done) {
   if ((int)blockIdx.x < nchunks)
-    gamma_t_partial_body<NV>(blockIdx.x, Gam, off, W, wstride, part, ns, nu, N, rc, cpb, done);
+    gamma_t_partial_body<NV>(blockIdx.x, Gt, W, wstride, part, ns, nu, N, done);
   else
     hv_body(blockIdx.x - nchunks, H, x, y, n, done);
 }
 
 int launch_mu_rhs(Problem& p) {
   const int* done = &p.st->done;
-  const int cpb = ceil_div(p.ns, p.gt_rows);
   hipLaunchKernelGGL(gamma_t_hv_kernel<3>, dim3(p.gt_chunks + ceil_div(p.n, 4)), dim3(256), 0,
-                     p.stream, p.Gam, p.goff, p.wx, (long long)p.mx, p.gt_part, p.ns, p.nu, p.N,
-                     p.gt_rows, cpb, p.gt_chunks, p.H, p.v, p.Hv, p.n, done);
+                     p.stream, p.Gt, p.wx, (long long)p.mx, p.gt_part, p.ns, p.nu, p.N,
+                     p.gt_chunks, p.H, p.v, p.Hv, p.n, done);
   CMPC_LAUNCH_CHECK();
-  hipLaunchKernelGGL(gamma_t_reduce_kernel<3>, dim3(ceil_div(p.n, 16)), dim3(256), 0, p.stream,
-                     p.gt_part, p.gt, p.n, p.nu, p.N, cpb, done);
+  hipLaunchKernelGGL(gamma_t_reduce_kernel<3>, dim3(ceil_div(p.n, 256)), dim3(256), 0, p.stream,
+                     p.gt_part, p.gt, p.n, p.ns, p.nu, done);
   CMPC_LAUNCH_CHECK();
   hipLaunchKernelGGL(mu_rhs_kernel, dim3(1), dim3(256), 0, p.stream, p.Hv, p.h, p.gt, p.wu,
                      p.norm_part, p.n_prep_blocks, p.v, p.rhs, p.n, p.st, 0);
@@ -921,9 +931,8 @@ template <int NV>
 __global__ __launch_bounds__(256) void gamma_t_partial_batch_kernel(
     const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems) {
   CMPC_ITEMS_BEGIN
-  gamma_t_partial_body<NV>(bid, V.Gam, V.goff, NV == 3 ? V.wx : V.gpv, (long long)V.mx,
-                           V.gt_part, V.ns, V.nu, V.N, V.gt_rows, V.gt_cpb,
-                           gate_of(V, NV == 3 ? 0 : 1));
+  gamma_t_partial_body<NV>(bid, V.Gt, NV == 3 ? V.wx : V.gpv, (long long)V.mx, V.gt_part,
+                           V.ns, V.nu, V.N, gate_of(V, NV == 3 ? 0 : 1));
   CMPC_ITEMS_END
 }
 
@@ -931,7 +940,7 @@ template <int NV>
 __global__ __launch_bounds__(256) void gamma_t_reduce_batch_kernel(
     const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems) {
   CMPC_ITEMS_BEGIN
-  gamma_t_reduce_body<NV>(bid, V.gt_part, NV == 3 ? V.gt : V.ref_gt, V.n, V.nu, V.N, V.gt_cpb,
+  gamma_t_reduce_body<NV>(bid, V.gt_part, NV == 3 ? V.gt : V.ref_gt, V.n, V.ns, V.nu,
                           gate_of(V, NV == 3 ? 0 : 1));
   CMPC_ITEMS_END
 }

@@ -81,7 +81,7 @@ struct Problem {
   double *gt = nullptr, *Hv = nullptr, *tmpn = nullptr, *tmpn2 = nullptr, *tmpmx = nullptr;
   double *ref_res = nullptr, *ref_dlt = nullptr, *ref_gt = nullptr;  // refinement vectors (n)
   double *norm_part = nullptr, *alpha_part = nullptr, *gt_part = nullptr;
-  int n_prep_blocks = 0, n_step_blocks = 0, gt_chunks = 0, gt_rows = 0;
+  int n_prep_blocks = 0, n_step_blocks = 0, gt_chunks = 0;
   bool eq_on = false;               // this solve factors the equilibrated S K S
   IpmState* st = nullptr;
   SyrkPlan syrk;
@@ -106,7 +106,7 @@ int ensure_plan(Problem& p, int precision, bool* changed);
 struct InstView {
   int ns, nu, N, n, mx, m;
   int nblk;                      // 256-pair blocks of the vector kernels
-  int gt_rows, gt_cpb, gt_chunks;
+  int gt_chunks;
   int nt;                        // ceil(n / 64)
   int syrk_nwg;
   const double* Gam;
@@ -128,13 +128,12 @@ struct InstView {
   const int *slot_begin, *slots;
 };
 
-// Chunks of the Gamma' passes: column block cb (64 columns) is reached by row blocks
-// t >= gt_tmin(cb) (t nu > 64 cb); each such block is cut into ceil(ns / rc) row chunks.
-__host__ __device__ inline int gt_tmin(int cb, int nu) { return (64 * cb) / nu + 1; }
-inline int gt_chunk_count(int ns, int nu, int N, int n, int rc) {
-  long long c = 0;
-  for (int cb = 0; 64 * cb < n; ++cb) c += (long long)(N - gt_tmin(cb, nu) + 1) * ((ns + rc - 1) / rc);
-  return (int)c;
+// Gamma' passes through Gt (Gamma block (t, j) = G_{t-1-j}, so (Gamma' w)_j = sum_{m<N-j} G_m' w_{m+j+1}):
+// one workgroup per (range of kGtJ column blocks j, column k within a block, 256 rows i).
+constexpr int kGtJ = 8;
+__host__ __device__ inline int gt_row_chunks(int ns) { return (ns + 255) / 256; }
+inline int gt_chunk_count(int ns, int nu, int N) {
+  return ((N + kGtJ - 1) / kGtJ) * nu * gt_row_chunks(ns);
 }
 // Gamma x through the blocks of Gamma: block (t, j) is G_{t-1-j} = A^(t-1-j) B (zero for
 // j >= t), so Gamma is block Toeplitz and (Gamma x)_t = sum_{m<t} G_m x_{t-1-m}, read from Gt
