@@ -55,7 +55,8 @@ int ipm_alloc_work(Problem& p) {
 // block of W read once per range).  kGtJ steps of m are loaded together (the window's
 // earlier blocks are kept in registers, the step's new ones loaded with the Gt entries), then
 // consumed in m order.  The workgroup adds its 256 rows in a fixed pattern (quad sums by DPP,
-// then the 64 quads in order) into its partial; a second pass adds the row chunks in order.
+// then the 64 quads in order) into its partial; a second pass adds the partials in order.
+// Each workgroup takes one of kGtMs consecutive parts of the range of m (shorter chains).
 template <int NV>
 __device__ __forceinline__ void gamma_t_partial_body(int bid, const double* __restrict__ Gt,
                                                      const double* __restrict__ W,
@@ -66,9 +67,13 @@ __device__ __forceinline__ void gamma_t_partial_body(int bid, const double* __re
   __shared__ double red[J * NV][65];
   if (done != nullptr && *done) return;
   const int nic = gt_row_chunks(ns);
-  const int ic = bid % nic, rest = bid / nic;
+  const int mh = bid % kGtMs, r2 = bid / kGtMs;
+  const int ic = r2 % nic, rest = r2 / nic;
   const int k = rest % nu, jr = rest / nu;
   const int j0 = J * jr;
+  const int mend = N - j0;  // m < N - j0 reaches the range's first column block
+  const int half = ((mend + J - 1) / J + kGtMs - 1) / kGtMs;  // steps of J per part
+  const int ms0 = mh * half * J, ms1 = min(mend, (mh + 1) * half * J);
   const int tid = threadIdx.x;
   const int i = 256 * ic + tid;
   const int icl = i < ns ? i : ns - 1;
@@ -84,19 +89,18 @@ __device__ __forceinline__ void gamma_t_partial_body(int bid, const double* __re
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[q][v] = 0.0;
 #pragma unroll
-  for (int q = 0; q < J - 1; ++q) wblock(j0 + q, old[q]);
-  const int mend = N - j0;  // m < N - j0 reaches the range's first column block
-  for (int m0 = 0; m0 < mend; m0 += J) {
+  for (int q = 0; q < J - 1; ++q) wblock(ms0 + j0 + q, old[q]);
+  for (int m0 = ms0; m0 < ms1; m0 += J) {
     double g[J], nw[J][NV];
 #pragma unroll
     for (int u = 0; u < J; ++u) {
-      const int mc = m0 + u < mend ? m0 + u : mend - 1;
+      const int mc = m0 + u < ms1 ? m0 + u : ms1 - 1;
       g[u] = Gt[((long long)mc * nu + k) * ns + icl];
       wblock(m0 + j0 + J - 1 + u, nw[u]);
     }
 #pragma unroll
     for (int u = 0; u < J; ++u) {
-      if (m0 + u < mend) {  // uniform
+      if (m0 + u < ms1) {  // uniform
 #pragma unroll
         for (int jj = 0; jj < J; ++jj) {
           if (m0 + u + j0 + jj <= N - 1) {  // block m + j within the horizon (uniform)
@@ -141,7 +145,8 @@ __global__ __launch_bounds__(256) void gamma_t_partial_kernel(
   gamma_t_partial_body<NV>(blockIdx.x, Gt, W, wstride, part, ns, nu, N, done);
 }
 
-// out[v][a] for 256 columns a per workgroup: the row chunks of column a in order.
+// out[v][a] for 256 columns a per workgroup: the (row chunk, part of m) partials of column a
+// in order.
 template <int NV>
 __device__ __forceinline__ void gamma_t_reduce_body(int bid, const double* __restrict__ part,
                                                     double* __restrict__ out, int n, int ns,
@@ -151,12 +156,12 @@ __device__ __forceinline__ void gamma_t_reduce_body(int bid, const double* __res
   if (a >= n) return;
   const int j = a / nu, k = a - j * nu;
   const int jr = j / kGtJ, jj = j - jr * kGtJ;
-  const int nic = gt_row_chunks(ns);
-  const long long base = ((long long)jr * nu + k) * nic;
+  const int nparts = gt_row_chunks(ns) * kGtMs;  // (row chunk, part of m), in order
+  const long long base = ((long long)jr * nu + k) * nparts;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     double sum = 0.0;
-    for (int ic = 0; ic < nic; ++ic) sum += part[((base + ic) * kGtJ + jj) * NV + v];
+    for (int c = 0; c < nparts; ++c) sum += part[((base + c) * kGtJ + jj) * NV + v];
     out[(long long)v * n + a] = sum;
   }
 }

@@ -129,11 +129,14 @@ struct InstView {
 };
 
 // Gamma' passes through Gt (Gamma block (t, j) = G_{t-1-j}, so (Gamma' w)_j = sum_{m<N-j} G_m' w_{m+j+1}):
-// one workgroup per (range of kGtJ column blocks j, column k within a block, 256 rows i).
+// one workgroup per (range of kGtJ column blocks j, column k within a block, 256 rows i, part
+// of the range of m).
+// Each workgroup's range of m is split in kGtMs parts (shorter dependent chains).
 constexpr int kGtJ = 8;
+constexpr int kGtMs = 2;
 __host__ __device__ inline int gt_row_chunks(int ns) { return (ns + 255) / 256; }
 inline int gt_chunk_count(int ns, int nu, int N) {
-  return ((N + kGtJ - 1) / kGtJ) * nu * gt_row_chunks(ns);
+  return ((N + kGtJ - 1) / kGtJ) * nu * gt_row_chunks(ns) * kGtMs;
 }
 // Gamma x through the blocks of Gamma: block (t, j) is G_{t-1-j} = A^(t-1-j) B (zero for
 // j >= t), so Gamma is block Toeplitz and (Gamma x)_t = sum_{m<t} G_m x_{t-1-m}, read from Gt
