@@ -289,7 +289,6 @@ static int enqueue_syrk(Batch& b, int mixed) {
 static int enqueue_iteration(Batch& b, int mixed, int refine, int eq) {
   if (launch_b_prep(arg(b, b.blk))) return CMPC_ERR_HIP;
   if (launch_b_gamma_t_partial(arg(b, b.gt), 3)) return CMPC_ERR_HIP;
-  if (launch_b_gamma_t_reduce(arg(b, b.n256), 3)) return CMPC_ERR_HIP;
   if (launch_b_hv(arg(b, b.n4), 0)) return CMPC_ERR_HIP;
   if (launch_b_mu_rhs(arg(b, b.one))) return CMPC_ERR_HIP;
   if (enqueue_syrk(b, mixed)) return CMPC_ERR_HIP;

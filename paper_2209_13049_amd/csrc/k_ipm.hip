@@ -145,8 +145,24 @@ __global__ __launch_bounds__(256) void gamma_t_partial_kernel(
   gamma_t_partial_body<NV>(blockIdx.x, Gt, W, wstride, part, ns, nu, N, done);
 }
 
-// out[v][a] for 256 columns a per workgroup: the (row chunk, part of m) partials of column a
-// in order.
+// (Gamma' W)[v][a] from the pass's partials: the (row chunk, part of m) partials of column a
+// added in order.
+template <int NV>
+__device__ __forceinline__ void gamma_t_column(const double* __restrict__ part, int a, int ns,
+                                               int nu, double (&out)[NV]) {
+  const int j = a / nu, k = a - j * nu;
+  const int jr = j / kGtJ, jj = j - jr * kGtJ;
+  const int nparts = gt_row_chunks(ns) * kGtMs;
+  const long long base = ((long long)jr * nu + k) * nparts;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v] = 0.0;
+#pragma unroll 8
+  for (int c = 0; c < nparts; ++c)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] += part[((base + c) * kGtJ + jj) * NV + v];
+}
+
+// out[v][a] for 256 columns a per workgroup.
 template <int NV>
 __device__ __forceinline__ void gamma_t_reduce_body(int bid, const double* __restrict__ part,
                                                     double* __restrict__ out, int n, int ns,
@@ -154,16 +170,10 @@ __device__ __forceinline__ void gamma_t_reduce_body(int bid, const double* __res
   if (done != nullptr && *done) return;
   const int a = bid * 256 + threadIdx.x;
   if (a >= n) return;
-  const int j = a / nu, k = a - j * nu;
-  const int jr = j / kGtJ, jj = j - jr * kGtJ;
-  const int nparts = gt_row_chunks(ns) * kGtMs;  // (row chunk, part of m), in order
-  const long long base = ((long long)jr * nu + k) * nparts;
+  double g[NV];
+  gamma_t_column<NV>(part, a, ns, nu, g);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    double sum = 0.0;
-    for (int c = 0; c < nparts; ++c) sum += part[((base + c) * kGtJ + jj) * NV + v];
-    out[(long long)v * n + a] = sum;
-  }
+  for (int v = 0; v < NV; ++v) out[(long long)v * n + a] = g[v];
 }
 
 template <int NV>
@@ -471,14 +481,24 @@ int launch_prep(Problem& p) {
 //   while E_mu <= kappa_eps mu: mu <- max(mu_min, min(kappa_mu mu, mu^theta_mu)),
 //   rhs = -r1 + J' r2 - J' Sigma r3 = -(H v + h) - mu J' S^-1 1 - J' Sigma r3.
 // fixed_mu != 0: no test and no update (used for a single step from a given iterate).
+// gt_part != NULL: gt = Gamma' [wx] is first formed from the Gamma' pass's partials (each
+// thread its own columns, in gamma_t_reduce_body's order) and stored, instead of read.
 __device__ __forceinline__ void mu_rhs_body(int bid, 
-    const double* __restrict__ Hv, const double* __restrict__ h, const double* __restrict__ gt,
+    const double* __restrict__ Hv, const double* __restrict__ h, double* gt,
     const double* __restrict__ wu, const double* __restrict__ norm_part, int nparts,
-    const double* __restrict__ v, double* __restrict__ rhs, int n, IpmState* st, int fixed_mu) {
+    const double* __restrict__ v, double* __restrict__ rhs, int n, IpmState* st, int fixed_mu,
+    const double* __restrict__ gt_part = nullptr, int ns = 0, int nu = 0) {
   __shared__ double sh[4];
   if (st->done) return;
   double nr1 = 0.0, f = 0.0;
   for (int c = threadIdx.x; c < n; c += 256) {
+    if (gt_part != nullptr) {
+      double g[3];
+      gamma_t_column<3>(gt_part, c, ns, nu, g);
+      gt[c] = g[0];
+      gt[n + c] = g[1];
+      gt[2 * n + c] = g[2];
+    }
     const double r1 = Hv[c] + h[c] + (gt[c] + wu[c]);
     nr1 = fmax(nr1, fabs(r1));
     f += v[c] * (0.5 * Hv[c] + h[c]);
@@ -549,10 +569,12 @@ __device__ __forceinline__ void mu_rhs_body(int bid,
 }
 
 __global__ __launch_bounds__(256) void mu_rhs_kernel(
-    const double* __restrict__ Hv, const double* __restrict__ h, const double* __restrict__ gt,
+    const double* __restrict__ Hv, const double* __restrict__ h, double* gt,
     const double* __restrict__ wu, const double* __restrict__ norm_part, int nparts,
-    const double* __restrict__ v, double* __restrict__ rhs, int n, IpmState* st, int fixed_mu) {
-  mu_rhs_body(blockIdx.x, Hv, h, gt, wu, norm_part, nparts, v, rhs, n, st, fixed_mu);
+    const double* __restrict__ v, double* __restrict__ rhs, int n, IpmState* st, int fixed_mu,
+    const double* __restrict__ gt_part, int ns, int nu) {
+  mu_rhs_body(blockIdx.x, Hv, h, gt, wu, norm_part, nparts, v, rhs, n, st, fixed_mu, gt_part, ns,
+              nu);
 }
 
 // Gamma' [wx] partial sums (the first gt_chunks workgroups) and Hv = H v (the rest, 4 rows
@@ -574,11 +596,10 @@ int launch_mu_rhs(Problem& p) {
                      p.stream, p.Gt, p.wx, (long long)p.mx, p.gt_part, p.ns, p.nu, p.N,
                      p.gt_chunks, p.H, p.v, p.Hv, p.n, done);
   CMPC_LAUNCH_CHECK();
-  hipLaunchKernelGGL(gamma_t_reduce_kernel<3>, dim3(ceil_div(p.n, 256)), dim3(256), 0, p.stream,
-                     p.gt_part, p.gt, p.n, p.ns, p.nu, done);
-  CMPC_LAUNCH_CHECK();
+  // the one-workgroup mu / rhs kernel adds the pass's partials itself (no reduction launch)
   hipLaunchKernelGGL(mu_rhs_kernel, dim3(1), dim3(256), 0, p.stream, p.Hv, p.h, p.gt, p.wu,
-                     p.norm_part, p.n_prep_blocks, p.v, p.rhs, p.n, p.st, 0);
+                     p.norm_part, p.n_prep_blocks, p.v, p.rhs, p.n, p.st, 0, p.gt_part, p.ns,
+                     p.nu);
   CMPC_LAUNCH_CHECK();
   return 0;
 }
@@ -887,7 +908,8 @@ int launch_step_given(Problem& p, const double* v, const double* s, const double
   if (launch_gamma_t(p, p.wx, 3, p.gt, done)) return CMPC_ERR_HIP;
   if (launch_hv(p, p.v, p.Hv, done)) return CMPC_ERR_HIP;
   hipLaunchKernelGGL(mu_rhs_kernel, dim3(1), dim3(256), 0, p.stream, p.Hv, p.h, p.gt, p.wu,
-                     p.norm_part, p.n_prep_blocks, p.v, p.rhs, p.n, p.st, 1);
+                     p.norm_part, p.n_prep_blocks, p.v, p.rhs, p.n, p.st, 1,
+                     (const double*)nullptr, 0, 0);
   CMPC_LAUNCH_CHECK();
   if (launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K)) return CMPC_ERR_HIP;
   if (launch_potrf(p.stream, p.K, p.n, p.n, p.Wdiag, &p.st->done, &p.st->info, &p.st->status,
@@ -963,7 +985,8 @@ __global__ __launch_bounds__(256) void mu_rhs_batch_kernel(const InstView* __res
                                                            const WorkItem* __restrict__ items,
                                                            int nitems) {
   CMPC_ITEMS_BEGIN
-  mu_rhs_body(bid, V.Hv, V.h, V.gt, V.wu, V.norm_part, V.nblk, V.v, V.rhs, V.n, V.st, 0);
+  mu_rhs_body(bid, V.Hv, V.h, V.gt, V.wu, V.norm_part, V.nblk, V.v, V.rhs, V.n, V.st, 0,
+              V.gt_part, V.ns, V.nu);
   CMPC_ITEMS_END
 }
 
