@@ -387,7 +387,7 @@ int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
     hf[slot] = 0;
     hipEvent_t e0 = prof ? p.prof_ev[4 * it] : nullptr, e1 = prof ? p.prof_ev[4 * it + 1] : nullptr;
     hipEvent_t e2 = prof ? p.prof_ev[4 * it + 2] : nullptr, e3 = prof ? p.prof_ev[4 * it + 3] : nullptr;
-    rc = launch_prep(p);
+    if (it == 0) rc = launch_prep(p);  // later iterations' prep runs in the update kernel
     if (!rc) rc = launch_mu_rhs(p);
     if (!rc) rc = launch_syrk(p, CMPC_FP64, p.Dx, p.H, p.Du, p.K, e0, e1, mixed);
     if (!rc && p.eq_on) rc = launch_equilibrate(p.stream, p.K, p.n, p.n, p.eqs, &p.st->done);

@@ -682,14 +682,15 @@ int launch_step(Problem& p, int refine) {
 // Every workgroup reduces the step-length partials itself (min is order independent), then
 // v += alpha p_v, s += alpha p_s, lambda += alpha p_lambda, z += alpha_z p_z, and z is
 // safeguarded into [mu/(kappa s), kappa mu/s].  apply == 0 only records alpha, alpha_z.
-__device__ __forceinline__ void update_body(int bid, 
+// Returns whether the step was applied (the same in every workgroup: each reduces all partials).
+__device__ __forceinline__ bool update_body(int bid, 
     const double* __restrict__ d, double* __restrict__ s, double* __restrict__ lam,
     double* __restrict__ z, double* __restrict__ gv, double* __restrict__ v,
     const double* __restrict__ gpv, const double* __restrict__ pv, const double* __restrict__ ps,
     const double* __restrict__ plam, const double* __restrict__ pz,
     const double* __restrict__ alpha_part, int nparts, int mx, int n, IpmState* st, int apply) {
   __shared__ double sh[4];
-  if (st->done) return;
+  if (st->done) return false;
   double amin = 1.0, azmin = 1.0;
   for (int b = threadIdx.x; b < nparts; b += 256) {
     amin = fmin(amin, alpha_part[2LL * b]);
@@ -702,13 +703,13 @@ __device__ __forceinline__ void update_body(int bid,
     st->alpha = alpha;
     st->alpha_z = alpha_z;
   }
-  if (!apply) return;
+  if (!apply) return false;
   if (alpha < kAlphaMin) {
     if (bid == 0 && threadIdx.x == 0) {
       st->status = CMPC_SMALL_STEP;
       st->done = 1;
     }
-    return;
+    return false;
   }
   const int p = bid * 256 + threadIdx.x;
   if (p < mx + n) {
@@ -737,6 +738,7 @@ __device__ __forceinline__ void update_body(int bid,
     }
   }
   if (bid == 0 && threadIdx.x == 0) st->iter += 1;
+  return true;
 }
 
 __global__ __launch_bounds__(256) void update_kernel(
@@ -757,13 +759,31 @@ __global__ void publish_kernel(IpmState* st, int* flag) {
   __hip_atomic_store(flag, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// The update and the host flag of ring slot `slot` (two launches: the flag needs every
-// workgroup of the update finished, which a last-workgroup tail could only see through a
-// device-scope fence per workgroup, an L2 write-back each, measured slower).
+// The update followed, in the same threads, by the next iteration's prep: both map thread p to
+// the pair of rows p (n_step_blocks == n_prep_blocks), so each thread re-reads only what it has
+// just written.  Runs only where the step was applied; a skipped or final iteration leaves the
+// previous prep outputs, which still describe the unchanged iterate.
+__global__ __launch_bounds__(256) void update_prep_kernel(
+    const double* __restrict__ d, double* __restrict__ s, double* __restrict__ lam,
+    double* __restrict__ z, double* __restrict__ gv, double* __restrict__ v,
+    const double* __restrict__ gpv, const double* __restrict__ pv, const double* __restrict__ ps,
+    const double* __restrict__ plam, const double* __restrict__ pz,
+    const double* __restrict__ alpha_part, int nparts, int mx, int n, IpmState* st,
+    double* __restrict__ Dx, double* __restrict__ Du, double* __restrict__ wx,
+    double* __restrict__ wu, double* __restrict__ norm_part) {
+  if (update_body(blockIdx.x, d, s, lam, z, gv, v, gpv, pv, ps, plam, pz, alpha_part, nparts, mx,
+                  n, st, 1))
+    prep_body(blockIdx.x, d, s, lam, z, gv, v, Dx, Du, wx, wu, norm_part, mx, n, &st->done);
+}
+
+// The update (with the next iteration's prep) and the host flag of ring slot `slot` (two
+// launches: the flag needs every workgroup of the update finished, which a last-workgroup tail
+// could only see through a device-scope fence per workgroup, an L2 write-back each, measured
+// slower).  The first iteration's prep is launched by the caller.
 int launch_update_publish(Problem& p, int slot) {
-  hipLaunchKernelGGL(update_kernel, dim3(p.n_step_blocks), dim3(256), 0, p.stream, p.d, p.s,
-                     p.lam, p.z, p.gv, p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part,
-                     p.n_step_blocks, p.mx, p.n, p.st, 1);
+  hipLaunchKernelGGL(update_prep_kernel, dim3(p.n_step_blocks), dim3(256), 0, p.stream, p.d,
+                     p.s, p.lam, p.z, p.gv, p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part,
+                     p.n_step_blocks, p.mx, p.n, p.st, p.Dx, p.Du, p.wx, p.wu, p.norm_part);
   CMPC_LAUNCH_CHECK();
   hipLaunchKernelGGL(publish_kernel, dim3(1), dim3(1), 0, p.stream, p.st, p.dflags + slot);
   CMPC_LAUNCH_CHECK();
