@@ -285,9 +285,9 @@ static int enqueue_syrk(Batch& b, int mixed) {
 }
 
 // One interior-point iteration of every instance, in the order of the single-instance
-// driver (prep, residuals and rhs, K, Cholesky, solve and refinement, step, update).
+// driver (residuals and rhs, K, Cholesky, solve and refinement, step, update with the next
+// iteration's prep); the first iteration's prep is launched before the first replay.
 static int enqueue_iteration(Batch& b, int mixed, int refine, int eq) {
-  if (launch_b_prep(arg(b, b.blk))) return CMPC_ERR_HIP;
   if (launch_b_gamma_t_partial(arg(b, b.gt), 3)) return CMPC_ERR_HIP;
   if (launch_b_hv(arg(b, b.n4), 0)) return CMPC_ERR_HIP;
   if (launch_b_mu_rhs(arg(b, b.one))) return CMPC_ERR_HIP;
@@ -397,6 +397,7 @@ static int batch_solve(Batch& b, const cmpc_options& o, cmpc_result* res) {
   }
   CMPC_HIP(hipEventRecord(b.ev0, b.stream));
   if (launch_b_init(arg(b, b.init), o.tol, o.max_iter, mixed, o.mu_switch)) return CMPC_ERR_HIP;
+  if (launch_b_prep(arg(b, b.blk))) return CMPC_ERR_HIP;  // later ones run in the update
   if (launch_b_reset(b.stream, b.d_iter)) return CMPC_ERR_HIP;
   // The publish kernel of iteration it stores (running instances + 1) into ring slot
   // it % kRing; the host keeps `depth` iterations queued ahead of the last slot it read.

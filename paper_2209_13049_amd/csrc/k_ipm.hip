@@ -1028,12 +1028,16 @@ __global__ __launch_bounds__(256) void step_batch_kernel(const InstView* __restr
   CMPC_ITEMS_END
 }
 
+// The update, then (where it was applied) the next iteration's prep of the same pairs, as in
+// update_prep_kernel; the items are the 256-pair blocks of both.
 __global__ __launch_bounds__(256) void update_batch_kernel(const InstView* __restrict__ views,
                                                            const WorkItem* __restrict__ items,
                                                            int nitems) {
   CMPC_ITEMS_BEGIN
-  update_body(bid, V.d, V.s, V.lam, V.z, V.gv, V.v, V.gpv, V.pv, V.ps, V.plam, V.pz,
-              V.alpha_part, V.nblk, V.mx, V.n, V.st, 1);
+  if (update_body(bid, V.d, V.s, V.lam, V.z, V.gv, V.v, V.gpv, V.pv, V.ps, V.plam, V.pz,
+                  V.alpha_part, V.nblk, V.mx, V.n, V.st, 1))
+    prep_body(bid, V.d, V.s, V.lam, V.z, V.gv, V.v, V.Dx, V.Du, V.wx, V.wu, V.norm_part, V.mx,
+              V.n, &V.st->done);
   CMPC_ITEMS_END
 }
 
