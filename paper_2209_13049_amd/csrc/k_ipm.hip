@@ -690,7 +690,14 @@ __device__ __forceinline__ bool update_body(int bid,
     const double* __restrict__ plam, const double* __restrict__ pz,
     const double* __restrict__ alpha_part, int nparts, int mx, int n, IpmState* st, int apply) {
   __shared__ double sh[4];
-  if (st->done) return false;
+  __shared__ int sdone;
+  // done is read once per workgroup: workgroup 0 sets it during this launch on a small step,
+  // and every wavefront of a workgroup must take the same path through the barriers below.
+  if (threadIdx.x == 0) sdone = st->done;
+  __syncthreads();
+  const bool stopped = sdone != 0;
+  __syncthreads();
+  if (stopped) return false;
   double amin = 1.0, azmin = 1.0;
   for (int b = threadIdx.x; b < nparts; b += 256) {
     amin = fmin(amin, alpha_part[2LL * b]);
