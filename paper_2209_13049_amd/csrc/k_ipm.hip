@@ -488,7 +488,6 @@ __device__ __forceinline__ void mu_rhs_body(int bid,
     const double* __restrict__ wu, const double* __restrict__ norm_part, int nparts,
     const double* __restrict__ v, double* __restrict__ rhs, int n, IpmState* st, int fixed_mu,
     const double* __restrict__ gt_part = nullptr, int ns = 0, int nu = 0) {
-  __shared__ double sh[4];
   if (st->done) return;
   double nr1 = 0.0, f = 0.0;
   for (int c = threadIdx.x; c < n; c += 256) {
@@ -503,8 +502,6 @@ __device__ __forceinline__ void mu_rhs_body(int bid,
     nr1 = fmax(nr1, fabs(r1));
     f += v[c] * (0.5 * Hv[c] + h[c]);
   }
-  nr1 = block_max256(nr1, sh);
-  f = block_sum256(f, sh);
   double nr3 = 0.0, nlz = 0.0, szmax = 0.0, szmin = INFINITY, gap = 0.0;
   for (int b = threadIdx.x; b < nparts; b += 256) {
     nr3 = fmax(nr3, norm_part[5LL * b]);
@@ -513,11 +510,27 @@ __device__ __forceinline__ void mu_rhs_body(int bid,
     szmin = fmin(szmin, norm_part[5LL * b + 3]);
     gap += norm_part[5LL * b + 4];
   }
-  gap = block_sum256(gap, sh);
-  nr3 = block_max256(nr3, sh);
-  nlz = block_max256(nlz, sh);
-  szmax = block_max256(szmax, sh);
-  szmin = block_min256(szmin, sh);
+  // the seven workgroup reductions through one exchange of the wavefronts' results (the
+  // same wavefront reductions and the same order of the four as block_*256)
+  __shared__ double shr[7][4];
+  {
+    const double wr[7] = {wave_max(nr1), wave_sum(f),    wave_sum(gap),  wave_max(nr3),
+                          wave_max(nlz), wave_max(szmax), wave_min(szmin)};
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) shr[k][w] = wr[k];
+    }
+  }
+  __syncthreads();
+  nr1 = fmax(fmax(shr[0][0], shr[0][1]), fmax(shr[0][2], shr[0][3]));
+  f = (shr[1][0] + shr[1][1]) + (shr[1][2] + shr[1][3]);
+  gap = (shr[2][0] + shr[2][1]) + (shr[2][2] + shr[2][3]);
+  nr3 = fmax(fmax(shr[3][0], shr[3][1]), fmax(shr[3][2], shr[3][3]));
+  nlz = fmax(fmax(shr[4][0], shr[4][1]), fmax(shr[4][2], shr[4][3]));
+  szmax = fmax(fmax(shr[5][0], shr[5][1]), fmax(shr[5][2], shr[5][3]));
+  szmin = fmin(fmin(shr[6][0], shr[6][1]), fmin(shr[6][2], shr[6][3]));
+  __syncthreads();  // shr is written again by a workgroup's next item (batch lists)
   double mu = st->mu;
   bool stop = false;
   if (!fixed_mu) {
