@@ -117,4 +117,28 @@ __device__ inline double block_min256(double x, double* sh) {
   return r;
 }
 
+// K workgroup reductions (blockDim.x == 256) through one exchange of the wavefronts' results;
+// op[k]: 0 = sum, 1 = max, 2 = min.  Each value is reduced and combined exactly as by
+// block_sum256 / block_max256 / block_min256, so the results are the same bits.
+enum : int { kRedSum = 0, kRedMax = 1, kRedMin = 2 };
+template <int K>
+__device__ inline void block_multi256(double (&x)[K], const int (&op)[K], double (*sh)[4]) {
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double r = op[k] == kRedSum ? wave_sum(x[k])
+                                      : (op[k] == kRedMax ? wave_max(x[k]) : wave_min(x[k]));
+    if ((threadIdx.x & 63) == 0) sh[k][w] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double* q = sh[k];
+    x[k] = op[k] == kRedSum ? (q[0] + q[1]) + (q[2] + q[3])
+                            : (op[k] == kRedMax ? fmax(fmax(q[0], q[1]), fmax(q[2], q[3]))
+                                                : fmin(fmin(q[0], q[1]), fmin(q[2], q[3])));
+  }
+  __syncthreads();
+}
+
 }  // namespace cmpc

@@ -403,7 +403,7 @@ __device__ __forceinline__ void prep_body(int bid,
     double* __restrict__ Dx, double* __restrict__ Du, double* __restrict__ wx,
     double* __restrict__ wu, double* __restrict__ norm_part, int mx, int n,
     const int* __restrict__ done) {
-  __shared__ double sh[4];
+  __shared__ double sh5[5][4];
   if (*done) return;
   const int p = bid * 256 + threadIdx.x;
   double nr3 = 0.0, nlz = 0.0, szmax = 0.0, szmin = INFINITY, gap = 0.0;
@@ -445,11 +445,16 @@ __device__ __forceinline__ void prep_body(int bid,
       wu[2 * n + c] = y3[0] - y3[1];
     }
   }
-  nr3 = block_max256(nr3, sh);
-  nlz = block_max256(nlz, sh);
-  szmax = block_max256(szmax, sh);
-  szmin = block_min256(szmin, sh);
-  gap = block_sum256(gap, sh);
+  {
+    double r[5] = {nr3, nlz, szmax, szmin, gap};
+    constexpr int op[5] = {kRedMax, kRedMax, kRedMax, kRedMin, kRedSum};
+    block_multi256(r, op, sh5);
+    nr3 = r[0];
+    nlz = r[1];
+    szmax = r[2];
+    szmin = r[3];
+    gap = r[4];
+  }
   if (threadIdx.x == 0) {
     double* np = norm_part + 5LL * bid;
     np[0] = nr3;
@@ -626,7 +631,7 @@ __device__ __forceinline__ void step_body(int bid,
     const double* __restrict__ gpv, const double* __restrict__ pv, double* __restrict__ ps,
     double* __restrict__ plam, double* __restrict__ pz, double* __restrict__ alpha_part, int mx,
     int n, const IpmState* st) {
-  __shared__ double sh[4];
+  __shared__ double sh2[2][4];
   if (st->done) return;
   const double mu = st->mu, tau = st->tau;
   const int p = bid * 256 + threadIdx.x;
@@ -658,8 +663,13 @@ __device__ __forceinline__ void step_body(int bid,
       pz[r] = c;
     }
   }
-  amin = block_min256(amin, sh);
-  azmin = block_min256(azmin, sh);
+  {
+    double r[2] = {amin, azmin};
+    constexpr int op[2] = {kRedMin, kRedMin};
+    block_multi256(r, op, sh2);
+    amin = r[0];
+    azmin = r[1];
+  }
   if (threadIdx.x == 0) {
     alpha_part[2LL * bid] = amin;
     alpha_part[2LL * bid + 1] = azmin;
@@ -702,7 +712,7 @@ __device__ __forceinline__ bool update_body(int bid,
     const double* __restrict__ gpv, const double* __restrict__ pv, const double* __restrict__ ps,
     const double* __restrict__ plam, const double* __restrict__ pz,
     const double* __restrict__ alpha_part, int nparts, int mx, int n, IpmState* st, int apply) {
-  __shared__ double sh[4];
+  __shared__ double sh2[2][4];
   __shared__ int sdone;
   // done is read once per workgroup: workgroup 0 sets it during this launch on a small step,
   // and every wavefront of a workgroup must take the same path through the barriers below.
@@ -716,8 +726,10 @@ __device__ __forceinline__ bool update_body(int bid,
     amin = fmin(amin, alpha_part[2LL * b]);
     azmin = fmin(azmin, alpha_part[2LL * b + 1]);
   }
-  const double alpha = block_min256(amin, sh);
-  const double alpha_z = block_min256(azmin, sh);
+  double r[2] = {amin, azmin};
+  constexpr int op[2] = {kRedMin, kRedMin};
+  block_multi256(r, op, sh2);
+  const double alpha = r[0], alpha_z = r[1];
   const double mu = st->mu;
   if (bid == 0 && threadIdx.x == 0) {
     st->alpha = alpha;
