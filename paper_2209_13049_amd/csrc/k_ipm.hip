@@ -880,7 +880,7 @@ __device__ __forceinline__ void refine_check_body(int bid,
     const double* __restrict__ rhs, const double* __restrict__ Hp, const double* __restrict__ gtp,
     const double* __restrict__ Du, const double* __restrict__ p, double* __restrict__ res, int n,
     IpmState* st) {
-  __shared__ double sh[4];
+  __shared__ double sh2[2][4];
   if (st->ref_skip || st->done) return;
   double nr = 0.0, nb = 0.0;
   for (int c = threadIdx.x; c < n; c += 256) {
@@ -889,8 +889,13 @@ __device__ __forceinline__ void refine_check_body(int bid,
     nr = fmax(nr, fabs(r));
     nb = fmax(nb, fabs(rhs[c]));
   }
-  nr = block_max256(nr, sh);
-  nb = block_max256(nb, sh);
+  {
+    double r[2] = {nr, nb};
+    constexpr int op[2] = {kRedMax, kRedMax};
+    block_multi256(r, op, sh2);
+    nr = r[0];
+    nb = r[1];
+  }
   if (threadIdx.x == 0) {
     if (nr <= 1e-12 * nb) {
       st->ref_skip = 1;
