@@ -12,6 +12,7 @@ solving linear-quadratic MPC problems" (arXiv 2209.13049):
 * ``condensed_step``  -- Section 3, eqns. (aug_KKT) and (cond_KKT) and the recovery
   formulas that follow them: one Newton step through the condensed matrix H + J'Sigma J,
   factored by dense Cholesky.
+* ``barrier_update``  -- the barrier-parameter rule that Algorithm 1 leaves open (R8).
 * ``solve``           -- Algorithm 1 (condensed-space IPM), with the readings listed below.
 
 Everything is written from the definitions, in float64, with numpy/scipy primitives
@@ -180,13 +181,41 @@ def fraction_to_boundary(x: np.ndarray, p: np.ndarray, tau: float) -> float:
     return float(min(1.0, np.min(-tau * x[neg] / p[neg])))
 
 
-def kkt_error(red: Reduced, v, s, lam, z, mu):
-    """E_mu = max(|r1|, |r3|, |lambda - z|, |s z - mu|) in the inf-norm (reading R11)."""
-    r1 = red.H @ v + red.h + red.J.T @ lam
-    r3 = red.J @ v - red.d + s
+def optimality_error(r1, r3, lam, z, s, mu):
+    """E_mu = max(|r1|, |r3|, |lambda - z|, |s z - mu|) in the inf-norm (readings R8, R11).
+
+    r1 is the stationarity residual and r3 the primal residual defined under eqn. (aug_KKT);
+    lambda - z is the mismatch of the two multipliers of a row (stationarity in s) and
+    s z - mu the perturbed complementarity.  Returns (E_mu, [the four norms]).
+    """
     parts = [np.max(np.abs(r1), initial=0.0), np.max(np.abs(r3), initial=0.0),
              np.max(np.abs(lam - z), initial=0.0), np.max(np.abs(s * z - mu), initial=0.0)]
     return float(max(parts)), parts
+
+
+def kkt_error(red: Reduced, v, s, lam, z, mu):
+    """E_mu at the iterate (v, s, lambda, z) of the dense QP (see optimality_error)."""
+    r1 = red.H @ v + red.h + red.J.T @ lam
+    r3 = red.J @ v - red.d + s
+    return optimality_error(r1, r3, lam, z, s, mu)
+
+
+def barrier_update(mu, r1, r3, lam, z, s, mu_min):
+    """Monotone (Fiacco-McCormick) barrier rule of reading R8, applied at the top of an
+    iteration after the stop test.
+
+    While mu > mu_min and the barrier problem of the current mu is solved to
+    E_mu <= KAPPA_EPS mu, move to mu <- max(mu_min, min(KAPPA_MU mu, mu^THETA_MU)); the
+    residuals r1, r3 do not depend on mu, only the complementarity term of E_mu does.
+    Returns (mu, tau) with the fraction-to-boundary parameter tau = max(TAU_MIN, 1 - mu)
+    of the new mu (reading R9).
+    """
+    while mu > mu_min:
+        emu, _ = optimality_error(r1, r3, lam, z, s, mu)
+        if emu > KAPPA_EPS * mu:
+            break
+        mu = max(mu_min, min(KAPPA_MU * mu, mu ** THETA_MU))
+    return mu, max(TAU_MIN, 1.0 - mu)
 
 
 @dataclass
@@ -236,12 +265,8 @@ def solve(prob, tol: float = 1e-8, max_iter: int = 200, red: Reduced | None = No
             status = STATUS_MAX_ITER
             break
         # barrier update (reading R8)
-        while mu > mu_min:
-            emu, _ = kkt_error(red, v, s, lam, z, mu)
-            if emu > KAPPA_EPS * mu:
-                break
-            mu = max(mu_min, min(KAPPA_MU * mu, mu ** THETA_MU))
-        tau = max(TAU_MIN, 1.0 - mu)
+        mu, tau = barrier_update(mu, red.H @ v + red.h + red.J.T @ lam,
+                                 red.J @ v - red.d + s, lam, z, s, mu_min)
         step = condensed_step(red, v, s, lam, z, mu)
         alpha = fraction_to_boundary(s, step["ps"], tau)
         alpha_z = fraction_to_boundary(z, step["pz"], tau)

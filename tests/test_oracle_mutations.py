@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import brute_force as bf
+import test_oracle_barrier as tb
 from paper_2209_13049_amd import workloads as W
 from test_oracle_pins import random_stable, _binding_case, _pairs, _interior_point
 
@@ -41,6 +42,23 @@ MUTATIONS = {
     "r1_lambda_dropped": ("r1 = red.H @ v + red.h + red.J.T @ lam\n    r2",
                           "r1 = red.H @ v + red.h\n    r2"),
     "alpha_z_for_lambda": ("lam = lam + alpha * step[\"plam\"]", "lam = lam + alpha_z * step[\"plam\"]"),
+    # the barrier rule (reading R8) and its error measure
+    "kappa_eps_1": ("KAPPA_EPS = 10.0", "KAPPA_EPS = 1.0"),
+    "kappa_mu_half": ("KAPPA_MU = 0.2", "KAPPA_MU = 0.5"),
+    "theta_mu_2": ("THETA_MU = 1.5", "THETA_MU = 2.0"),
+    "mu_rule_max_for_min": ("mu = max(mu_min, min(KAPPA_MU * mu, mu ** THETA_MU))",
+                            "mu = max(mu_min, max(KAPPA_MU * mu, mu ** THETA_MU))"),
+    "mu_floor_tol": ("mu_min = tol / 10.0", "mu_min = tol"),
+    "tau_fixed": ("return mu, max(TAU_MIN, 1.0 - mu)", "return mu, TAU_MIN"),
+    "tau_min_for_max": ("return mu, max(TAU_MIN, 1.0 - mu)", "return mu, min(TAU_MIN, 1.0 - mu)"),
+    "emu_lambda_z_dropped": ("np.max(np.abs(lam - z), initial=0.0), np.max(np.abs(s * z - mu)",
+                             "0.0, np.max(np.abs(s * z - mu)"),
+    "emu_r3_dropped": ("parts = [np.max(np.abs(r1), initial=0.0), np.max(np.abs(r3), initial=0.0),",
+                       "parts = [np.max(np.abs(r1), initial=0.0), 0.0,"),
+    "emu_complementarity_not_shifted": ("np.max(np.abs(s * z - mu), initial=0.0)]",
+                                        "np.max(np.abs(s * z), initial=0.0)]"),
+    "emu_stationarity_dropped": ("parts = [np.max(np.abs(r1), initial=0.0),",
+                                 "parts = [0.0,"),
 }
 
 
@@ -124,8 +142,19 @@ def check_linear_residual_decay(m):
         np.testing.assert_allclose(b["r1"], (1 - a["alpha"]) * a["r1"], atol=1e-10)
 
 
+def check_barrier_rule(m):
+    bad = tb.rule_case_errors(m)
+    assert not bad, bad
+
+
+def check_scalar_mu_sequence(m):
+    got, _ = tb.scalar_mu_sequence(m)
+    np.testing.assert_allclose(got, tb._golden()["scalar_sequence"]["mu"], rtol=1e-12, atol=0)
+
+
 CHECKS = [check_simulation, check_objective, check_full_space, check_ftb, check_riccati,
-          check_active_set, check_tight_converges, check_linear_residual_decay]
+          check_active_set, check_tight_converges, check_linear_residual_decay,
+          check_barrier_rule, check_scalar_mu_sequence]
 
 
 def run_checks(m):
