@@ -245,6 +245,12 @@ int cmpc_batch_tune(cmpc_batch* b, int precision, cmpc_tune_report* rep);
  * if present, 1 if not. */
 int cmpc_tune_lookup(int n, int mx, int precision, int* quantum, int* persistent);
 
+/* Record a tuning-table entry for (n, mx, precision), e.g. one that cmpc_tune_lookup returned
+ * in an earlier process: later solves of a problem with that key build their SYRK plan with
+ * this work quantum (>= 256) and grid policy (persistent 0 or 1).  A batch whose instances'
+ * plans change this way rebuilds its work lists and graph at its next solve. */
+int cmpc_tune_store(int n, int mx, int precision, int quantum, int persistent);
+
 /* Empty the tuning table (plans are rebuilt with the defaults at the next solve). */
 void cmpc_tune_clear(void);
 

@@ -25,7 +25,7 @@ EXPORTS = [
     "cmpc_problem_info", "cmpc_set_x0", "cmpc_solve", "cmpc_get_solution", "cmpc_get_iterate", "cmpc_export_dense",
     "cmpc_form_condensed", "cmpc_newton_step", "cmpc_potrf", "cmpc_potrs", "cmpc_batch_create",
     "cmpc_batch_destroy", "cmpc_batch_size", "cmpc_batch_instance", "cmpc_batch_solve",
-    "cmpc_batch_tune", "cmpc_tune_lookup", "cmpc_tune_clear", "cmpc_default_train_opts",
+    "cmpc_batch_tune", "cmpc_tune_lookup", "cmpc_tune_store", "cmpc_tune_clear", "cmpc_default_train_opts",
     "cmpc_mlp_create", "cmpc_mlp_destroy", "cmpc_mlp_param_count", "cmpc_mlp_get_params",
     "cmpc_mlp_set_params", "cmpc_mlp_gradients", "cmpc_mlp_train", "cmpc_mlp_predict",
     "cmpc_judge", "cmpc_surrogate_solve", "cmpc_last_error", "cmpc_status_str",
@@ -134,6 +134,7 @@ def load(path: str = LIB_PATH):
         "cmpc_batch_solve": (i, [vp, ctypes.POINTER(Options), ctypes.POINTER(Result)]),
         "cmpc_batch_tune": (i, [vp, i, ctypes.POINTER(TuneReport)]),
         "cmpc_tune_lookup": (i, [i, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
+        "cmpc_tune_store": (i, [i, i, i, i, i]),
         "cmpc_tune_clear": (None, []),
         "cmpc_default_train_opts": (None, [ctypes.POINTER(TrainOpts)]),
         "cmpc_mlp_create": (i, [vp, i, i, i, vp, ctypes.POINTER(vp)]),
@@ -484,6 +485,11 @@ def tune_lookup(n, mx, precision=FP64):
     q, pers = ctypes.c_int(), ctypes.c_int()
     rc = load().cmpc_tune_lookup(n, mx, precision, ctypes.byref(q), ctypes.byref(pers))
     return (q.value, pers.value) if rc == 0 else None
+
+
+def tune_store(n, mx, precision, quantum, persistent=1):
+    """Record a tuning-table entry (SYRK work quantum and grid policy) for (n, mx, precision)."""
+    _check(load().cmpc_tune_store(n, mx, precision, quantum, persistent))
 
 
 def tune_clear():

@@ -96,6 +96,7 @@ struct Batch {
   int cus = 256;
   int persistent = 1;
   InstView* views = nullptr;
+  std::vector<InstView> hviews;  // host copy of `views` as uploaded by build_lists
   WorkItem* items = nullptr;
   size_t items_cap = 0;
   List init, blk, gt, n4, one, syrk, fin, n256, gmv, mx256;
@@ -141,6 +142,7 @@ static void free_batch(Batch* b) {
 
 static InstView view_of(const Problem& p) {
   InstView v;
+  std::memset(&v, 0, sizeof(v));  // padding too: views are compared bytewise
   v.ns = p.ns;
   v.nu = p.nu;
   v.N = p.N;
@@ -202,6 +204,7 @@ static int build_lists(Batch& b) {
   for (Problem* p : b.inst) hv.push_back(view_of(*p));
   if (!b.views) CMPC_HIP(hipMalloc(&b.views, sizeof(InstView) * b.count));
   CMPC_HIP(hipMemcpy(b.views, hv.data(), sizeof(InstView) * b.count, hipMemcpyHostToDevice));
+  b.hviews = hv;
   std::vector<WorkItem> all;
   auto add = [&](List& L, auto per) {
     L.off = (int)all.size();
@@ -375,6 +378,14 @@ static int prepare(Batch& b, int precision) {
     }
   }
   CMPC_HIP(hipStreamSynchronize(b.user));  // creation, x0 and conversion work is done
+  // Calls on an instance handle between batch solves (a single solve at another precision
+  // rebuilds that instance's SYRK plan and frees the old one; a first BF16 solve allocates
+  // its bfloat16 copy of Gamma) change what its view points to: the device views, the work
+  // lists and the captured graph are rebuilt whenever any view differs from the uploaded one.
+  for (int i = 0; i < b.count && !any && b.lists_valid; ++i) {
+    const InstView v = view_of(*b.inst[i]);
+    any = std::memcmp(&v, &b.hviews[i], sizeof(InstView)) != 0;
+  }
   if (any || !b.lists_valid) {
     drop_graph(b);
     const int rc = build_lists(b);
@@ -643,6 +654,17 @@ int cmpc_tune_lookup(int n, int mx, int precision, int* quantum, int* persistent
   if (!tune_lookup(n, mx, precision, &tv)) return 1;
   if (quantum) *quantum = tv.quantum;
   if (persistent) *persistent = tv.persistent;
+  return 0;
+}
+
+int cmpc_tune_store(int n, int mx, int precision, int quantum, int persistent) {
+  if (n <= 0 || mx <= 0 || quantum < 256 || (persistent != 0 && persistent != 1) ||
+      (precision != CMPC_FP64 && precision != CMPC_FP32_SYRK && precision != CMPC_BF16_SYRK)) {
+    set_error("cmpc_tune_store: need n, mx > 0, quantum >= 256, persistent 0 or 1 and a "
+              "supported precision");
+    return CMPC_ERR_INVALID;
+  }
+  tune_store(n, mx, precision, TuneVal{quantum, persistent, 0.0});
   return 0;
 }
 

@@ -494,6 +494,10 @@ __device__ __forceinline__ void mu_rhs_body(int bid,
     const double* __restrict__ v, double* __restrict__ rhs, int n, IpmState* st, int fixed_mu,
     const double* __restrict__ gt_part = nullptr, int ns = 0, int nu = 0) {
   if (st->done) return;
+  // The barrier parameter of the previous iteration, read by every thread before the
+  // exchange barrier below: thread 0 stores the new one at the end, and a wavefront reading
+  // st->mu after the barrier could see it.
+  const double mu_prev = st->mu;
   double nr1 = 0.0, f = 0.0;
   for (int c = threadIdx.x; c < n; c += 256) {
     if (gt_part != nullptr) {
@@ -536,7 +540,7 @@ __device__ __forceinline__ void mu_rhs_body(int bid,
   szmax = fmax(fmax(shr[5][0], shr[5][1]), fmax(shr[5][2], shr[5][3]));
   szmin = fmin(fmin(shr[6][0], shr[6][1]), fmin(shr[6][2], shr[6][3]));
   __syncthreads();  // shr is written again by a workgroup's next item (batch lists)
-  double mu = st->mu;
+  double mu = mu_prev;
   bool stop = false;
   if (!fixed_mu) {
     const double e0 = fmax(fmax(nr1, nr3), fmax(nlz, szmax));

@@ -223,3 +223,37 @@ def test_batch_mixed_equals_single_mixed(batch):
         assert r["iters"] == results[i]["iters"]
         assert r["precision_switch_iter"] == results[i]["precision_switch_iter"]
         assert np.array_equal(ub, us)
+
+
+def test_batch_rebuilds_views_after_instance_calls(batch):
+    """Single solves on instance handles between batch solves: with a tuning-table quantum
+    that differs from the batch's, each one rebuilds its instance's SYRK plan (the old plan's
+    device memory is freed), and a first BF16 solve allocates the instance's bfloat16 copy of
+    Gamma.  The next batch solve at the same precision sees no plan change of its own, so it
+    must notice the changed instances and rebuild its device views, work lists and graph; it
+    then equals the single solves bit for bit and matches the oracle."""
+    probs, b, refs = batch
+    condmpc.tune_clear()
+    rc, _ = b.solve(precision=condmpc.FP32_SYRK)   # views, lists and graph on the default plans
+    assert rc == condmpc.OK
+    for i in range(len(probs)):
+        for prec in (condmpc.FP32_SYRK, condmpc.BF16_SYRK):
+            condmpc.tune_store(b[i].n, b[i].mx, prec, 3000, 1)
+    singles = []
+    for i in range(len(probs)):
+        r = b[i].solve(precision=condmpc.FP32_SYRK)  # re-plans instance i (quantum 3000)
+        singles.append((r, b[i].solution(with_x=False)[0]))
+    rc, results = b.solve(precision=condmpc.FP32_SYRK)
+    assert rc == condmpc.OK
+    for i, ((r, us), res, ref) in enumerate(zip(singles, results, refs)):
+        ub, _ = b[i].solution(with_x=False)
+        assert res["iters"] == r["iters"] and np.array_equal(ub, us), f"instance {i}"
+        check_against_oracle(f"replanned {i}", res, ref, ub, iters_equal=False)
+    for i in range(len(probs)):
+        b[i].solve(precision=condmpc.BF16_SYRK)      # allocates the bfloat16 copy
+    rc, results = b.solve(precision=condmpc.BF16_SYRK)
+    assert rc == condmpc.OK
+    for i, (res, ref) in enumerate(zip(results, refs)):
+        ub, _ = b[i].solution(with_x=False)
+        check_against_oracle(f"bf16 after singles {i}", res, ref, ub, iters_equal=False)
+    condmpc.tune_clear()
