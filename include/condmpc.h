@@ -83,6 +83,15 @@ typedef struct {
                         ms_syrk, ms_form, ms_potrf) */
   int equilibrate;   /* factor S K S with S = diag(K)^-1/2 instead of K: 1 on, 0 off,
                         -1 (default) on in the mixed modes only */
+  double refine_contract; /* mixed modes: a refinement step whose FP64 residual exceeds
+                             refine_contract x the previous step's counts as not contracting
+                             (default 0.1; two such steps move the SYRK one level up) */
+  void (*log)(const char* line, void* ctx); /* cmpc_solve only, if not NULL: called from the
+                             calling thread once per iteration with a one-line summary (barrier
+                             parameter, KKT error and residual norms at the top of the
+                             iteration, step lengths, SYRK precision level) and once at the
+                             end; the line is valid during the call only (default NULL) */
+  void* log_ctx;     /* passed to log unchanged */
 } cmpc_options;
 
 typedef struct {

@@ -40,11 +40,16 @@ class LQDesc(ctypes.Structure):
                 ("xl", _dp), ("xu", _dp), ("ul", _dp), ("uu", _dp)]
 
 
+LOG_FN = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_void_p)
+
+
 class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("precision", ctypes.c_int), ("max_refine", ctypes.c_int),
                 ("mu_switch", ctypes.c_double), ("check_every", ctypes.c_int),
-                ("profile", ctypes.c_int), ("equilibrate", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("equilibrate", ctypes.c_int),
+                ("refine_contract", ctypes.c_double), ("log", LOG_FN),
+                ("log_ctx", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -251,8 +256,13 @@ class Problem:
         x = _f64(x0)
         return _check(load().cmpc_set_x0(self._h, x.ctypes.data_as(ctypes.c_void_p), 0))
 
-    def solve(self, **opts) -> dict:
+    def solve(self, log=None, **opts) -> dict:
+        """Algorithm 1 from the start point; log: callable receiving one line (str) per
+        iteration and one at the end."""
         o = default_options(**opts)
+        if log is not None:
+            fn = LOG_FN(lambda line, ctx: log(line.decode()))
+            o.log = fn                      # referenced by `fn` for the duration of the call
         r = Result()
         rc = load().cmpc_solve(self._h, ctypes.byref(o), ctypes.byref(r))
         _check(rc, allow_positive=True)

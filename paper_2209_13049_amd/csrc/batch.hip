@@ -407,7 +407,8 @@ static int batch_solve(Batch& b, const cmpc_options& o, cmpc_result* res) {
     if (rc) return rc;
   }
   CMPC_HIP(hipEventRecord(b.ev0, b.stream));
-  if (launch_b_init(arg(b, b.init), o.tol, o.max_iter, mixed, o.mu_switch)) return CMPC_ERR_HIP;
+  if (launch_b_init(arg(b, b.init), o.tol, o.max_iter, mixed, o.mu_switch,
+                    o.refine_contract)) return CMPC_ERR_HIP;
   if (launch_b_prep(arg(b, b.blk))) return CMPC_ERR_HIP;  // later ones run in the update
   if (launch_b_reset(b.stream, b.d_iter)) return CMPC_ERR_HIP;
   // The publish kernel of iteration it stores (running instances + 1) into ring slot
@@ -505,7 +506,8 @@ static int batch_tune(Batch& b, int precision, cmpc_tune_report* rep) {
     // valid Sigma: the start point of the method, then its fold
     cmpc_options o;
     cmpc_default_options(&o);
-    if (launch_b_init(arg(b, b.init), o.tol, o.max_iter, mixed, o.mu_switch)) return CMPC_ERR_HIP;
+    if (launch_b_init(arg(b, b.init), o.tol, o.max_iter, mixed, o.mu_switch,
+                    o.refine_contract)) return CMPC_ERR_HIP;
     if (launch_b_prep(arg(b, b.blk))) return CMPC_ERR_HIP;
     for (int pers = 0; pers <= 1; ++pers) {
       b.persistent = pers;

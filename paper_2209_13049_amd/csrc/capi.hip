@@ -43,6 +43,7 @@ void free_problem(Problem* p) {
   if (p->st) hipFree(p->st);
   for (hipEvent_t e : p->prof_ev) hipEventDestroy(e);
   if (p->hflags) hipHostFree(p->hflags);
+  if (p->hlog) hipHostFree(p->hlog);
   if (p->ev0) hipEventDestroy(p->ev0);
   if (p->ev1) hipEventDestroy(p->ev1);
   syrk_free(p->syrk);
@@ -359,8 +360,35 @@ int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
     CMPC_HIP(hipHostMalloc((void**)&p.hflags, sizeof(int) * R, hipHostMallocMapped));
     CMPC_HIP(hipHostGetDevicePointer((void**)&p.dflags, p.hflags, 0));
   }
+  if (o.log != nullptr && p.hlog == nullptr) {
+    CMPC_HIP(hipHostMalloc((void**)&p.hlog, sizeof(IterLog) * R, hipHostMallocMapped));
+    CMPC_HIP(hipHostGetDevicePointer((void**)&p.dlog, p.hlog, 0));
+  }
+  IterLog* const dlog_keep = p.dlog;
+  if (o.log == nullptr) p.dlog = nullptr;  // the iteration kernels write no snapshot
   volatile int* hf = p.hflags;
   int rc = 0;
+  // log callback: iteration j's snapshot is read once its flag is set, in order
+  int logged = 0, queued = 0;
+  bool log_done = o.log == nullptr;
+  auto emit = [&](int j) {
+    if (log_done || j != logged) return;
+    const volatile IterLog& e = p.hlog[j % R];
+    char line[320];
+    if (e.done == 2)
+      std::snprintf(line, sizeof line, "iter %d: Cholesky of the low-precision K failed, "
+                    "iteration redone at level %d", j, e.level);
+    else if (e.done == 1)
+      std::snprintf(line, sizeof line, "stop after %d iterations: %s, E0 %.3e, mu %.3e", e.iter,
+                    cmpc_status_str(e.pad), e.err0, e.mu);
+    else
+      std::snprintf(line, sizeof line, "iter %d: mu %.3e E0 %.3e |r1| %.3e |r3| %.3e "
+                    "|lam-z| %.3e max sz %.3e alpha %.3e alpha_z %.3e level %d", j, e.mu, e.err0,
+                    e.nr1, e.nr3, e.nlz, e.szmax, e.alpha, e.alpha_z, e.level);
+    o.log(line, o.log_ctx);
+    ++logged;
+    if (e.done == 1) log_done = true;
+  };
   for (int it = 0; it <= o.max_iter && rc == 0; ++it) {
     if (it >= depth) {
       const int slot = (it - depth) % R;
@@ -381,6 +409,7 @@ int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
         }
       }
       if (rc) break;
+      emit(it - depth);
       if (hf[slot] == 2) break;
     }
     const int slot = it % R;
@@ -396,12 +425,15 @@ int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
                                p.eq_on ? p.eqs : nullptr, p.tmpn);
     if (!rc) rc = launch_step(p, mixed ? o.max_refine : 0);
     if (!rc) rc = launch_update_publish(p, slot);
+    if (!rc) queued = it + 1;
   }
+  p.dlog = dlog_keep;
   if (rc) return rc;
   CMPC_HIP(hipEventRecord(p.ev1, p.stream));
   IpmState hs;
   CMPC_HIP(hipMemcpyAsync(&hs, p.st, sizeof(IpmState), hipMemcpyDeviceToHost, p.stream));
   CMPC_HIP(hipStreamSynchronize(p.stream));
+  for (int j = logged; j < queued && !log_done; ++j) emit(j);  // the last published ones
   const double gap = hs.gap;
   float ms = 0.f;
   hipEventElapsedTime(&ms, p.ev0, p.ev1);
@@ -450,6 +482,9 @@ void cmpc_default_options(cmpc_options* o) {
   o->precision = CMPC_FP64;
   o->max_refine = 5;
   o->mu_switch = 1e-6;
+  o->refine_contract = 0.1;
+  o->log = nullptr;
+  o->log_ctx = nullptr;
   o->check_every = 2;
   o->profile = 0;
   o->equilibrate = -1;

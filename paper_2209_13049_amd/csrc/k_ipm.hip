@@ -317,7 +317,7 @@ __device__ __forceinline__ void ipm_init_body(int bid, const double* __restrict_
                                 double* __restrict__ lam, double* __restrict__ z,
                                 double* __restrict__ v, double* __restrict__ gv, int m, int n,
                                 int mx, IpmState* st, double tol, int max_iter, int low,
-                                double mu_switch) {
+                                double mu_switch, double contract) {
   const long long i = (long long)bid * blockDim.x + threadIdx.x;
   if (i < m) {
     const double di = d[i];
@@ -352,6 +352,7 @@ __device__ __forceinline__ void ipm_init_body(int bid, const double* __restrict_
     st->use_low = low;
     st->mixed = low;
     st->mu_switch = mu_switch;
+    st->contract = contract;
     st->ref_skip = 1;
     st->res_prev = INFINITY;
   }
@@ -361,8 +362,9 @@ __global__ void ipm_init_kernel(const double* __restrict__ d, double* __restrict
                                 double* __restrict__ lam, double* __restrict__ z,
                                 double* __restrict__ v, double* __restrict__ gv, int m, int n,
                                 int mx, IpmState* st, double tol, int max_iter, int low,
-                                double mu_switch) {
-  ipm_init_body(blockIdx.x, d, s, lam, z, v, gv, m, n, mx, st, tol, max_iter, low, mu_switch);
+                                double mu_switch, double contract) {
+  ipm_init_body(blockIdx.x, d, s, lam, z, v, gv, m, n, mx, st, tol, max_iter, low, mu_switch,
+                contract);
 }
 
 int launch_ipm_init(Problem& p, const cmpc_options& o) {
@@ -370,7 +372,7 @@ int launch_ipm_init(Problem& p, const cmpc_options& o) {
   const int low = o.precision == CMPC_BF16_SYRK ? 2 : (o.precision == CMPC_FP32_SYRK ? 1 : 0);
   hipLaunchKernelGGL(ipm_init_kernel, dim3(ceil_div(len, 256)), dim3(256), 0, p.stream, p.d, p.s,
                      p.lam, p.z, p.v, p.gv, p.m, p.n, p.mx, p.st, o.tol, o.max_iter, low,
-                     o.mu_switch);
+                     o.mu_switch, o.refine_contract);
   CMPC_LAUNCH_CHECK();
   return 0;
 }
@@ -788,9 +790,25 @@ __global__ __launch_bounds__(256) void update_kernel(
 
 // End-of-iteration flag for the host: 1 = still running, 2 = done, written with a
 // system-scope release into mapped pinned memory (the host polls it; no copy, no event).
-__global__ void publish_kernel(IpmState* st, int* flag) {
+__global__ void publish_kernel(IpmState* st, int* flag, IterLog* log) {
   const int d = st->done;
-  if (d == 2) st->done = 0;  // the iteration was skipped for a retry in FP64
+  if (log != nullptr) {  // ordered before the flag by the release store
+    IterLog e;
+    e.iter = st->iter;
+    e.level = st->use_low;
+    e.done = d;
+    e.pad = st->status;
+    e.mu = st->mu;
+    e.err0 = st->err0;
+    e.nr1 = st->nr1;
+    e.nr3 = st->nr3;
+    e.nlz = st->nlz;
+    e.szmax = st->szmax;
+    e.alpha = st->alpha;
+    e.alpha_z = st->alpha_z;
+    *log = e;
+  }
+  if (d == 2) st->done = 0;  // the iteration was skipped for a retry one level up
   const int v = d == 1 ? 2 : 1;
   __hip_atomic_store(flag, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
@@ -821,7 +839,8 @@ int launch_update_publish(Problem& p, int slot) {
                      p.s, p.lam, p.z, p.gv, p.v, p.gpv, p.pv, p.ps, p.plam, p.pz, p.alpha_part,
                      p.n_step_blocks, p.mx, p.n, p.st, p.Dx, p.Du, p.wx, p.wu, p.norm_part);
   CMPC_LAUNCH_CHECK();
-  hipLaunchKernelGGL(publish_kernel, dim3(1), dim3(1), 0, p.stream, p.st, p.dflags + slot);
+  hipLaunchKernelGGL(publish_kernel, dim3(1), dim3(1), 0, p.stream, p.st, p.dflags + slot,
+                     p.dlog != nullptr ? p.dlog + slot : nullptr);
   CMPC_LAUNCH_CHECK();
   return 0;
 }
@@ -904,7 +923,7 @@ __device__ __forceinline__ void refine_check_body(int bid,
     if (nr <= 1e-12 * nb) {
       st->ref_skip = 1;
     } else {
-      if (nr > 0.1 * st->res_prev) {
+      if (nr > st->contract * st->res_prev) {
         st->nonc += 1;
         if (st->nonc >= 2 && st->use_low > 0) {  // next iteration one precision level up
           st->use_low -= 1;
@@ -997,10 +1016,11 @@ int launch_step_given(Problem& p, const double* v, const double* s, const double
 __global__ __launch_bounds__(256) void ipm_init_batch_kernel(const InstView* __restrict__ views,
                                                              const WorkItem* __restrict__ items,
                                                              int nitems, double tol, int max_iter,
-                                                             int low, double mu_switch) {
+                                                             int low, double mu_switch,
+                                                             double contract) {
   CMPC_ITEMS_BEGIN
   ipm_init_body(bid, V.d, V.s, V.lam, V.z, V.v, V.gv, V.m, V.n, V.mx, V.st, tol, max_iter, low,
-                mu_switch);
+                mu_switch, contract);
   CMPC_ITEMS_END
 }
 
@@ -1142,8 +1162,9 @@ __global__ void gather_state_kernel(const InstView* __restrict__ views, int coun
   if (i < count) out[i] = *views[i].st;
 }
 
-int launch_b_init(const ListArg& L, double tol, int max_iter, int low, double mu_switch) {
-  CMPC_LAUNCH_LIST(ipm_init_batch_kernel, L, tol, max_iter, low, mu_switch);
+int launch_b_init(const ListArg& L, double tol, int max_iter, int low, double mu_switch,
+                  double contract) {
+  CMPC_LAUNCH_LIST(ipm_init_batch_kernel, L, tol, max_iter, low, mu_switch, contract);
 }
 int launch_b_prep(const ListArg& L) { CMPC_LAUNCH_LIST(prep_batch_kernel, L); }
 int launch_b_gamma_t_partial(const ListArg& L, int nv) {

@@ -1,6 +1,6 @@
 // Formation of the condensed matrix K = Hbase + Gamma' diag(D) Gamma + diag(Ddiag)
 // (left-hand side of eqn. (cond_KKT) after folding the two-sided bound rows; the paper's
-// Section 4 names this condensation as the step whose cost grows with the row count of J).
+// Section 5 names this condensation as the step whose cost grows with the row count of J).
 //
 // Design (gfx950):
 //  * Gamma is stored packed by row block t (ns x t nu), so only its structural nonzeros

@@ -26,9 +26,17 @@ struct IpmState {
   int ref_skip;  // mixed modes: nonzero = no (more) refinement in this iteration
   int mixed;     // starting precision level of the solve (0 = plain FP64)
   double mu_switch, res_prev;
+  double contract;  // mixed modes: a refinement step must shrink |res| below contract x the last
 };
 
 constexpr int kRunning = 100;
+
+// Snapshot of one iteration for the host's log callback (written by the iteration's last
+// kernel into a mapped pinned ring next to its flag).
+struct IterLog {
+  int iter, level, done, pad;
+  double mu, err0, nr1, nr3, nlz, szmax, alpha, alpha_z;
+};
 
 // One split-K job of the SYRK: rows [r0, r1) of row block t (1-based) contribute to
 // output tile `tile`; slot >= 0 means the accumulator is written to partial slot `slot`
@@ -89,6 +97,8 @@ struct Problem {
   std::vector<hipEvent_t> prof_ev;  // per iteration: SYRK begin/end, Cholesky begin/end
   int* hflags = nullptr;            // mapped pinned ring: 0 pending, 1 running, 2 done
   int* dflags = nullptr;            // device alias of hflags
+  IterLog* hlog = nullptr;          // mapped pinned ring of iteration snapshots (log callback)
+  IterLog* dlog = nullptr;          // device alias of hlog
   std::vector<double> xl_host, xu_host;
 };
 
@@ -199,7 +209,8 @@ inline int grid_for(const ListArg& L, const void* kernel) {
 
 // ---- work-list launchers (k_ipm.hip, k_syrk.hip, k_chol.hip); a list of length 0 launches
 // nothing.  gate / which: 0 = the solve, 1 = the refinement (see gate_of).
-int launch_b_init(const ListArg& L, double tol, int max_iter, int low, double mu_switch);
+int launch_b_init(const ListArg& L, double tol, int max_iter, int low, double mu_switch,
+                  double contract);
 int launch_b_prep(const ListArg& L);
 int launch_b_gamma_t_partial(const ListArg& L, int nv);
 int launch_b_gamma_t_reduce(const ListArg& L, int nv);

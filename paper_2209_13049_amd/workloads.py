@@ -7,7 +7,7 @@ interior-point step); both the HIP library's tests and the CPU oracle take their
 from here.
 
 Workloads are explicit-Euler finite-difference heat equations with boundary or distributed
-actuators, the family of the paper's Section 4 (a PDE temperature-control problem whose
+actuators, the family of the paper's Section 5 (a PDE temperature-control problem whose
 states are interior grid temperatures and whose inputs act through the boundary).
 
 Seeds: ``numpy.random.default_rng([config_id, instance_id])``.
@@ -162,14 +162,14 @@ def heat2d(g: int = 70, nu_per_edge: int = 5, N: int = 100, seed=(2, 0), *, r: f
                      meta={"seed": list(seed)})
 
 
-# Table 1 of the paper: the copper cube of the 3-D temperature-control problem (Section 4).
+# Table 1 of the paper: the copper cube of the 3-D temperature-control problem (Section 5).
 HEAT3D_TABLE1 = dict(dt=0.1, dw=0.02, rho=8960.0, cp=386.0, k=400.0, xl=200.0, xu=550.0,
                      ul=300.0, uu=500.0, xhat=300.0)
 
 
 def heat3d_dynamics(m: int, dt: float = 0.1, dw: float = 0.02, rho: float = 8960.0,
                     cp: float = 386.0, k: float = 400.0):
-    """3-D 7-point explicit-Euler heat step on the m^3 interior nodes of a cube (Section 4,
+    """3-D 7-point explicit-Euler heat step on the m^3 interior nodes of a cube (Section 5,
     eqn. (3DPDE), Table 1): x+ = x + r (sum of the 6 neighbours - 6 x), r = k dt / (rho cp dw^2).
 
     The 6 faces are the inputs (Dirichlet values, not states): a neighbour that lies on face

@@ -62,6 +62,10 @@ def test_struct_layouts_match_header():
             decl = decl.strip()
             if not decl:
                 continue
+            fp = re.match(r"[^(]*\(\*\s*([A-Za-z_][A-Za-z0-9_]*)\s*\)", decl)
+            if fp:  # function pointer: void (*name)(args)
+                names.append(fp.group(1))
+                continue
             for part in decl.split(","):
                 names.append(re.findall(r"[A-Za-z_][A-Za-z0-9_]*", part)[-1])
         return names

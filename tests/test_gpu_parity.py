@@ -369,3 +369,133 @@ def test_equilibrated_fp64_solve(problems, name):
     assert res["status"] == condmpc.OK and res["iters"] == ref.iters
     assert abs(res["obj"] - ref.obj) <= 1e-8 * max(1.0, abs(ref.obj))
     assert res["primal_res"] <= 1e-8 and res["dual_res"] <= 1e-8
+
+
+# ----------------------------------------------------------------- the benchmarked workload
+CONFIG2 = [("seed0", 0, {}), ("seed1", 1, {}), ("seed2", 2, {}),
+           ("tight", 0, {"xu": 0.05, "x0_range": (-0.4, 0.04)})]
+
+
+@pytest.fixture(scope="module")
+def config2(lib):
+    """The benchmarked 1-D heat workload (ns 1000, nu 10, N 50: K 500 x 500, 50,000 state
+    rows) for three x0 seeds and the tight-bound variant (thousands of active rows)."""
+    out = {}
+    for name, inst, kw in CONFIG2:
+        p = W.heat1d_config("1d", instance=inst, **kw)
+        print(f"[config2] oracle {name}", flush=True)
+        out[name] = (p, oracle.solve(p))
+    yield out
+
+
+@pytest.mark.parametrize("name", [c[0] for c in CONFIG2])
+def test_config2_matches_oracle(config2, name):
+    """FP64: same status and iteration count as the oracle, objective within 1e-8, residuals
+    within 1e-8; FP32 and BF16 starts: the same bar on the objective and the residuals."""
+    p, ref = config2[name]
+    gp = condmpc.Problem(p)
+    gp.set_x0(p.x0)
+    try:
+        for prec, label in ((condmpc.FP64, "fp64"), (condmpc.FP32_SYRK, "fp32"),
+                            (condmpc.BF16_SYRK, "bf16")):
+            res = gp.solve(precision=prec)
+            u, x = gp.solution()
+            err = abs(res["obj"] - ref.obj) / max(1.0, abs(ref.obj))
+            print(f"[config2] {name} {label}: iters {res['iters']} (oracle {ref.iters}) obj "
+                  f"rel err {err:.2e} |u-u*| {rel_err(u, ref.v):.2e} switch "
+                  f"{res['precision_switch_iter']} refine {res['refine_steps']}", flush=True)
+            assert res["status"] == condmpc.OK == ref.status
+            if prec == condmpc.FP64:
+                assert res["iters"] == ref.iters
+            else:
+                assert abs(res["iters"] - ref.iters) <= 4
+            assert err <= 1e-8
+            assert res["primal_res"] <= 1e-8 and res["dual_res"] <= 1e-8
+            assert res["compl_res"] <= 1e-8
+            assert rel_err(u, ref.v) <= 1e-6 and rel_err(x, ref.x) <= 1e-6
+    finally:
+        gp.close()
+
+
+def test_config2_log_follows_the_oracle_barrier_sequence(config2):
+    """The per-iteration log of an FP64 solve: one line per iteration and a final one; its
+    barrier parameters are the oracle's, iteration by iteration."""
+    p, ref = config2["seed0"]
+    rec = oracle.solve(p, record=True)
+    gp = condmpc.Problem(p)
+    gp.set_x0(p.x0)
+    lines = []
+    res = gp.solve(log=lines.append)
+    gp.close()
+    print("\n".join(lines), flush=True)
+    assert len(lines) == res["iters"] + 1
+    assert lines[-1].startswith(f"stop after {res['iters']} iterations")
+    mus = [float(l.split(" mu ")[1].split()[0]) for l in lines[:-1]]
+    np.testing.assert_allclose(mus, [h["mu"] for h in rec.history], rtol=1e-3)
+
+
+# ----------------------------------------------------------------- precision-level moves
+@pytest.mark.parametrize("start", [condmpc.FP32_SYRK, condmpc.BF16_SYRK])
+def test_precision_moves_by_refinement(problems, start):
+    """refine_contract = 0 counts every refinement step of an iteration after its first as not
+    contracting, and mu_switch = 0 disables the switch by the barrier parameter: the SYRK
+    moves up one level per two counts (BF16 -> FP32 -> FP64, or FP32 -> FP64) within the
+    first iterations (an iteration whose refinement reaches 1e-12 stops early and counts
+    fewer); the solve still meets the FP64 bar."""
+    p, gp, red = problems["tight"]
+    ref = oracle.solve(p, red=red)
+    res = gp.solve(precision=start, refine_contract=0.0, mu_switch=0.0)
+    print(f"[moves] start {start}: switch {res['precision_switch_iter']} refine "
+          f"{res['refine_steps']} iters {res['iters']}", flush=True)
+    assert res["status"] == condmpc.OK
+    assert 1 <= res["precision_switch_iter"] <= 3
+    assert res["refine_steps"] >= (4 if start == condmpc.BF16_SYRK else 2)
+    assert abs(res["obj"] - ref.obj) <= 1e-8 * max(1.0, abs(ref.obj))
+    assert res["primal_res"] <= 1e-8 and res["dual_res"] <= 1e-8
+
+
+def test_precision_switch_by_barrier(problems):
+    """Default rule, FP32 start: refinement runs (steps > 0) and the SYRK moves to FP64 no
+    later than the first iteration whose barrier parameter is below mu_switch = 1e-6."""
+    p, gp, red = problems["tight"]
+    rec = oracle.solve(p, red=red, record=True)
+    res = gp.solve(precision=condmpc.FP32_SYRK)
+    first_small = next(h["k"] for h in rec.history if h["mu"] < 1e-6)
+    print(f"[switch] FP32 start: switch {res['precision_switch_iter']} (oracle mu < 1e-6 at "
+          f"{first_small}) refine {res['refine_steps']}", flush=True)
+    assert res["refine_steps"] > 0
+    assert 0 < res["precision_switch_iter"] <= first_small + 2
+
+
+def test_no_refinement_no_moves(problems):
+    """max_refine = 0 and mu_switch = 0: no refinement step and no level change (the FP32
+    Newton directions are used as they are) over the first iterations."""
+    p, gp, red = problems["small"]
+    res = gp.solve(precision=condmpc.FP32_SYRK, max_refine=0, mu_switch=0.0, max_iter=6)
+    assert res["refine_steps"] == 0 and res["precision_switch_iter"] == -1
+    assert res["status"] in (condmpc.OK, condmpc.MAX_ITER)
+
+
+# ----------------------------------------------------------------- the 2-D 70 x 70 workload
+def test_heat2d_70x70_reduced_horizon(lib):
+    """The 2-D heat grid of the largest workload (70 x 70 interior nodes, 4900 states, 20
+    boundary actuators) at horizon N = 12 (K 240 x 240, 58,800 state rows) against the
+    oracle: FP64 with the oracle's iteration count, FP32 and BF16 starts on the FP64 bar."""
+    p = W.heat2d(70, 5, 12, seed=(2, 0))
+    ref = oracle.solve(p)
+    gp = condmpc.Problem(p)
+    gp.set_x0(p.x0)
+    try:
+        for prec in (condmpc.FP64, condmpc.FP32_SYRK, condmpc.BF16_SYRK):
+            res = gp.solve(precision=prec)
+            u, _ = gp.solution(with_x=False)
+            print(f"[heat2d] prec {prec}: iters {res['iters']} (oracle {ref.iters}) obj "
+                  f"{res['obj']:.12e} vs {ref.obj:.12e}", flush=True)
+            assert res["status"] == condmpc.OK == ref.status
+            if prec == condmpc.FP64:
+                assert res["iters"] == ref.iters
+            assert abs(res["obj"] - ref.obj) <= 1e-8 * max(1.0, abs(ref.obj))
+            assert res["primal_res"] <= 1e-8 and res["dual_res"] <= 1e-8
+            assert rel_err(u, ref.v) <= 1e-6
+    finally:
+        gp.close()

@@ -338,7 +338,7 @@ def test_config_1d_no_bound_active_matches_riccati():
 
 
 def test_heat3d_generator_table1():
-    """The 3-D cube of Section 4 with Table 1's constants: r = k dt / (rho cp dw^2); a uniform
+    """The 3-D cube of Section 5 with Table 1's constants: r = k dt / (rho cp dw^2); a uniform
     temperature with every face at that temperature is a steady state (A 1 + B 1 = 1); each face
     touches m^2 interior nodes; the step is symmetric and stable."""
     m = 4
