@@ -39,6 +39,11 @@ R10 After each update z is safeguarded into [mu / (kappa_S s), kappa_S mu / s],
     kappa_S = 1e10.
 R11 Termination: E_0 = max(|r1|, |r3|, |lambda - z|, |s z|) <= tol (unscaled inf-norms),
     checked at the top of every iteration; iteration limit 200.
+R14 Receding horizon (Section 1: the controller solves the problem from each measured state
+    and applies the first input): a solve may start from given controls v0 instead of 0,
+    with s, lambda and z as in R7 at that v0 and the barrier parameter starting at
+    WARM_MU_INIT = 1e-3; the warm start of the next step is the previous step's controls
+    shifted one stage earlier, the last stage repeated (``shift_controls``).
 """
 from __future__ import annotations
 
@@ -53,6 +58,7 @@ THETA_MU = 1.5
 KAPPA_SIGMA = 1e10
 TAU_MIN = 0.99
 MU_INIT = 0.1
+WARM_MU_INIT = 1e-3
 S_INIT_MIN = 1e-2
 ALPHA_MIN = 1e-14
 
@@ -236,10 +242,10 @@ class Result:
     history: list = field(default_factory=list)
 
 
-def initial_point(red: Reduced, mu0: float = MU_INIT):
-    """Reading R7."""
+def initial_point(red: Reduced, mu0: float = MU_INIT, v0=None):
+    """Reading R7 (v0 = None: v = 0), or reading R14 from the controls v0."""
     n = red.H.shape[0]
-    v = np.zeros(n)
+    v = np.zeros(n) if v0 is None else np.array(v0, dtype=np.float64)
     s = np.maximum(red.d - red.J @ v, S_INIT_MIN)
     lam = mu0 / s
     z = lam.copy()
@@ -247,13 +253,14 @@ def initial_point(red: Reduced, mu0: float = MU_INIT):
 
 
 def solve(prob, tol: float = 1e-8, max_iter: int = 200, red: Reduced | None = None,
-          callback=None, record: bool = False) -> Result:
-    """Algorithm 1 (condensed-space interior-point method) with readings R7-R11."""
+          callback=None, record: bool = False, v0=None, mu0: float | None = None) -> Result:
+    """Algorithm 1 (condensed-space interior-point method) with readings R7-R11; v0 starts
+    from given controls (reading R14, barrier parameter mu0, default WARM_MU_INIT)."""
     if red is None:
         red = reduce_problem(prob)
-    mu = MU_INIT
+    mu = (MU_INIT if v0 is None else WARM_MU_INIT) if mu0 is None else mu0
     mu_min = tol / 10.0
-    v, s, lam, z = initial_point(red, mu)
+    v, s, lam, z = initial_point(red, mu, v0)
     history = []
     status, k = STATUS_MAX_ITER, 0
     for k in range(max_iter + 1):
@@ -321,3 +328,33 @@ def sparse_objective(prob, u: np.ndarray) -> float:
         W = prob.Qf if t == N else prob.Q
         f += 0.5 * xt @ W @ xt
     return float(f)
+
+
+def shift_controls(v: np.ndarray, nu: int, N: int) -> np.ndarray:
+    """Warm start of the next receding-horizon step (reading R14): stage t of the result is
+    stage t + 1 of v (t = 0..N-2), and the last stage repeats stage N-1 of v."""
+    v = np.asarray(v, dtype=np.float64)
+    return np.concatenate([v[nu:nu * N], v[nu * (N - 1):nu * N]])
+
+
+def closed_loop(prob, steps: int, warm: bool = True, tol: float = 1e-8):
+    """Receding-horizon control of the model itself (Section 1): from x0, solve, apply the
+    first input u_0, step the dynamics x+ = A x + B u_0, and solve again from x+; with
+    warm, each solve after the first starts from the previous controls shifted
+    (reading R14).  Returns the states x_0..x_steps, the applied inputs and the results."""
+    from dataclasses import replace
+    nu, N = prob.B.shape[1], int(prob.N)
+    x = np.array(prob.x0, dtype=np.float64)
+    xs, us, results = [x.copy()], [], []
+    v_prev = None
+    for _ in range(steps):
+        p = replace(prob, x0=x.copy())
+        v0 = shift_controls(v_prev, nu, N) if (warm and v_prev is not None) else None
+        r = solve(p, tol=tol, v0=v0)
+        results.append(r)
+        u0 = r.v[:nu].copy()
+        us.append(u0)
+        x = prob.A @ x + prob.B @ u0
+        xs.append(x.copy())
+        v_prev = r.v
+    return np.array(xs), np.array(us), results

@@ -59,6 +59,16 @@ MUTATIONS = {
                                         "np.max(np.abs(s * z), initial=0.0)]"),
     "emu_stationarity_dropped": ("parts = [np.max(np.abs(r1), initial=0.0),",
                                  "parts = [0.0,"),
+    # the receding-horizon warm start (reading R14)
+    "shift_wrong_direction": ("return np.concatenate([v[nu:nu * N], v[nu * (N - 1):nu * N]])",
+                              "return np.concatenate([v[:nu], v[:nu * (N - 1)]])"),
+    "shift_last_stage_zero": ("return np.concatenate([v[nu:nu * N], v[nu * (N - 1):nu * N]])",
+                              "return np.concatenate([v[nu:nu * N], 0.0 * v[:nu]])"),
+    "warm_start_ignored": ("v = np.zeros(n) if v0 is None else np.array(v0, dtype=np.float64)",
+                           "v = np.zeros(n)"),
+    "warm_mu_cold_value": ("WARM_MU_INIT = 1e-3\nS_INIT_MIN", "WARM_MU_INIT = 0.1\nS_INIT_MIN"),
+    "closed_loop_last_input": ("u0 = r.v[:nu].copy()", "u0 = r.v[-nu:].copy()"),
+    "closed_loop_no_input": ("x = prob.A @ x + prob.B @ u0", "x = prob.A @ x"),
 }
 
 
@@ -152,9 +162,45 @@ def check_scalar_mu_sequence(m):
     np.testing.assert_allclose(got, tb._golden()["scalar_sequence"]["mu"], rtol=1e-12, atol=0)
 
 
+def check_shift(m):
+    v = np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0])
+    assert np.array_equal(m.shift_controls(v, 2, 3), [3.0, 4.0, 5.0, 6.0, 5.0, 6.0])
+
+
+def check_warm_start_point(m):
+    """The start point from given controls (reading R14): r3 = 0 on rows with slack >= 1e-2,
+    lambda s = 1e-3, and the first barrier parameter of a start far from the solution is
+    that value."""
+    p = W.heat1d(20, 2, 6, seed=(0, 2), xu=0.05, x0_range=(-0.4, 0.04))
+    red = m.reduce_problem(p)
+    v0 = np.random.default_rng(5).uniform(-1.5, 1.5, p.n)
+    r = m.solve(p, red=red, v0=v0, record=True, max_iter=1)
+    assert r.history[0]["mu"] == 1e-3
+    v, s, lam, z = m.initial_point(red, 1e-3, v0)
+    slack = red.d - red.J @ v0
+    inside = slack >= 1e-2
+    r3 = red.J @ v - red.d + s
+    np.testing.assert_allclose(r3[inside], 0.0, atol=1e-14)
+    np.testing.assert_allclose(r3[~inside], 1e-2 - slack[~inside], rtol=1e-12)
+
+
+def check_closed_loop_lqr(m):
+    p = random_stable(4, 2, 6, 0, bound_x=1e3, bound_u=1e3)
+    P, K = p.Qf.copy(), None
+    for _ in range(p.N):
+        K = np.linalg.solve(p.R + p.B.T @ P @ p.B, p.B.T @ P @ p.A)
+        P = p.Q + p.A.T @ P @ (p.A - p.B @ K)
+    xs, us, _ = m.closed_loop(p, 3, warm=True)
+    x = p.x0.copy()
+    for k in range(3):
+        x = (p.A - p.B @ K) @ x
+        assert np.max(np.abs(xs[k + 1] - x)) <= 1e-7
+
+
 CHECKS = [check_simulation, check_objective, check_full_space, check_ftb, check_riccati,
           check_active_set, check_tight_converges, check_linear_residual_decay,
-          check_barrier_rule, check_scalar_mu_sequence]
+          check_barrier_rule, check_scalar_mu_sequence, check_shift, check_warm_start_point,
+          check_closed_loop_lqr]
 
 
 def run_checks(m):
