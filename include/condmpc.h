@@ -193,6 +193,18 @@ int cmpc_newton_step(cmpc_problem* p, const double* v, const double* s, const do
  * the stream. */
 int cmpc_potrf(double* K, int n, int ld, void* stream, int* info);
 
+/* cmpc_potrf for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same factorisation, kernels and
+ * results, but its scratch (the 64 x 64 tile inverses and the status flags) is a fixed
+ * file-scope device array of the library, 2 MiB per device, held until the process ends; the
+ * call allocates nothing.  n <= CMPC_POTRF_NOALLOC_MAX_N, else CMPC_ERR_INVALID.  The
+ * stream's device (the current device if stream is NULL) is the one used.  Every call on a
+ * device shares that device's array: calls that overlap on one device (other streams or
+ * threads) race and must be serialised by the caller.  Synchronises the stream, as
+ * cmpc_potrf does. */
+#define CMPC_POTRF_NOALLOC_MAX_N 4096
+int cmpc_potrf_noalloc(double* K, int n, int ld, void* stream, int* info);
+
 /* Solve L L' x = b in place (b: n, device) with the factor from cmpc_potrf. */
 int cmpc_potrs(const double* L, int n, int ld, double* b, void* stream);
 

@@ -17,13 +17,14 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcondmpc.
 OK, MAX_ITER, SMALL_STEP = 0, 1, 2
 ERR_INVALID, ERR_NONFINITE, ERR_X0_BOUNDS, ERR_CHOLESKY, ERR_HIP, ERR_NOMEM = -1, -2, -3, -4, -5, -6
 FP64, FP32_SYRK, BF16_SYRK = 0, 1, 2
+POTRF_NOALLOC_MAX_N = 4096
 MLP_BF16, MLP_FP32 = 0, 1
 
 # every function declared in include/condmpc.h
 EXPORTS = [
     "cmpc_default_options", "cmpc_problem_create", "cmpc_problem_destroy", "cmpc_problem_dims",
     "cmpc_problem_info", "cmpc_set_x0", "cmpc_solve", "cmpc_get_solution", "cmpc_get_iterate", "cmpc_export_dense",
-    "cmpc_form_condensed", "cmpc_newton_step", "cmpc_potrf", "cmpc_potrs", "cmpc_batch_create",
+    "cmpc_form_condensed", "cmpc_newton_step", "cmpc_potrf", "cmpc_potrf_noalloc", "cmpc_potrs", "cmpc_batch_create",
     "cmpc_batch_destroy", "cmpc_batch_size", "cmpc_batch_instance", "cmpc_batch_solve",
     "cmpc_batch_tune", "cmpc_tune_lookup", "cmpc_tune_store", "cmpc_tune_clear", "cmpc_default_train_opts",
     "cmpc_mlp_create", "cmpc_mlp_destroy", "cmpc_mlp_param_count", "cmpc_mlp_get_params",
@@ -130,6 +131,7 @@ def load(path: str = LIB_PATH):
         "cmpc_newton_step": (i, [vp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp,
                                  vp, vp, vp]),
         "cmpc_potrf": (i, [vp, i, i, vp, ctypes.POINTER(i)]),
+        "cmpc_potrf_noalloc": (i, [vp, i, i, vp, ctypes.POINTER(i)]),
         "cmpc_potrs": (i, [vp, i, i, vp, vp]),
         "cmpc_batch_create": (i, [i, ctypes.POINTER(LQDesc), ctypes.POINTER(_dp), vp,
                                   ctypes.POINTER(vp)]),
@@ -511,6 +513,16 @@ def potrf(K, ld=None):
     n = K.shape[0]
     info = ctypes.c_int(0)
     rc = load().cmpc_potrf(_dev(K), n, ld or K.shape[1], _stream(), ctypes.byref(info))
+    _check(rc)
+    return info.value
+
+
+def potrf_noalloc(K, ld=None):
+    """cmpc_potrf_noalloc: the same factorisation with the library's fixed device scratch
+    (n <= POTRF_NOALLOC_MAX_N; allocates nothing)."""
+    n = K.shape[0]
+    info = ctypes.c_int(0)
+    rc = load().cmpc_potrf_noalloc(_dev(K), n, ld or K.shape[1], _stream(), ctypes.byref(info))
     _check(rc)
     return info.value
 

@@ -1,6 +1,9 @@
 // C ABI (include/condmpc.h) and the host-side interior-point driver (Algorithm 1).
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "problem.hpp"
@@ -11,6 +14,59 @@ static thread_local std::string g_error;
 void set_error(const std::string& msg) { g_error = msg; }
 
 int launch_convert_gamma(Problem& p, int precision);
+
+// ---- the scratch of cmpc_potrf_noalloc: the tile inverses W_k of the factorisation
+// (4096 doubles per 64-column block) and three status flags, in one file-scope device array
+// of fixed size.  Host code never passes the array's name to a kernel or a copy: it is a
+// host-side stand-in, not a device address.  Each device's copy is looked up once with
+// hipGetSymbolAddress (that device current) and that address is used from then on.
+constexpr size_t kNoAllocWallDoubles = 4096 * (size_t)((CMPC_POTRF_NOALLOC_MAX_N + 63) / 64);
+static __device__ __align__(256) double scratch[kNoAllocWallDoubles + 8];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;  // device ordinal -> address of that device's scratch
+}  // namespace
+
+__global__ void zero_ints_kernel(int* __restrict__ p, int count) {
+  if ((int)threadIdx.x < count) p[threadIdx.x] = 0;
+}
+
+// Address of the scratch array on the device that runs `s` (set up once per device).
+static int potrf_scratch(hipStream_t s, double** out) {
+  int dev = 0;
+  if (s != nullptr) {
+    if (hipStreamGetDevice(s, &dev) != hipSuccess) {
+      set_error("cmpc_potrf_noalloc: cannot tell the stream's device");
+      return CMPC_ERR_HIP;
+    }
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    set_error("cmpc_potrf_noalloc: no current device");
+    return CMPC_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return 0;
+  }
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess || (cur != dev && hipSetDevice(dev) != hipSuccess)) {
+    set_error("cmpc_potrf_noalloc: cannot make the stream's device current");
+    return CMPC_ERR_HIP;
+  }
+  double* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (cur != dev) hipSetDevice(cur);
+  if (e != hipSuccess || ptr == nullptr) {
+    set_error(std::string("cmpc_potrf_noalloc: hipGetSymbolAddress failed: ") +
+              hipGetErrorString(e));
+    return CMPC_ERR_HIP;
+  }
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return 0;
+}
 
 __global__ void add_vec_kernel(const double* __restrict__ a, const double* __restrict__ b,
                                double* __restrict__ out, int len) {
@@ -715,6 +771,41 @@ int cmpc_potrf(double* K, int n, int ld, void* stream, int* info) {
     rc = CMPC_ERR_HIP;
   hipFree(flags);
   hipFree(Wall);
+  if (rc) return rc;
+  if (info) *info = hf[1];
+  if (hf[0]) {
+    set_error("matrix is not positive definite (column " + std::to_string(hf[1]) + ")");
+    return CMPC_ERR_CHOLESKY;
+  }
+  return 0;
+}
+
+int cmpc_potrf_noalloc(double* K, int n, int ld, void* stream, int* info) {
+  if (!K || n <= 0 || ld < n) {
+    set_error("invalid argument");
+    return CMPC_ERR_INVALID;
+  }
+  if (n > CMPC_POTRF_NOALLOC_MAX_N) {
+    set_error("cmpc_potrf_noalloc: n = " + std::to_string(n) + " exceeds its maximum " +
+              std::to_string(CMPC_POTRF_NOALLOC_MAX_N) + " (use cmpc_potrf)");
+    return CMPC_ERR_INVALID;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double* base = nullptr;
+  int rc = potrf_scratch(s, &base);
+  if (rc) return rc;
+  double* Wall = base;
+  int* flags = (int*)(base + kNoAllocWallDoubles);  // done, info, status
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, flags, 3);
+  if (hipGetLastError() != hipSuccess) {
+    set_error("cmpc_potrf_noalloc: launch failed");
+    return CMPC_ERR_HIP;
+  }
+  rc = launch_potrf(s, K, n, ld, Wall, flags, flags + 1, flags + 2);
+  int hf[3] = {0, 0, 0};
+  if (!rc && (hipMemcpyAsync(hf, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+              hipStreamSynchronize(s) != hipSuccess))
+    rc = CMPC_ERR_HIP;
   if (rc) return rc;
   if (info) *info = hf[1];
   if (hf[0]) {
