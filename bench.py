@@ -49,29 +49,66 @@ def measured_traffic():
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(p, solves: int = 1):
-    """The CPU oracle, timed on the host on a bounded sample of the same workload."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(solves: int = 3, gpu_solve=None):
+    """The CPU oracle, timed on the host on a bounded sample of the same workload: the median
+    of `solves` solves with the BLAS threads the host gives it, then one solve on one thread.
+    With gpu_solve(k) -> (iters, obj, primal_res, dual_res), each sampled instance is also
+    solved on the GPU and compared with the oracle's result."""
     import numpy as np
     import oracle
     from paper_2209_13049_amd import workloads as W
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()
                        if i.get("internal_api") in ("openblas", "mkl", "blis")] or [1])
     except Exception:
+        threadpool_limits = None
         threads = len(os.sched_getaffinity(0))
-    total, iters = 0.0, 0
+    times, iters, results = [], 0, []
     for k in range(solves):
         pk = W.heat1d_config("1d", instance=k)
         red = oracle.reduce_problem(pk)
         t0 = time.perf_counter()
         r = oracle.solve(pk, red=red)
-        total += time.perf_counter() - t0
+        times.append(time.perf_counter() - t0)
         iters += r.iters
-    return {"value": solves / total, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{solves} full oracle solve(s) of the same workload (instances 0..{solves - 1}, "
-                      f"{iters} iterations; state elimination built beforehand, not timed)",
-            "s_per_iter": total / max(1, iters)}
+        results.append(r)
+    med = float(np.median(times))
+    out = {"value": 1.0 / med, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"median of {solves} full oracle solves of the same workload (instances "
+                     f"0..{solves - 1}, {iters} iterations in all; state elimination built "
+                     f"beforehand, not timed), BLAS on {threads} threads",
+           "s_per_iter": sum(times) / max(1, iters), "cpu_model": cpu_model(),
+           "affinity_cpus": len(os.sched_getaffinity(0))}
+    if threadpool_limits is not None:
+        pk = W.heat1d_config("1d", instance=0)
+        red = oracle.reduce_problem(pk)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            r1 = oracle.solve(pk, red=red)
+            el = time.perf_counter() - t0
+        out["one_thread"] = {"value": 1.0 / el, "unit": "solves/s", "cores": 1,
+                             "s_per_iter": el / max(1, r1.iters)}
+    if gpu_solve is not None:
+        errs, same_iters, res_max = [], True, 0.0
+        for k, r in enumerate(results):
+            it, obj, pr, dr = gpu_solve(k)
+            errs.append(abs(obj - r.obj) / max(1.0, abs(r.obj)))
+            same_iters = same_iters and it == r.iters
+            res_max = max(res_max, pr, dr)
+        out["parity"] = {"instances": list(range(len(results))), "max_obj_rel_err": max(errs),
+                         "same_iters": same_iters, "max_primal_dual_res": res_max}
+    return out
 
 
 def batch_leg(steps: int, count: int = 512):
@@ -203,6 +240,75 @@ PAPER_SHAPES = [
 ]
 
 
+def heat2d_leg(solves: int):
+    """The 2-D heat workload at full size (70 x 70 interior grid, 4900 states, 20 boundary
+    actuators, N = 100: K 2000 x 2000, Gamma 490,000 x 2000): FP64, then the FP32- and
+    BF16-start mixed modes, `solves` timed solves each after one untimed one, plus one with
+    the SYRK / Cholesky events.  The oracle's dense reduction does not fit at this size, so
+    each result is checked on the CPU through the oracle's forward simulation (eqn. (dyn)):
+    its objective against the reported one and its largest bound violation."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2209_13049_amd import condmpc
+    from paper_2209_13049_amd import workloads as W
+
+    p = W.heat2d(**W.CONFIG_2D, seed=(2, 0))
+    t0 = time.perf_counter()
+    prob = condmpc.Problem(p)
+    prob.set_x0(torch.from_numpy(p.x0).to("cuda:0"))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = prob.info()
+    res = condmpc.Result()
+    out = {"workload": "heat2d_70x70_nu20_N100", "ns": p.ns, "nu": p.nu, "N": p.N,
+           "n": info["n"], "state_rows": info["mx"], "setup_s": setup_s}
+
+    def solve(precision, profile):
+        rc = prob.solve_raw(condmpc.default_options(precision=precision, profile=profile), res)
+        if rc != condmpc.OK:
+            raise RuntimeError(f"heat2d: solve at precision {precision} returned {rc}")
+        return res.iters, res.ms_syrk, res.ms_form, res.ms_potrf, res.obj
+
+    fp64_rate = None
+    for name, prec, peak in (("fp64", condmpc.FP64, PEAK["fp64"]),
+                             ("fp32_start", condmpc.FP32_SYRK, PEAK["fp32"]),
+                             ("bf16_start", condmpc.BF16_SYRK, PEAK["fp32"])):
+        solve(prec, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = 0
+        for _ in range(solves):
+            iters += solve(prec, 0)[0]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        it, ms_syrk, ms_form, ms_potrf, obj = solve(prec, 1)
+        u, _ = prob.solution(with_x=False)
+        x = oracle.simulate(p, u)
+        viol = max(float(np.max(x - np.tile(p.xu, p.N))), float(np.max(np.tile(p.xl, p.N) - x)),
+                   float(np.max(u - np.tile(p.uu, p.N))), float(np.max(np.tile(p.ul, p.N) - u)))
+        f_sim = oracle.sparse_objective(p, u)
+        rate = solves / el
+        fp64_rate = rate if fp64_rate is None else fp64_rate
+        out[name] = {"iters_per_solve": iters / solves, "solves_per_s": rate,
+                     "ms_per_iter": el * 1e3 / max(1, iters),
+                     "ms_per_iter_syrk_potrf": (ms_form + ms_potrf) / max(1, it),
+                     "syrk_ms_per_iter": ms_syrk / max(1, it),
+                     "syrk_achieved_tflops": info["syrk_flops"] / (ms_syrk / 1e3 / max(1, it)) / 1e12,
+                     "syrk_peak_tflops": peak, "obj": obj,
+                     "obj_rel_err_vs_oracle_simulation": abs(obj - f_sim) / max(1.0, abs(f_sim)),
+                     "max_bound_violation": max(0.0, viol),
+                     "primal_res": res.primal_res, "dual_res": res.dual_res,
+                     "precision_switch_iter": res.precision_switch_iter,
+                     "refine_steps": res.refine_steps,
+                     "speedup_vs_fp64": rate / fp64_rate}
+    f64 = out["fp64"]["obj"]
+    for name in ("fp32_start", "bf16_start"):
+        out[name]["obj_rel_diff_vs_fp64"] = abs(out[name]["obj"] - f64) / max(1.0, abs(f64))
+    prob.close()
+    return out
+
+
 def paper_shapes_leg(solves: int):
     """Solves of the paper's own workload shapes (heat3d, Table 1 constants, deviation form
     around a uniform 400 K set point): FP64 (one untimed solve, `solves` timed ones, one with
@@ -273,7 +379,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-solves", type=int, default=1)
+    ap.add_argument("--cpu-solves", type=int, default=3)
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the timed run at the other precision")
     ap.add_argument("--batch-steps", type=int, default=0,
@@ -284,6 +390,9 @@ def main():
                     help="IPM-generated training pairs of the surrogate (0 = skip the leg)")
     ap.add_argument("--surrogate-queries", type=int, default=2048)
     ap.add_argument("--surrogate-epochs", type=int, default=200)
+    ap.add_argument("--heat2d-solves", type=int, default=1,
+                    help="timed solves per precision of the 2-D heat workload (70 x 70 grid, "
+                         "N = 100, K 2000 x 2000; 0 = skip the leg)")
     ap.add_argument("--paper-solves", type=int, default=2,
                     help="timed FP64 solves per paper 3-D cube shape (0 = skip the leg)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -345,7 +454,8 @@ def main():
         elapsed = time.perf_counter() - t0
         iters = max(1.0, acc[0])
         syrk_avg_s = acc[1] / 1e3 / iters
-        achieved = info["syrk_flops"] / syrk_avg_s / 1e12
+        # the SYRK events are recorded only in the profiled pass
+        achieved = info["syrk_flops"] / syrk_avg_s / 1e12 if syrk_avg_s > 0 else None
         return {"solves_per_s": args.steps / elapsed, "ms_per_step": elapsed * 1e3 / args.steps,
                 "iters_per_solve": acc[0] / args.steps, "ms_per_iter": elapsed * 1e3 / iters,
                 "ms_per_iter_syrk_potrf": (acc[2] + acc[3]) / iters,
@@ -415,7 +525,15 @@ def main():
             "syrk_peak_tflops": PEAK[other],
             "max_obj_rel_diff": max(rel) if rel else None,
         }
+    if not args.no_cpu_baseline:
+        def gpu_solve(k):
+            prob.set_x0(torch.from_numpy(W.heat1d_config("1d", instance=k).x0).to("cuda:0"))
+            r = prob.solve()
+            return r["iters"], r["obj"], r["primal_res"], r["dual_res"]
+        out["cpu_baseline"] = cpu_baseline(args.cpu_solves, gpu_solve)
     prob.close()
+    if args.heat2d_solves > 0:
+        out["heat2d"] = heat2d_leg(args.heat2d_solves)
     if args.paper_solves > 0:
         out["paper_shapes"] = paper_shapes_leg(args.paper_solves)
     if args.batch_steps > 0:
@@ -423,8 +541,6 @@ def main():
     if args.surrogate_train > 0:
         out["surrogate"] = surrogate_leg(args.surrogate_train, args.surrogate_queries,
                                          args.surrogate_epochs)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(base, args.cpu_solves)
     print(json.dumps(out))
 
 

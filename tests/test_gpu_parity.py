@@ -500,3 +500,41 @@ def test_heat2d_70x70_reduced_horizon(lib):
             assert rel_err(u, ref.v) <= 1e-6
     finally:
         gp.close()
+
+
+def test_heat2d_70x70_full_size(lib):
+    """The largest workload at its full size (70 x 70 grid, N = 100: K 2000 x 2000, 490,000
+    state rows), in the configuration the benchmark times.  The oracle's dense reduction does
+    not fit here, so every result is checked through properties that hold at any size and
+    that the oracle computes on the CPU one by one: the objective of the returned controls by
+    forward simulation (eqn. (dyn)) equals the reported one, the simulated states and the
+    controls keep their bounds, the FP64 KKT residuals meet the bar, and the FP32- and
+    BF16-start solves reach the FP64 solve's objective within 1e-8."""
+    p = W.heat2d(**W.CONFIG_2D, seed=(2, 0))
+    print(f"[heat2d full] ns {p.ns} nu {p.nu} N {p.N}", flush=True)
+    gp = condmpc.Problem(p)
+    gp.set_x0(p.x0)
+    objs = {}
+    try:
+        for prec in (condmpc.FP64, condmpc.FP32_SYRK, condmpc.BF16_SYRK):
+            res = gp.solve(precision=prec)
+            u, _ = gp.solution(with_x=False)
+            f_sim = oracle.sparse_objective(p, u)
+            x = oracle.simulate(p, u)
+            viol = max(float(np.max(x - np.tile(p.xu, p.N))),
+                       float(np.max(np.tile(p.xl, p.N) - x)),
+                       float(np.max(u - np.tile(p.uu, p.N))),
+                       float(np.max(np.tile(p.ul, p.N) - u)))
+            print(f"[heat2d full] prec {prec}: status {res['status']} iters {res['iters']} obj "
+                  f"{res['obj']:.12e} simulated {f_sim:.12e} violation {viol:.2e} switch "
+                  f"{res['precision_switch_iter']} refine {res['refine_steps']}", flush=True)
+            assert res["status"] == condmpc.OK
+            assert abs(res["obj"] - f_sim) <= 1e-10 * max(1.0, abs(f_sim))
+            assert viol <= 1e-9
+            assert res["primal_res"] <= 1e-8 and res["dual_res"] <= 1e-8
+            objs[prec] = res["obj"]
+    finally:
+        gp.close()
+    f64 = objs[condmpc.FP64]
+    for prec in (condmpc.FP32_SYRK, condmpc.BF16_SYRK):
+        assert abs(objs[prec] - f64) <= 1e-8 * max(1.0, abs(f64))
