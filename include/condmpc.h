@@ -114,7 +114,8 @@ typedef struct {
 /* Sizes and per-iteration work of a problem. */
 typedef struct {
   int n, mx, m;              /* as cmpc_problem_dims */
-  long long gamma_nnz;       /* stored entries of Gamma: ns nu N(N+1)/2 */
+  long long gamma_nnz;       /* structural nonzeros of Gamma: ns nu N(N+1)/2 (only the N blocks
+                              * G_m = A^m B, ns nu N entries, are stored) */
   double syrk_flops;         /* algorithmic FLOPs of one formation of K: 2 per multiply-add
                                 over the structural nonzeros, lower triangle with diagonal,
                                 sum_t ns (t nu)(t nu + 1) */
@@ -127,11 +128,13 @@ typedef struct {
 /* Default options (values above). */
 void cmpc_default_options(cmpc_options* opts);
 
-/* Build the reduced problem of Section 2: G_k = A^k B, the packed block-Toeplitz
- * Gamma (block (t, j) = A^(t-1-j) B, t = 1..N, j < t), and H = Gamma'Qbar Gamma + Rbar.
- * stream: a hipStream_t (NULL = default).  On success *out owns device memory of about
- * 8 (ns nu N(N+1)/2 + 3 (nu N)^2 + 8 ns N) bytes.  Errors: CMPC_ERR_INVALID (dimensions,
- * NULL data), CMPC_ERR_NONFINITE, CMPC_ERR_NOMEM, CMPC_ERR_HIP. */
+/* Build the reduced problem of Section 2: G_k = A^k B (k = 0..N-1) and
+ * H = Gamma'Qbar Gamma + Rbar.  Gamma itself is block Toeplitz (block (t, j) = G_{t-1-j},
+ * t = 1..N, j < t) and is never stored: every pass over it reads the blocks G_k (the paper's
+ * Section 6 proposes keeping the Jacobian implicitly this way).  stream: a hipStream_t
+ * (NULL = default).  On success *out owns device memory of about
+ * 8 (2 ns nu N + 3 (nu N)^2 + 8 ns N) bytes.  Errors: CMPC_ERR_INVALID (dimensions,
+ * NULL data, ns nu N 8 >= 4 GiB), CMPC_ERR_NONFINITE, CMPC_ERR_NOMEM, CMPC_ERR_HIP. */
 int cmpc_problem_create(const cmpc_lq_desc* desc, void* stream, cmpc_problem** out);
 
 /* Release all device memory of the problem (NULL is ignored).  Synchronises its stream. */

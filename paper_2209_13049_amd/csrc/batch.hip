@@ -153,11 +153,10 @@ static InstView view_of(const Problem& p) {
   v.gt_chunks = p.gt_chunks;
   v.nt = ceil_div(p.n, 64);
   v.syrk_nwg = p.syrk.nwg;
-  v.Gam = p.Gam;
+  v.G = p.G;
   v.Gt = p.Gt;
-  v.Gam32 = p.Gam32;
-  v.Gam16 = (const bf16_t*)p.Gam16;
-  v.goff = p.goff;
+  v.G32 = p.G32;
+  v.G16 = (const bf16_t*)p.G16;
   v.H = p.H;
   v.d = p.d;
   v.h = p.h;
@@ -370,8 +369,8 @@ static int prepare(Batch& b, int precision) {
     const int rc = ensure_plan(*p, precision, &ch);
     if (rc) return rc;
     any = any || ch;
-    if ((precision == CMPC_FP32_SYRK && p->Gam32 == nullptr) ||
-        (precision == CMPC_BF16_SYRK && (p->Gam16 == nullptr || p->Gam32 == nullptr))) {
+    if ((precision == CMPC_FP32_SYRK && p->G32 == nullptr) ||
+        (precision == CMPC_BF16_SYRK && (p->G16 == nullptr || p->G32 == nullptr))) {
       const int rc2 = launch_convert_gamma(*p, precision);
       if (rc2) return rc2;
       any = true;

@@ -79,7 +79,7 @@ void free_problem(Problem* p) {
   if (p->stream) hipStreamSynchronize(p->stream);
   else hipDeviceSynchronize();
   double** bufs[] = {&p->A,  &p->B,   &p->Q,    &p->Qf,    &p->R,    &p->xl,   &p->xu,
-                     &p->ul, &p->uu,  &p->qdiag, &p->G,    &p->Gt,   &p->Gam,  &p->H,    &p->K,
+                     &p->ul, &p->uu,  &p->qdiag, &p->G,    &p->Gt,   &p->H,    &p->K,
                      &p->x0, &p->c,   &p->qc,   &p->h,     &p->d,    &p->v,    &p->s,
                      &p->lam, &p->z,  &p->gv,   &p->pv,    &p->ps,   &p->plam, &p->pz,
                      &p->gpv, &p->rhs, &p->Dx,  &p->Du,    &p->wx,   &p->wu,   &p->gt,
@@ -89,13 +89,12 @@ void free_problem(Problem* p) {
     if (*b) hipFree(*b);
     *b = nullptr;
   }
-  if (p->goff) hipFree(p->goff);
   if (p->a_rowptr) hipFree(p->a_rowptr);
   if (p->a_col) hipFree(p->a_col);
   if (p->a_val) hipFree(p->a_val);
   if (p->red_part) hipFree(p->red_part);
-  if (p->Gam32) hipFree(p->Gam32);
-  if (p->Gam16) hipFree(p->Gam16);
+  if (p->G32) hipFree(p->G32);
+  if (p->G16) hipFree(p->G16);
   if (p->st) hipFree(p->st);
   for (hipEvent_t e : p->prof_ev) hipEventDestroy(e);
   if (p->hflags) hipHostFree(p->hflags);
@@ -276,24 +275,12 @@ int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
     return CMPC_ERR_NOMEM;
   }
   TRY(launch_transpose_g(*p));
-  // packed Gamma
-  p->off.resize(N + 1);
-  for (int t = 1; t <= N + 1; ++t) p->off[t - 1] = (long long)ns * nu * (long long)t * (t - 1) / 2;
-  if (hipMalloc(&p->Gam, sizeof(double) * (size_t)p->off[N]) != hipSuccess) {
-    set_error("out of device memory (Gamma)");
+  if ((long long)N * ns * nu * (long long)sizeof(double) >= (1LL << 32)) {
+    // the SYRK addresses G with 32-bit byte offsets
+    set_error("ns * nu * N too large (G must stay below 4 GiB)");
     free_problem(p);
-    return CMPC_ERR_NOMEM;
+    return CMPC_ERR_INVALID;
   }
-  if (hipMalloc(&p->goff, sizeof(long long) * (N + 1)) != hipSuccess) {
-    free_problem(p);
-    return CMPC_ERR_NOMEM;
-  }
-  if (hipMemcpyAsync(p->goff, p->off.data(), sizeof(long long) * (N + 1), hipMemcpyHostToDevice,
-                     stream) != hipSuccess) {
-    free_problem(p);
-    return CMPC_ERR_HIP;
-  }
-  TRY(launch_pack_gamma(*p));
   TRY(ipm_alloc_work(*p));
   if (hipMalloc(&p->H, sizeof(double) * (size_t)p->n * p->n) != hipSuccess ||
       hipMalloc(&p->K, sizeof(double) * (size_t)p->n * p->n) != hipSuccess) {
@@ -307,20 +294,24 @@ int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
   if (qd) {
     TRY(launch_syrk(*p, CMPC_FP64, p->qdiag, p->H, nullptr, p->H));
   } else {
-    double* Y = nullptr;
-    if (hipMalloc(&Y, sizeof(double) * (size_t)ns * p->n) != hipSuccess) {
+    // one row block Gamma_t of Gamma at a time: H += Gamma_t' (W Gamma_t)
+    double *Y = nullptr, *Gb = nullptr;
+    if (hipMalloc(&Y, sizeof(double) * (size_t)ns * p->n) != hipSuccess ||
+        hipMalloc(&Gb, sizeof(double) * (size_t)ns * p->n) != hipSuccess) {
+      if (Y) hipFree(Y);
       free_problem(p);
       return CMPC_ERR_NOMEM;
     }
     for (int t = 1; t <= N && rc == 0; ++t) {
       const int len = t * nu;
-      const double* Gt = p->Gam + p->off[t - 1];
       const double* W = (t == N) ? p->Qf : p->Q;
-      rc = launch_gemm_f64(stream, ns, len, ns, 1.0, W, ns, 1, Gt, len, 1, 0.0, Y, len);
-      if (!rc) rc = launch_gemm_f64(stream, len, len, ns, 1.0, Gt, 1, len, Y, len, 1, 1.0, p->H, p->n);
+      rc = launch_gamma_block(*p, t, Gb);
+      if (!rc) rc = launch_gemm_f64(stream, ns, len, ns, 1.0, W, ns, 1, Gb, len, 1, 0.0, Y, len);
+      if (!rc) rc = launch_gemm_f64(stream, len, len, ns, 1.0, Gb, 1, len, Y, len, 1, 1.0, p->H, p->n);
     }
     hipStreamSynchronize(stream);
     hipFree(Y);
+    hipFree(Gb);
     if (rc) {
       free_problem(p);
       return rc;
@@ -555,14 +546,16 @@ int cmpc_problem_info(const cmpc_problem* h, cmpc_info* info) {
   info->n = p.n;
   info->mx = p.mx;
   info->m = p.m;
-  info->gamma_nnz = p.off[p.N];
+  info->gamma_nnz = (long long)p.ns * p.nu * ((long long)p.N * (p.N + 1) / 2);
   info->syrk_flops = p.syrk.flops_structural;
   info->potrf_flops = (double)p.n * p.n * p.n / 3.0;
   info->syrk_workgroups = p.syrk.nwg;
   info->syrk_partial_slots = p.syrk.nslots;
-  double b = 8.0 * (double)p.off[p.N];
-  if (p.Gam32) b += 4.0 * (double)p.off[p.N];
-  b += 8.0 * (2.0 * p.n * p.n + 2.0 * p.N * p.ns * p.nu + 2.0 * p.ns * p.ns);
+  const double gsz = (double)p.N * p.ns * p.nu;  // G and its transpose; Gamma is not stored
+  double b = 0.0;
+  if (p.G32) b += 4.0 * gsz;
+  if (p.G16) b += 2.0 * gsz;
+  b += 8.0 * (2.0 * p.n * p.n + 2.0 * gsz + 2.0 * p.ns * p.ns);
   b += 8.0 * 4096.0 * p.syrk.nslots + 8.0 * 3.0 * kGtJ * (double)p.gt_chunks;
   b += 8.0 * (7.0 * p.m + 12.0 * p.mx + 16.0 * p.n);
   info->device_bytes = b;

@@ -47,24 +47,23 @@ int launch_gemm_f64(hipStream_t s, int M, int Nc, int Kd, double alpha, const do
   return 0;
 }
 
-// Packed Gamma: block t (1..N) holds rows (t-1) ns + i, columns a = j nu + k < t nu, with
-// entry G_{t-1-j}[i][k] = (A^(t-1-j) B)[i][k]  (eqn. (x_def) with K = 0).
-__global__ void pack_gamma_kernel(const double* __restrict__ G, const long long* __restrict__ off,
-                                  double* __restrict__ Gam, int ns, int nu) {
-  const int t = blockIdx.y + 1;
+// Row block t (1..N) of Gamma: rows (t-1) ns + i, columns a = j nu + k < t nu, entry
+// G_{t-1-j}[i][k] = (A^(t-1-j) B)[i][k] (eqn. (x_def) with K = 0), written ns x (t nu)
+// row-major.  Setup only: the general-Q Hessian takes one block at a time.
+__global__ void gamma_block_kernel(const double* __restrict__ G, double* __restrict__ out,
+                                   int t, int ns, int nu) {
   const long long len = (long long)t * nu;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)ns * len) return;
   const int i = (int)(e / len);
   const int a = (int)(e - (long long)i * len);
   const int j = a / nu, k = a - j * nu;
-  Gam[off[t - 1] + e] = G[((long long)(t - 1 - j) * ns + i) * nu + k];
+  out[e] = G[((long long)(t - 1 - j) * ns + i) * nu + k];
 }
 
-int launch_pack_gamma(Problem& p) {
-  dim3 grid(ceil_div((long long)p.ns * p.N * p.nu, 256), p.N);
-  hipLaunchKernelGGL(pack_gamma_kernel, grid, dim3(256), 0, p.stream, p.G, p.goff, p.Gam, p.ns,
-                     p.nu);
+int launch_gamma_block(Problem& p, int t, double* out) {
+  hipLaunchKernelGGL(gamma_block_kernel, dim3(ceil_div((long long)p.ns * t * p.nu, 256)),
+                     dim3(256), 0, p.stream, p.G, out, t, p.ns, p.nu);
   CMPC_LAUNCH_CHECK();
   return 0;
 }
@@ -304,9 +303,8 @@ int launch_mirror_lower(hipStream_t s, double* H, int n) {
   return 0;
 }
 
-// Dense Gamma (mx x n) from the packed blocks, structural zeros written.
-__global__ void dense_gamma_kernel(const double* __restrict__ Gam,
-                                   const long long* __restrict__ off, double* __restrict__ out,
+// Dense Gamma (mx x n) from the blocks G_m, structural zeros written.
+__global__ void dense_gamma_kernel(const double* __restrict__ G, double* __restrict__ out,
                                    int ns, int nu, int N) {
   const int n = nu * N;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -314,13 +312,13 @@ __global__ void dense_gamma_kernel(const double* __restrict__ Gam,
   const long long r = e / n;
   const int a = (int)(e - r * n);
   const int t = (int)(r / ns) + 1, i = (int)(r - (long long)(t - 1) * ns);
-  const int len = t * nu;
-  out[e] = a < len ? Gam[off[t - 1] + (long long)i * len + a] : 0.0;
+  const int j = a / nu, k = a - j * nu;
+  out[e] = a < t * nu ? G[((long long)(t - 1 - j) * ns + i) * nu + k] : 0.0;
 }
 
 int launch_dense_gamma(Problem& p, double* dense) {
   hipLaunchKernelGGL(dense_gamma_kernel, dim3(ceil_div((long long)p.mx * p.n, 256)), dim3(256), 0,
-                     p.stream, p.Gam, p.goff, dense, p.ns, p.nu, p.N);
+                     p.stream, p.G, dense, p.ns, p.nu, p.N);
   CMPC_LAUNCH_CHECK();
   return 0;
 }

@@ -3,14 +3,15 @@
 // Section 5 names this condensation as the step whose cost grows with the row count of J).
 //
 // Design (gfx950):
-//  * Gamma is stored packed by row block t (ns x t nu), so only its structural nonzeros
-//    are read; tile (I, J) of K receives row block t only if t nu > 64 I.
+//  * Gamma is never stored: it is block Toeplitz (block (t, j) = G_{t-1-j}, G_m = A^m B), so
+//    entry (row i of block t, column j nu + k) is read from G_{t-1-j}[i][k] (N x ns x nu,
+//    4 MB at K 500 x 500), which stays in the L2 / Infinity Cache while HBM is hardly
+//    touched; only structural nonzeros are read, and tile (I, J) of K receives row block t
+//    only if t nu > 64 I.
 //  * Split-K: each 64 x 64 output tile's rows (its row blocks, t descending, all ns rows
 //    of each) are cut into pieces, and the pieces packed into workgroups of equal cost
 //    under a measured time model, all workgroups resident at once (at most 512, 2 per CU).
-//    Pieces that cover the same rows of different tiles run together on one XCD, so those
-//    rows come from HBM once and are re-read from that XCD's L2 by every tile that needs
-//    them.
+//    Pieces that cover the same rows of different tiles run together on one XCD.
 //  * Each of the 4 wavefronts of a workgroup accumulates the whole tile over every 4th
 //    group of 4 rows with v_mfma_f64_16x16x4f64 (v_mfma_f32_16x16x4f32 for FP32 and for
 //    bfloat16 storage), operands loaded straight from memory in the MFMA lane layout
@@ -272,9 +273,10 @@ struct MfmaOps<bf16_t> {
 // and only the blocks on or below the diagonal are computed.
 template <typename TIn, bool DIAG, int NIB>
 __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4][4],
-                                          const TIn* __restrict__ base,
-                                          const double* __restrict__ Dt, int len, int a0, int b0,
-                                          int r0, int r1, int wave, int li, int lk) {
+                                          const TIn* __restrict__ G,
+                                          const double* __restrict__ Dt, int t, int ns, int nu,
+                                          int a0, int b0, int r0, int r1, int wave, int li,
+                                          int lk) {
   typedef MfmaOps<TIn> Ops;
   typedef typename Ops::comp_t TC;
   typedef typename Ops::scale_t TS;
@@ -283,6 +285,7 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
   // rows: FP32 launch 8.7 ms at depth 3, 6.6 at 8, 5.2 at 12; 16 spills; FP64 no better at 4, 5).
   // BF16 storage needs a few more registers for the conversions: 10 (12 spills in the batch form).
   constexpr int PF = sizeof(TIn) == 8 ? 3 : (sizeof(TIn) == 4 ? 12 : 10);
+  const int len = t * nu;
   bool va[4], vb[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -297,16 +300,24 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
   // outside the piece are zeroed where a group is consumed.  With no branch around a load
   // and no use of a value before its group is due, the compiler waits for exactly that
   // group instead of draining every load in flight.
-  // Byte offsets from the row block's base are 32-bit (a row block of Gamma is far below
-  // 4 GiB), so every load takes the uniform base in SGPRs plus one offset VGPR.
+  // Column c = j nu + k of row block t is column k of G_{t-1-j}, and row r of that block is
+  // row r of G_{t-1-j}: element ((t-1-j) ns + r) nu + k of G.  Each lane's column offset is
+  // fixed for the job and a row adds r nu elements.  Byte offsets are 32-bit (G is far below
+  // 4 GiB; the problem's creation checks it), so every load takes the uniform base in SGPRs
+  // plus one offset VGPR.
+  auto col_off = [&](int c) {
+    const int j = c / nu, k = c - j * nu;
+    return ((unsigned)(t - 1 - j) * (unsigned)ns * (unsigned)nu + (unsigned)k) *
+           (unsigned)sizeof(TIn);
+  };
   unsigned ca[4], cb[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    ca[q] = (unsigned)(va[q] ? a0 + 16 * q + li : 0) * (unsigned)sizeof(TIn);
-    cb[q] = (unsigned)(vb[q] ? b0 + 16 * q + li : 0) * (unsigned)sizeof(TIn);
+    ca[q] = va[q] ? col_off(a0 + 16 * q + li) : 0u;
+    cb[q] = vb[q] ? col_off(b0 + 16 * q + li) : 0u;
   }
-  const char* __restrict__ gb = (const char*)base;
-  const unsigned rowbytes = (unsigned)len * (unsigned)sizeof(TIn);
+  const char* __restrict__ gb = (const char*)G;
+  const unsigned rowbytes = (unsigned)nu * (unsigned)sizeof(TIn);
   auto load = [&](int step, TIn (&xa)[4], TIn (&xb)[4], TS& xd) {
     const int r = r0 + 16 * step + 4 * wave + lk;
     const int rr = r < r1 ? r : r0;
@@ -356,8 +367,7 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
 // blocks reached): accumulate, and at a job that carries a slot sum the 4 wavefronts'
 // accumulators in LDS and write the partial tile.
 template <typename TIn, bool DIAG, int NIB>
-__device__ __forceinline__ void syrk_jobs(const TIn* __restrict__ Gam,
-                                          const long long* __restrict__ off,
+__device__ __forceinline__ void syrk_jobs(const TIn* __restrict__ G,
                                           const double* __restrict__ D,
                                           const SyrkJob* __restrict__ jobs, int j0, int j1,
                                           const int2* __restrict__ tiles,
@@ -376,10 +386,8 @@ __device__ __forceinline__ void syrk_jobs(const TIn* __restrict__ Gam,
     const SyrkJob job = jobs[jj];
     const int2 tl = tiles[job.tile];
     const int a0 = tl.x * 64, b0 = tl.y * 64;
-    const int len = job.t * nu;
-    const TIn* __restrict__ base = Gam + off[job.t - 1];
     const double* __restrict__ Dt = D + (long long)(job.t - 1) * ns;
-    syrk_rows<TIn, DIAG, NIB>(acc, base, Dt, len, a0, b0, job.r0, job.r1, wave, li, lk);
+    syrk_rows<TIn, DIAG, NIB>(acc, G, Dt, job.t, ns, nu, a0, b0, job.r0, job.r1, wave, li, lk);
     if (job.slot >= 0) {
       __syncthreads();
       for (int w = 0; w < 4; ++w) {
@@ -409,7 +417,7 @@ __device__ __forceinline__ void syrk_jobs(const TIn* __restrict__ Gam,
 
 template <typename TIn>
 __device__ __forceinline__ void syrk_splitk_body(int bid, 
-    const TIn* __restrict__ Gam, const long long* __restrict__ off, const double* __restrict__ D,
+    const TIn* __restrict__ G, const double* __restrict__ D,
     const SyrkJob* __restrict__ jobs, const int* __restrict__ wg_begin,
     const int2* __restrict__ tiles, double* __restrict__ partials, int ns, int nu, int nwg,
     const int* __restrict__ done, const int* __restrict__ lowflag, int want_low) {
@@ -428,7 +436,7 @@ __device__ __forceinline__ void syrk_splitk_body(int bid,
     const int2 tl = tiles[jobs[pj].tile];
     const int nib = min(4, (jobs[pj].t * nu - 64 * tl.x + 15) >> 4);  // >= 1 (t nu > 64 I)
 #define CMPC_SYRK_JOBS(DIAG, NIB) \
-  syrk_jobs<TIn, DIAG, NIB>(Gam, off, D, jobs, pj, pe + 1, tiles, partials, ns, nu, red)
+  syrk_jobs<TIn, DIAG, NIB>(G, D, jobs, pj, pe + 1, tiles, partials, ns, nu, red)
     if (tl.x == tl.y) {
       switch (nib) {
         case 1: CMPC_SYRK_JOBS(true, 1); break;
@@ -451,11 +459,12 @@ __device__ __forceinline__ void syrk_splitk_body(int bid,
 
 template <typename TIn>
 __global__ __launch_bounds__(256, 2) void syrk_splitk_kernel(
-    const TIn* __restrict__ Gam, const long long* __restrict__ off, const double* __restrict__ D,
+    const TIn* __restrict__ G, const double* __restrict__ D,
     const SyrkJob* __restrict__ jobs, const int* __restrict__ wg_begin,
     const int2* __restrict__ tiles, double* __restrict__ partials, int ns, int nu, int nwg,
     const int* __restrict__ done, const int* __restrict__ lowflag, int want_low) {
-  syrk_splitk_body<TIn>((blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3), Gam, off, D, jobs, wg_begin, tiles, partials, ns, nu, nwg, done, lowflag, want_low);
+  syrk_splitk_body<TIn>((blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3), G, D, jobs, wg_begin,
+                        tiles, partials, ns, nu, nwg, done, lowflag, want_low);
 }
 
 // K(lower) = Hb(lower) + sum of the tile's partial slots (fixed order) + diag(Ddiag).
@@ -495,9 +504,9 @@ __global__ __launch_bounds__(256, 2) void syrk_batch_kernel(const InstView* __re
                                                             const WorkItem* __restrict__ items,
                                                             int nitems, int mixed, int want_low) {
   CMPC_ITEMS_BEGIN
-  const TIn* G = sizeof(TIn) == 8 ? (const TIn*)V.Gam
-                                   : (sizeof(TIn) == 4 ? (const TIn*)V.Gam32 : (const TIn*)V.Gam16);
-  syrk_splitk_body<TIn>(bid, G, V.goff, V.Dx, V.jobs, V.wg_begin, V.tiles, V.partials, V.ns,
+  const TIn* G = sizeof(TIn) == 8 ? (const TIn*)V.G
+                                   : (sizeof(TIn) == 4 ? (const TIn*)V.G32 : (const TIn*)V.G16);
+  syrk_splitk_body<TIn>(bid, G, V.Dx, V.jobs, V.wg_begin, V.tiles, V.partials, V.ns,
                          V.nu, V.syrk_nwg, &V.st->done, mixed ? &V.st->use_low : nullptr,
                          want_low);
   CMPC_ITEMS_END
@@ -533,25 +542,25 @@ int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hba
   // st->use_low; otherwise only the requested precision
   const int top = mixed ? mixed : (precision == CMPC_BF16_SYRK ? 2 : (precision == CMPC_FP32_SYRK ? 1 : 0));
   const int bottom = mixed ? 0 : top;
-  if ((top >= 1 && bottom <= 1 && p.Gam32 == nullptr) || (top == 2 && p.Gam16 == nullptr)) {
-    set_error("low-precision copy of Gamma not allocated");
+  if ((top >= 1 && bottom <= 1 && p.G32 == nullptr) || (top == 2 && p.G16 == nullptr)) {
+    set_error("low-precision copy of G not allocated");
     return CMPC_ERR_INVALID;
   }
   for (int lev = top; lev >= bottom; --lev) {
     hipEvent_t e0 = lev == top ? ev_start : nullptr, e1 = lev == bottom ? ev_stop : nullptr;
     if (lev == 2)
       hipExtLaunchKernelGGL(syrk_splitk_kernel<bf16_t>, dim3(sp.nwg), dim3(256), 0, p.stream, e0,
-                            e1, 0, (const bf16_t*)p.Gam16, (const long long*)p.goff, Drow,
+                            e1, 0, (const bf16_t*)p.G16, Drow,
                             (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
                             (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done, low, 2);
     else if (lev == 1)
       hipExtLaunchKernelGGL(syrk_splitk_kernel<float>, dim3(sp.nwg), dim3(256), 0, p.stream, e0,
-                            e1, 0, (const float*)p.Gam32, (const long long*)p.goff, Drow,
+                            e1, 0, (const float*)p.G32, Drow,
                             (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
                             (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done, low, 1);
     else
       hipExtLaunchKernelGGL(syrk_splitk_kernel<double>, dim3(sp.nwg), dim3(256), 0, p.stream, e0,
-                            e1, 0, (const double*)p.Gam, (const long long*)p.goff, Drow,
+                            e1, 0, (const double*)p.G, Drow,
                             (const SyrkJob*)sp.jobs, (const int*)sp.wg_begin,
                             (const int2*)sp.tiles, sp.partials, p.ns, p.nu, sp.nwg, done, low, 0);
     CMPC_LAUNCH_CHECK();
@@ -578,29 +587,29 @@ __global__ void convert_bf16_kernel(const double* __restrict__ in, bf16_t* __res
   if (i < len) out[i] = f2bf((float)in[i]);
 }
 
-// Low-precision copies of the packed Gamma for the mixed-precision SYRK (made once):
-// CMPC_FP32_SYRK makes the float copy, CMPC_BF16_SYRK both (a BF16 solve may step to FP32).
+// Low-precision copies of G for the mixed-precision SYRK (made once): CMPC_FP32_SYRK makes
+// the float copy, CMPC_BF16_SYRK both (a BF16 solve may step to FP32).
 int launch_convert_gamma(Problem& p, int precision) {
-  const long long nnz = p.off[p.N];
-  if (precision == CMPC_BF16_SYRK && p.Gam16 == nullptr) {
-    if (hipMalloc(&p.Gam16, sizeof(bf16_t) * (size_t)nnz) != hipSuccess) {
-      p.Gam16 = nullptr;
-      set_error("out of device memory (BF16 Gamma)");
+  const long long len = (long long)p.N * p.ns * p.nu;
+  if (precision == CMPC_BF16_SYRK && p.G16 == nullptr) {
+    if (hipMalloc(&p.G16, sizeof(bf16_t) * (size_t)len) != hipSuccess) {
+      p.G16 = nullptr;
+      set_error("out of device memory (BF16 copy of G)");
       return CMPC_ERR_NOMEM;
     }
-    hipLaunchKernelGGL(convert_bf16_kernel, dim3(ceil_div(nnz, 256)), dim3(256), 0, p.stream,
-                       p.Gam, (bf16_t*)p.Gam16, nnz);
+    hipLaunchKernelGGL(convert_bf16_kernel, dim3(ceil_div(len, 256)), dim3(256), 0, p.stream,
+                       p.G, (bf16_t*)p.G16, len);
     CMPC_LAUNCH_CHECK();
   }
   if (precision == CMPC_BF16_SYRK) precision = CMPC_FP32_SYRK;
-  if (precision == CMPC_FP32_SYRK && p.Gam32 == nullptr) {
-    if (hipMalloc(&p.Gam32, sizeof(float) * (size_t)nnz) != hipSuccess) {
-      p.Gam32 = nullptr;
-      set_error("out of device memory (FP32 Gamma)");
+  if (precision == CMPC_FP32_SYRK && p.G32 == nullptr) {
+    if (hipMalloc(&p.G32, sizeof(float) * (size_t)len) != hipSuccess) {
+      p.G32 = nullptr;
+      set_error("out of device memory (FP32 copy of G)");
       return CMPC_ERR_NOMEM;
     }
-    hipLaunchKernelGGL(convert_f32_kernel, dim3(ceil_div(nnz, 256)), dim3(256), 0, p.stream, p.Gam,
-                       p.Gam32, nnz);
+    hipLaunchKernelGGL(convert_f32_kernel, dim3(ceil_div(len, 256)), dim3(256), 0, p.stream, p.G,
+                       p.G32, len);
     CMPC_LAUNCH_CHECK();
   }
   return 0;

@@ -65,13 +65,12 @@ struct Problem {
   double *A = nullptr, *B = nullptr, *Q = nullptr, *Qf = nullptr, *R = nullptr;
   double *xl = nullptr, *xu = nullptr, *ul = nullptr, *uu = nullptr;
   double *qdiag = nullptr;       // diag(Qbar), length mx (diagonal weights only)
-  double *G = nullptr;           // G_k = A^k B, k = 0..N-1: N x ns x nu
+  // Gamma is never formed: it is block Toeplitz (block (t, j) = G_{t-1-j}), so every pass
+  // over it reads only the N blocks G_m.
+  double *G = nullptr;           // G_m = A^m B, m = 0..N-1: N x ns x nu (the SYRK's operand)
   double *Gt = nullptr;          // Gt[(m nu + k) ns + i] = G_m[i][k]: n x ns (Gamma products)
-  double *Gam = nullptr;         // packed Gamma: block t (t = 1..N) is ns x (t nu) row-major
-  long long* goff = nullptr;     // device copy of off (N + 1)
-  std::vector<long long> off;    // off[t - 1] = start of block t; off[N] = nnz
-  float* Gam32 = nullptr;        // FP32 copy (mixed modes)
-  unsigned short* Gam16 = nullptr;  // BF16 copy (mixed modes)
+  float* G32 = nullptr;          // FP32 copy of G (mixed modes)
+  unsigned short* G16 = nullptr; // BF16 copy of G (mixed modes)
   double *H = nullptr;           // n x n, full symmetric
   double *Wdiag = nullptr;       // inverses of the diagonal 64 x 64 factor tiles
   double *eqs = nullptr;         // equilibration scales diag(K)^-1/2 (n)
@@ -119,11 +118,10 @@ struct InstView {
   int gt_chunks;
   int nt;                        // ceil(n / 64)
   int syrk_nwg;
-  const double* Gam;
+  const double* G;
   const double* Gt;
-  const float* Gam32;
-  const bf16_t* Gam16;
-  const long long* goff;
+  const float* G32;
+  const bf16_t* G16;
   const double *H, *d, *h;
   double *K, *Wdiag, *eqs;
   double *v, *s, *lam, *z, *gv, *pv, *ps, *plam, *pz, *gpv;
@@ -242,7 +240,8 @@ int launch_b_trsv_bwd(const ListArg& L, int k, int which);
 int launch_gemm_f64(hipStream_t s, int M, int Nc, int Kd, double alpha, const double* A,
                     long long a_i, long long a_k, const double* B, long long b_k, long long b_j,
                     double beta, double* C, long long ldc);
-int launch_pack_gamma(Problem& p);
+// Row block t (1..N) of Gamma, ns x (t nu) row-major, into out (setup only).
+int launch_gamma_block(Problem& p, int t, double* out);
 int launch_transpose_g(Problem& p);
 int launch_gemv(hipStream_t s, const double* A, const double* x, double* y, int rows, int cols);
 int launch_block_diag_weight(Problem& p, const double* in, double* out);
