@@ -246,20 +246,31 @@ struct MfmaOps<float> {
   __device__ static inline int out_row(int lk, int v) { return 4 * lk + v; }
 };
 
-// BF16 storage, FP32 MFMA: the operands are widened where they are consumed and the D-scaled
-// one is rounded back to bfloat16, so each product is the exact product of two bfloat16
-// values (as in a bfloat16 MFMA) accumulated in float32; the loads, half the bytes of the
-// FP32 path, go through the same deep ring.
+// bfloat16: the real bfloat16 MFMA (v_mfma_f32_16x16x32_bf16, float32 accumulation); the
+// element type only selects the interleaved row loop below.
 template <>
 struct MfmaOps<bf16_t> {
   typedef f4 acc_t;
-  typedef float comp_t, scale_t;
-  __device__ static inline acc_t mma(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static inline comp_t scaled(bf16_t x, float d) { return bf2f(f2bf(bf2f(x) * d)); }
-  __device__ static inline comp_t plain(bf16_t x) { return bf2f(x); }
   __device__ static inline int out_row(int lk, int v) { return 4 * lk + v; }
+};
+
+// The low-precision copies of G are interleaved by rows: element (m, r, k) sits at
+// ((m RV + r / V) nu + k) V + r % V with RV = ceil(ns / V) and the rows past ns zero, so that
+// V consecutive rows of one column of Gamma are one 16-byte load.  float: V = 4, and the
+// 4 rows of a lane feed 4 steps of v_mfma_f32_16x16x4f32 (one row per step, the 4 lanes of
+// a column group contracting 4 rows per step); bfloat16: V = 8, the 8 rows feed one
+// v_mfma_f32_16x16x32_bf16 (lane group g supplies contraction elements 8 g .. 8 g + 7).
+template <typename TIn>
+struct VecRows;
+template <>
+struct VecRows<float> {
+  static constexpr int V = 4;
+  typedef f4 vec_t;
+};
+template <>
+struct VecRows<bf16_t> {
+  static constexpr int V = 8;
+  typedef s8 vec_t;
 };
 
 // Rows [r0, r1) of one row block against one tile.  Every wavefront takes every 4th group
@@ -363,6 +374,125 @@ __device__ __forceinline__ void syrk_rows(typename MfmaOps<TIn>::acc_t (&acc)[4]
   }
 }
 
+// Rows [r0, r1) of row block t against one tile, from an interleaved copy of G (see
+// VecRows): the wavefronts take every 4th group of 4 V rows (lane group lk: rows
+// R + V lk .. R + V lk + V - 1), operands loaded 16 bytes per lane straight into the MFMA
+// lane layout through a PF-deep register ring; the A operand is scaled by D per row (for
+// bfloat16 rounded back to bfloat16, so each product is one of two bfloat16 values), rows
+// >= r1 scaled by 0, columns >= t nu zero.  r0 is a multiple of 16 (the planner cuts rows in
+// groups of 16), so every lane's V rows are one chunk of the copy.
+template <typename TIn, bool DIAG, int NIB>
+__device__ __forceinline__ void syrk_rows_vec(f4 (&acc)[4][4], const TIn* __restrict__ Gv,
+                                              const double* __restrict__ Dt, int t, int ns,
+                                              int nu, int a0, int b0, int r0, int r1, int wave,
+                                              int li, int lk) {
+  constexpr int V = VecRows<TIn>::V, GR = 4 * V;
+  typedef typename VecRows<TIn>::vec_t vec_t;
+  constexpr int PF = 2;
+  const int len = t * nu;
+  const int RV = (ns + V - 1) / V;
+  bool va[4], vb[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    va[q] = a0 + 16 * q + li < len;
+    vb[q] = b0 + 16 * q + li < len;
+  }
+  // column c = j nu + k of row block t: column k of G_{t-1-j}; 32-bit byte offsets (the copy
+  // is smaller than G, which creation keeps below 4 GiB)
+  auto col_off = [&](int c) {
+    const int j = c / nu, k = c - j * nu;
+    return (((unsigned)(t - 1 - j) * (unsigned)RV * (unsigned)nu + (unsigned)k) * (unsigned)V) *
+           (unsigned)sizeof(TIn);
+  };
+  unsigned ca[4], cb[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ca[q] = va[q] ? col_off(a0 + 16 * q + li) : 0u;
+    cb[q] = vb[q] ? col_off(b0 + 16 * q + li) : 0u;
+  }
+  const char* __restrict__ gb = (const char*)Gv;
+  const unsigned chunkbytes = (unsigned)nu * (unsigned)V * (unsigned)sizeof(TIn);
+  const int nsteps = (r1 - r0 + 4 * GR - 1) / (4 * GR);
+  vec_t ra[PF][4], rb[PF][4];
+  double rd[PF][V];
+  // loads from in-bounds addresses only: a lane whose rows lie past r1 reads chunk r0 / V
+  // (its rows are scaled by 0 when consumed), D rows past ns read row ns - 1
+  auto load = [&](int step, vec_t (&xa)[4], vec_t (&xb)[4], double (&xd)[V]) {
+    const int rc = r0 + 4 * GR * step + GR * wave + V * lk;
+    const int rr = rc < r1 ? rc : r0;
+    const unsigned ro = (unsigned)(rr / V) * chunkbytes;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < NIB) xa[q] = *(const vec_t*)(gb + (ro + ca[q]));
+      if (!DIAG) xb[q] = *(const vec_t*)(gb + (ro + cb[q]));
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) xd[e] = Dt[rr + e < ns ? rr + e : ns - 1];
+  };
+#pragma unroll
+  for (int u = 0; u < PF; ++u) {
+    load(u, ra[u], rb[u], rd[u]);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  for (int step = 0; step < nsteps; step += PF) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int rc = r0 + 4 * GR * (step + u) + GR * wave + V * lk;
+      float d[V];
+#pragma unroll
+      for (int e = 0; e < V; ++e) d[e] = rc + e < r1 ? (float)rd[u][e] : 0.0f;
+      if constexpr (V == 4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float sa[4], sb[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (q < NIB) sa[q] = va[q] ? ra[u][q][e] * d[e] : 0.0f;
+            if (!DIAG) sb[q] = vb[q] ? rb[u][q][e] : 0.0f;
+            else if (q < NIB) sb[q] = vb[q] ? ra[u][q][e] : 0.0f;
+          }
+#pragma unroll
+          for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb)
+              if (!DIAG || jb <= ib)
+                acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(sa[ib], sb[jb], acc[ib][jb],
+                                                                   0, 0, 0);
+        }
+      } else {
+        s8 sa[4], sb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q < NIB) {
+            if (va[q]) {
+#pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                const __bf16 x = (__bf16)(bf2f((bf16_t)ra[u][q][e]) * d[e]);
+                sa[q][e] = __builtin_bit_cast(short, x);
+              }
+            } else {
+              sa[q] = s8{0, 0, 0, 0, 0, 0, 0, 0};
+            }
+          }
+          if (!DIAG) sb[q] = vb[q] ? rb[u][q] : s8{0, 0, 0, 0, 0, 0, 0, 0};
+          else if (q < NIB) sb[q] = vb[q] ? ra[u][q] : s8{0, 0, 0, 0, 0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int ib = 0; ib < NIB; ++ib)
+#pragma unroll
+          for (int jb = 0; jb < 4; ++jb)
+            if (!DIAG || jb <= ib)
+              acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sa[ib], sb[jb], acc[ib][jb],
+                                                                    0, 0, 0);
+      }
+      load(step + u + PF, ra[u], rb[u], rd[u]);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 // The jobs [j0, j1) of one workgroup (all on one tile, all with the same number NIB of row
 // blocks reached): accumulate, and at a job that carries a slot sum the 4 wavefronts'
 // accumulators in LDS and write the partial tile.
@@ -387,7 +517,11 @@ __device__ __forceinline__ void syrk_jobs(const TIn* __restrict__ G,
     const int2 tl = tiles[job.tile];
     const int a0 = tl.x * 64, b0 = tl.y * 64;
     const double* __restrict__ Dt = D + (long long)(job.t - 1) * ns;
-    syrk_rows<TIn, DIAG, NIB>(acc, G, Dt, job.t, ns, nu, a0, b0, job.r0, job.r1, wave, li, lk);
+    if constexpr (sizeof(TIn) == 8)
+      syrk_rows<TIn, DIAG, NIB>(acc, G, Dt, job.t, ns, nu, a0, b0, job.r0, job.r1, wave, li, lk);
+    else
+      syrk_rows_vec<TIn, DIAG, NIB>(acc, G, Dt, job.t, ns, nu, a0, b0, job.r0, job.r1, wave, li,
+                                    lk);
     if (job.slot >= 0) {
       __syncthreads();
       for (int w = 0; w < 4; ++w) {
@@ -575,41 +709,53 @@ int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hba
 
 namespace cmpc {
 
-__global__ void convert_f32_kernel(const double* __restrict__ in, float* __restrict__ out,
-                                   long long len) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < len) out[i] = (float)in[i];
-}
-
-__global__ void convert_bf16_kernel(const double* __restrict__ in, bf16_t* __restrict__ out,
-                                    long long len) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < len) out[i] = f2bf((float)in[i]);
+// The interleaved low-precision copy of G (see VecRows): out element
+// ((m RV + rv) nu + k) V + e = G[(m ns + V rv + e) nu + k], zero for rows V rv + e >= ns.
+template <typename TOut, int V>
+__global__ void convert_interleaved_kernel(const double* __restrict__ G, TOut* __restrict__ out,
+                                           int ns, int nu, int N) {
+  const int RV = (ns + V - 1) / V;
+  const long long len = (long long)N * RV * nu * V;
+  const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= len) return;
+  const int e = (int)(o % V);
+  long long q = o / V;
+  const int k = (int)(q % nu);
+  q /= nu;
+  const int rv = (int)(q % RV);
+  const int m = (int)(q / RV);
+  const int r = V * rv + e;
+  const double x = r < ns ? G[((long long)m * ns + r) * nu + k] : 0.0;
+  if constexpr (sizeof(TOut) == 4)
+    out[o] = (TOut)x;
+  else
+    out[o] = f2bf((float)x);
 }
 
 // Low-precision copies of G for the mixed-precision SYRK (made once): CMPC_FP32_SYRK makes
 // the float copy, CMPC_BF16_SYRK both (a BF16 solve may step to FP32).
 int launch_convert_gamma(Problem& p, int precision) {
-  const long long len = (long long)p.N * p.ns * p.nu;
   if (precision == CMPC_BF16_SYRK && p.G16 == nullptr) {
+    const long long len = (long long)p.N * ceil_div(p.ns, 8) * p.nu * 8;
     if (hipMalloc(&p.G16, sizeof(bf16_t) * (size_t)len) != hipSuccess) {
       p.G16 = nullptr;
       set_error("out of device memory (BF16 copy of G)");
       return CMPC_ERR_NOMEM;
     }
-    hipLaunchKernelGGL(convert_bf16_kernel, dim3(ceil_div(len, 256)), dim3(256), 0, p.stream,
-                       p.G, (bf16_t*)p.G16, len);
+    hipLaunchKernelGGL((convert_interleaved_kernel<bf16_t, 8>), dim3(ceil_div(len, 256)),
+                       dim3(256), 0, p.stream, p.G, (bf16_t*)p.G16, p.ns, p.nu, p.N);
     CMPC_LAUNCH_CHECK();
   }
   if (precision == CMPC_BF16_SYRK) precision = CMPC_FP32_SYRK;
   if (precision == CMPC_FP32_SYRK && p.G32 == nullptr) {
+    const long long len = (long long)p.N * ceil_div(p.ns, 4) * p.nu * 4;
     if (hipMalloc(&p.G32, sizeof(float) * (size_t)len) != hipSuccess) {
       p.G32 = nullptr;
       set_error("out of device memory (FP32 copy of G)");
       return CMPC_ERR_NOMEM;
     }
-    hipLaunchKernelGGL(convert_f32_kernel, dim3(ceil_div(len, 256)), dim3(256), 0, p.stream, p.G,
-                       p.G32, len);
+    hipLaunchKernelGGL((convert_interleaved_kernel<float, 4>), dim3(ceil_div(len, 256)),
+                       dim3(256), 0, p.stream, p.G, p.G32, p.ns, p.nu, p.N);
     CMPC_LAUNCH_CHECK();
   }
   return 0;
