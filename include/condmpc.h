@@ -92,6 +92,7 @@ typedef struct {
                              iteration, step lengths, SYRK precision level) and once at the
                              end; the line is valid during the call only (default NULL) */
   void* log_ctx;     /* passed to log unchanged */
+  double warm_mu;    /* cmpc_solve_warm: barrier parameter of the warm start (default 1e-3) */
 } cmpc_options;
 
 typedef struct {
@@ -156,6 +157,17 @@ int cmpc_set_x0(cmpc_problem* p, const double* x0, int on_device);
 /* Run Algorithm 1 from the start point above.  opts NULL = defaults.  res may be NULL.
  * Returns the solver status (also in res->status). */
 int cmpc_solve(cmpc_problem* p, const cmpc_options* opts, cmpc_result* res);
+
+/* Algorithm 1 from a warm start, for receding-horizon control (Section 1: the controller
+ * solves the problem again from each new measured state and applies the first input).  The
+ * start controls are v0 (length nu N, host or device by on_device) or, with v0 = NULL, this
+ * problem's last solution shifted one stage earlier with its last stage repeated (call
+ * cmpc_set_x0 with the new state first); then s = max(d - J v0, 1e-2), lambda = z =
+ * warm_mu / s and the barrier parameter starts at opts->warm_mu.  Everything else is
+ * cmpc_solve.  Errors: CMPC_ERR_INVALID (no x0, or v0 = NULL before any solve, warm_mu not
+ * positive), CMPC_ERR_NONFINITE (host v0). */
+int cmpc_solve_warm(cmpc_problem* p, const cmpc_options* opts, const double* v0, int on_device,
+                    cmpc_result* res);
 
 /* Copy out the last solve's controls u = v (length nu N) and, if x != NULL, the states
  * x_1..x_N = c + Gamma v (length ns N).  Host or device pointers by on_device. */

@@ -23,7 +23,7 @@ MLP_BF16, MLP_FP32 = 0, 1
 # every function declared in include/condmpc.h
 EXPORTS = [
     "cmpc_default_options", "cmpc_problem_create", "cmpc_problem_destroy", "cmpc_problem_dims",
-    "cmpc_problem_info", "cmpc_set_x0", "cmpc_solve", "cmpc_get_solution", "cmpc_get_iterate", "cmpc_export_dense",
+    "cmpc_problem_info", "cmpc_set_x0", "cmpc_solve", "cmpc_solve_warm", "cmpc_get_solution", "cmpc_get_iterate", "cmpc_export_dense",
     "cmpc_form_condensed", "cmpc_newton_step", "cmpc_potrf", "cmpc_potrf_noalloc", "cmpc_potrs", "cmpc_batch_create",
     "cmpc_batch_destroy", "cmpc_batch_size", "cmpc_batch_instance", "cmpc_batch_solve",
     "cmpc_batch_tune", "cmpc_tune_lookup", "cmpc_tune_store", "cmpc_tune_clear", "cmpc_default_train_opts",
@@ -50,7 +50,7 @@ class Options(ctypes.Structure):
                 ("mu_switch", ctypes.c_double), ("check_every", ctypes.c_int),
                 ("profile", ctypes.c_int), ("equilibrate", ctypes.c_int),
                 ("refine_contract", ctypes.c_double), ("log", LOG_FN),
-                ("log_ctx", ctypes.c_void_p)]
+                ("log_ctx", ctypes.c_void_p), ("warm_mu", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
@@ -124,6 +124,7 @@ def load(path: str = LIB_PATH):
         "cmpc_problem_info": (i, [vp, ctypes.POINTER(Info)]),
         "cmpc_set_x0": (i, [vp, vp, i]),
         "cmpc_solve": (i, [vp, ctypes.POINTER(Options), ctypes.POINTER(Result)]),
+        "cmpc_solve_warm": (i, [vp, ctypes.POINTER(Options), vp, i, ctypes.POINTER(Result)]),
         "cmpc_get_solution": (i, [vp, vp, vp, i]),
         "cmpc_get_iterate": (i, [vp, vp, vp, vp, vp, i]),
         "cmpc_export_dense": (i, [vp, vp, vp, vp, vp, vp, vp]),
@@ -272,6 +273,23 @@ class Problem:
 
     def solve_raw(self, options: Options, result: Result) -> int:
         return load().cmpc_solve(self._h, ctypes.byref(options), ctypes.byref(result))
+
+    def solve_warm(self, v0=None, **opts) -> dict:
+        """cmpc_solve_warm: Algorithm 1 from the controls v0 (numpy array or float64 CUDA
+        tensor), or with v0 None from the last solution shifted one stage (receding horizon)."""
+        import torch
+        o = default_options(**opts)
+        r = Result()
+        if v0 is None:
+            rc = load().cmpc_solve_warm(self._h, ctypes.byref(o), None, 0, ctypes.byref(r))
+        elif isinstance(v0, torch.Tensor):
+            rc = load().cmpc_solve_warm(self._h, ctypes.byref(o), _dev(v0), 1, ctypes.byref(r))
+        else:
+            v = _f64(v0)
+            rc = load().cmpc_solve_warm(self._h, ctypes.byref(o), v.ctypes.data_as(ctypes.c_void_p),
+                                        0, ctypes.byref(r))
+        _check(rc, allow_positive=True)
+        return r.as_dict()
 
     def solution(self, with_x=True):
         u = np.empty(self.n)

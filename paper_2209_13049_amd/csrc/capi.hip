@@ -365,7 +365,7 @@ int set_x0(Problem& p, const double* x0, int on_device) {
   return 0;
 }
 
-int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
+int solve(Problem& p, const cmpc_options& o, cmpc_result* res, int warm) {
   if (!p.have_x0) {
     set_error("cmpc_set_x0 must be called before cmpc_solve");
     return CMPC_ERR_INVALID;
@@ -397,7 +397,7 @@ int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
     }
   }
   CMPC_HIP(hipEventRecord(p.ev0, p.stream));
-  if (launch_ipm_init(p, o)) return CMPC_ERR_HIP;
+  if (launch_ipm_init(p, o, warm, o.warm_mu)) return CMPC_ERR_HIP;
   // Convergence is read back without stalling the queue: the last kernel of iteration it
   // stores 1 (running) or 2 (done) into slot it % R of a mapped pinned ring; before queueing
   // iteration it + depth the host polls slot it only.
@@ -496,6 +496,7 @@ int solve(Problem& p, const cmpc_options& o, cmpc_result* res) {
       ms_potrf += c;
     }
   const int status = hs.done ? hs.status : CMPC_MAX_ITER;
+  p.have_solution = status >= 0;
   if (res) {
     res->status = status;
     res->iters = hs.iter;
@@ -532,6 +533,7 @@ void cmpc_default_options(cmpc_options* o) {
   o->refine_contract = 0.1;
   o->log = nullptr;
   o->log_ctx = nullptr;
+  o->warm_mu = 1e-3;
   o->check_every = 2;
   o->profile = 0;
   o->equilibrate = -1;
@@ -600,24 +602,68 @@ int cmpc_set_x0(cmpc_problem* h, const double* x0, int on_device) {
   return set_x0(*h->p, x0, on_device);
 }
 
+static int solve_options(const cmpc_options* opts, cmpc_options* o) {
+  cmpc_default_options(o);
+  if (opts) *o = *opts;
+  if (o->precision != CMPC_FP64 && o->precision != CMPC_FP32_SYRK &&
+      o->precision != CMPC_BF16_SYRK) {
+    set_error("unsupported precision mode");
+    return CMPC_ERR_INVALID;
+  }
+  if (o->max_refine < 0 || o->max_refine > 20) {
+    set_error("max_refine must lie in [0, 20]");
+    return CMPC_ERR_INVALID;
+  }
+  return 0;
+}
+
 int cmpc_solve(cmpc_problem* h, const cmpc_options* opts, cmpc_result* res) {
   if (!h) {
     set_error("NULL problem");
     return CMPC_ERR_INVALID;
   }
   cmpc_options o;
-  cmpc_default_options(&o);
-  if (opts) o = *opts;
-  if (o.precision != CMPC_FP64 && o.precision != CMPC_FP32_SYRK &&
-      o.precision != CMPC_BF16_SYRK) {
-    set_error("unsupported precision mode");
-    return CMPC_ERR_INVALID;
-  }
-  if (o.max_refine < 0 || o.max_refine > 20) {
-    set_error("max_refine must lie in [0, 20]");
-    return CMPC_ERR_INVALID;
-  }
+  const int rc = solve_options(opts, &o);
+  if (rc) return rc;
   return solve(*h->p, o, res);
+}
+
+int cmpc_solve_warm(cmpc_problem* h, const cmpc_options* opts, const double* v0, int on_device,
+                    cmpc_result* res) {
+  if (!h) {
+    set_error("NULL problem");
+    return CMPC_ERR_INVALID;
+  }
+  cmpc_options o;
+  int rc = solve_options(opts, &o);
+  if (rc) return rc;
+  if (!(o.warm_mu > 0) || !std::isfinite(o.warm_mu)) {
+    set_error("warm_mu must be positive and finite");
+    return CMPC_ERR_INVALID;
+  }
+  Problem& p = *h->p;
+  if (!p.have_x0) {
+    set_error("cmpc_set_x0 must be called before cmpc_solve_warm");
+    return CMPC_ERR_INVALID;
+  }
+  if (v0 == nullptr) {
+    if (!p.have_solution) {
+      set_error("cmpc_solve_warm with v0 = NULL needs an earlier solve of this problem");
+      return CMPC_ERR_INVALID;
+    }
+    rc = launch_shift_controls(p);
+  } else if (on_device) {
+    CMPC_HIP(hipMemcpyAsync(p.v, v0, sizeof(double) * p.n, hipMemcpyDeviceToDevice, p.stream));
+  } else {
+    if (!all_finite(v0, (size_t)p.n)) {
+      set_error("non-finite entry in v0");
+      return CMPC_ERR_NONFINITE;
+    }
+    CMPC_HIP(hipMemcpyAsync(p.v, v0, sizeof(double) * p.n, hipMemcpyHostToDevice, p.stream));
+    CMPC_HIP(hipStreamSynchronize(p.stream));  // v0 is host memory the caller may reuse
+  }
+  if (rc) return rc;
+  return solve(p, o, res, 1);
 }
 
 int cmpc_get_solution(const cmpc_problem* h, double* u, double* x, int on_device) {

@@ -313,11 +313,15 @@ static int launch_hv(Problem& p, const double* x, double* y, const int* done) {
 }
 
 // ---------------------------------------------------------------- start point
+// Start point.  Cold (warm = 0): v = 0, s = max(d, 1e-2), lambda = z = mu0 / s with
+// mu0 = 0.1.  Warm (warm = 1, the receding-horizon start): v and gv = Gamma v are given, so
+// s = max(d - J v, 1e-2) with J v = [Gamma v; -Gamma v; v; -v], and lambda = z = mu0 / s.
 __device__ __forceinline__ void ipm_init_body(int bid, const double* __restrict__ d, double* __restrict__ s,
                                 double* __restrict__ lam, double* __restrict__ z,
                                 double* __restrict__ v, double* __restrict__ gv, int m, int n,
                                 int mx, IpmState* st, double tol, int max_iter, int low,
-                                double mu_switch, double contract) {
+                                double mu_switch, double contract, int warm = 0,
+                                double mu0 = kMuInit) {
   const long long i = (long long)bid * blockDim.x + threadIdx.x;
   if (i < m) {
     const double di = d[i];
@@ -326,18 +330,27 @@ __device__ __forceinline__ void ipm_init_body(int bid, const double* __restrict_
       lam[i] = 0.0;
       z[i] = 0.0;
     } else {
-      const double si = fmax(di, kSInitMin);  // v = 0, so d - J v = d
+      double jv = 0.0;
+      if (warm) {
+        if (i < mx) jv = gv[i];
+        else if (i < 2LL * mx) jv = -gv[i - mx];
+        else if (i < 2LL * mx + n) jv = v[i - 2LL * mx];
+        else jv = -v[i - 2LL * mx - n];
+      }
+      const double si = fmax(di - jv, kSInitMin);
       s[i] = si;
-      lam[i] = kMuInit / si;
-      z[i] = kMuInit / si;
+      lam[i] = mu0 / si;
+      z[i] = mu0 / si;
     }
   }
-  if (i < n) v[i] = 0.0;
-  if (i < mx) gv[i] = 0.0;
+  if (!warm) {
+    if (i < n) v[i] = 0.0;
+    if (i < mx) gv[i] = 0.0;
+  }
   if (i == 0) {
     const int xf = st->x0_flag;
-    st->mu = kMuInit;
-    st->tau = fmax(kTauMin, 1.0 - kMuInit);
+    st->mu = mu0;
+    st->tau = fmax(kTauMin, 1.0 - mu0);
     st->alpha = st->alpha_z = 0.0;
     st->tol = tol;
     st->mu_min = tol / 10.0;
@@ -362,18 +375,37 @@ __global__ void ipm_init_kernel(const double* __restrict__ d, double* __restrict
                                 double* __restrict__ lam, double* __restrict__ z,
                                 double* __restrict__ v, double* __restrict__ gv, int m, int n,
                                 int mx, IpmState* st, double tol, int max_iter, int low,
-                                double mu_switch, double contract) {
+                                double mu_switch, double contract, int warm, double mu0) {
   ipm_init_body(blockIdx.x, d, s, lam, z, v, gv, m, n, mx, st, tol, max_iter, low, mu_switch,
-                contract);
+                contract, warm, mu0);
 }
 
-int launch_ipm_init(Problem& p, const cmpc_options& o) {
+int launch_ipm_init(Problem& p, const cmpc_options& o, int warm, double mu0) {
   const long long len = p.m;
   const int low = o.precision == CMPC_BF16_SYRK ? 2 : (o.precision == CMPC_FP32_SYRK ? 1 : 0);
+  if (warm && launch_gamma_mv(p, p.v, p.gv, nullptr)) return CMPC_ERR_HIP;
   hipLaunchKernelGGL(ipm_init_kernel, dim3(ceil_div(len, 256)), dim3(256), 0, p.stream, p.d, p.s,
                      p.lam, p.z, p.v, p.gv, p.m, p.n, p.mx, p.st, o.tol, o.max_iter, low,
-                     o.mu_switch, o.refine_contract);
+                     o.mu_switch, o.refine_contract, warm, warm ? mu0 : kMuInit);
   CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// Receding-horizon shift of the controls (reading of Section 1): stage t of the result is
+// stage t + 1 of v (t = 0..N-2), the last stage repeats stage N-1.  out must not alias v.
+__global__ void shift_controls_kernel(const double* __restrict__ v, double* __restrict__ out,
+                                      int nu, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int src = i + nu < n ? i + nu : i;  // the last stage (i >= n - nu) keeps its value
+  out[i] = v[src];
+}
+
+int launch_shift_controls(Problem& p) {
+  hipLaunchKernelGGL(shift_controls_kernel, dim3(ceil_div(p.n, 256)), dim3(256), 0, p.stream,
+                     p.v, p.tmpn, p.nu, p.n);
+  CMPC_LAUNCH_CHECK();
+  CMPC_HIP(hipMemcpyAsync(p.v, p.tmpn, sizeof(double) * p.n, hipMemcpyDeviceToDevice, p.stream));
   return 0;
 }
 

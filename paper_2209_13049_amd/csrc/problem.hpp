@@ -80,6 +80,7 @@ struct Problem {
   double *red_part = nullptr;    // 1024 partial sums
   double *x0 = nullptr, *c = nullptr, *qc = nullptr, *h = nullptr, *d = nullptr;
   bool have_x0 = false;
+  bool have_solution = false;     // p.v holds the controls of a finished solve
   // iterate
   double *v = nullptr, *s = nullptr, *lam = nullptr, *z = nullptr, *gv = nullptr;
   // step and work vectors
@@ -105,7 +106,7 @@ struct Problem {
 int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out);
 void free_problem(Problem* p);
 int set_x0(Problem& p, const double* x0, int on_device);
-int solve(Problem& p, const cmpc_options& o, cmpc_result* res);
+int solve(Problem& p, const cmpc_options& o, cmpc_result* res, int warm = 0);
 // Rebuild the SYRK plan if the tuning table holds another work quantum for
 // (n, mx, precision); *changed tells whether it did.
 int ensure_plan(Problem& p, int precision, bool* changed);
@@ -302,7 +303,11 @@ int launch_tri_inv(hipStream_t s, const double* L, int n, int ld, double* Wall);
 int ipm_alloc_work(Problem& p);
 int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int* done);
 int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done);
-int launch_ipm_init(Problem& p, const cmpc_options& o);
+// warm = 0: the cold start; warm = 1: start from the controls already in p.v with barrier
+// parameter mu0 (Gamma v is formed first).
+int launch_ipm_init(Problem& p, const cmpc_options& o, int warm = 0, double mu0 = 0.0);
+// p.v <- p.v shifted one stage earlier, the last stage repeated (receding horizon).
+int launch_shift_controls(Problem& p);
 int launch_prep(Problem& p);
 int launch_mu_rhs(Problem& p);
 int launch_step(Problem& p, int refine);  // refine: refinement steps queued (mixed modes)
