@@ -268,6 +268,14 @@ cmpc_problem* cmpc_batch_instance(cmpc_batch* b, int i);
  * all converged, else a negative error of some instance or its positive outcome. */
 int cmpc_batch_solve(cmpc_batch* b, const cmpc_options* opts, cmpc_result* results);
 
+/* cmpc_batch_solve from warm starts (cmpc_solve_warm for every instance): instance i starts
+ * from the controls v0s[i] (nu_i N_i doubles, host or device by on_device) or, where v0s or
+ * v0s[i] is NULL, from its last solution shifted one stage; the barrier parameter starts at
+ * opts->warm_mu.  Errors: CMPC_ERR_INVALID (a shift without an earlier solve, warm_mu not
+ * positive). */
+int cmpc_batch_solve_warm(cmpc_batch* b, const cmpc_options* opts, const double* const* v0s,
+                          int on_device, cmpc_result* results);
+
 /* Autotuner: time the batched formation of K at the start point of the method for each
  * candidate SYRK work quantum (3000 ... 96000) and grid policy, keep the fastest for this
  * batch and record it in the process-wide tuning table under (n, mx, precision) of every
@@ -360,6 +368,15 @@ int cmpc_judge(cmpc_mlp* m, const double* x0s, const double* u, int count, int* 
  * solve of Algorithm 1 from that x0 (on the network's problem, whose x0 is overwritten).
  * u: device (count x nu N); accepted: host (may be NULL); rep may be NULL.  Returns 0, or
  * CMPC_MAX_ITER if a fallback solve did not converge. */
+/* How cmpc_surrogate_solve replaces rejected answers.  batch NULL (the default): one FP64
+ * solve after another on the network's problem.  Otherwise the rejected queries are solved
+ * together, count(batch) at a time, by cmpc_batch_solve on that batch, whose instances must
+ * all be copies of the network's problem (same ns, nu, N; their x0 are overwritten; the
+ * batch must outlive its use here).  warm != 0: each fallback solve starts from the
+ * network's clipped answer (cmpc_solve_warm) instead of the cold start.
+ * Errors: CMPC_ERR_INVALID (dimensions differ). */
+int cmpc_mlp_set_fallback(cmpc_mlp* m, cmpc_batch* batch, int warm);
+
 int cmpc_surrogate_solve(cmpc_mlp* m, const double* x0s, int count, double* u, int* accepted,
                          cmpc_surrogate_report* rep);
 

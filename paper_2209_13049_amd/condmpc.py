@@ -26,6 +26,7 @@ EXPORTS = [
     "cmpc_problem_info", "cmpc_set_x0", "cmpc_solve", "cmpc_solve_warm", "cmpc_get_solution", "cmpc_get_iterate", "cmpc_export_dense",
     "cmpc_form_condensed", "cmpc_newton_step", "cmpc_potrf", "cmpc_potrf_noalloc", "cmpc_potrs", "cmpc_batch_create",
     "cmpc_batch_destroy", "cmpc_batch_size", "cmpc_batch_instance", "cmpc_batch_solve",
+    "cmpc_batch_solve_warm", "cmpc_mlp_set_fallback",
     "cmpc_batch_tune", "cmpc_tune_lookup", "cmpc_tune_store", "cmpc_tune_clear", "cmpc_default_train_opts",
     "cmpc_mlp_create", "cmpc_mlp_destroy", "cmpc_mlp_param_count", "cmpc_mlp_get_params",
     "cmpc_mlp_set_params", "cmpc_mlp_gradients", "cmpc_mlp_train", "cmpc_mlp_predict",
@@ -140,6 +141,9 @@ def load(path: str = LIB_PATH):
         "cmpc_batch_size": (i, [vp]),
         "cmpc_batch_instance": (vp, [vp, i]),
         "cmpc_batch_solve": (i, [vp, ctypes.POINTER(Options), ctypes.POINTER(Result)]),
+        "cmpc_batch_solve_warm": (i, [vp, ctypes.POINTER(Options), ctypes.POINTER(vp), i,
+                                      ctypes.POINTER(Result)]),
+        "cmpc_mlp_set_fallback": (i, [vp, vp, i]),
         "cmpc_batch_tune": (i, [vp, i, ctypes.POINTER(TuneReport)]),
         "cmpc_tune_lookup": (i, [i, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
         "cmpc_tune_store": (i, [i, i, i, i, i]),
@@ -391,6 +395,20 @@ class Batch:
     def solve_raw(self, options: Options, results) -> int:
         return load().cmpc_batch_solve(self._h, ctypes.byref(options), results)
 
+    def solve_warm(self, v0s=None, **opts):
+        """cmpc_batch_solve_warm: instance i starts from v0s[i] (float64 CUDA tensor, or None
+        for its last solution shifted one stage); v0s None shifts every instance."""
+        o = default_options(**opts)
+        res = (Result * self.count)()
+        if v0s is None:
+            rc = load().cmpc_batch_solve_warm(self._h, ctypes.byref(o), None, 1, res)
+        else:
+            ptrs = (ctypes.c_void_p * self.count)(*[None if v is None else _dev(v) for v in v0s])
+            rc = load().cmpc_batch_solve_warm(self._h, ctypes.byref(o), ptrs, 1, res)
+        if rc < 0 and not any(r.status < 0 for r in res):
+            _check(rc)
+        return rc, [r.as_dict() for r in res]
+
     def tune(self, precision=FP64) -> dict:
         rep = TuneReport()
         _check(load().cmpc_batch_tune(self._h, precision, ctypes.byref(rep)))
@@ -496,6 +514,13 @@ class Mlp:
         _check(load().cmpc_judge(self._h, _dev(x0s), _dev(u), count, _hp(acc), _hp(vio), _hp(f),
                                  _hp(lb)))
         return acc.astype(bool), vio, f, lb
+
+    def set_fallback(self, batch=None, warm=False):
+        """Rejected answers are re-solved on `batch` (a Batch of copies of the network's
+        problem, kept alive by this object) or one by one (None); warm: from the answer."""
+        self._fallback = batch
+        _check(load().cmpc_mlp_set_fallback(self._h, batch._h if batch is not None else None,
+                                            1 if warm else 0))
 
     def solve(self, x0s):
         """(u device tensor, accepted bool array, report dict) for a batch of queries."""

@@ -393,11 +393,38 @@ static int prepare(Batch& b, int precision) {
   return 0;
 }
 
-static int batch_solve(Batch& b, const cmpc_options& o, cmpc_result* res) {
+// warm: start each instance from controls (v0s[i], or with v0s / v0s[i] NULL its last
+// solution shifted one stage) instead of the cold start.
+static int batch_solve(Batch& b, const cmpc_options& o, cmpc_result* res, int warm = 0,
+                       const double* const* v0s = nullptr, int on_device = 0) {
   int rc = check_options(o);
   if (rc) return rc;
+  if (warm && (!(o.warm_mu > 0) || !std::isfinite(o.warm_mu))) {
+    set_error("warm_mu must be positive and finite");
+    return CMPC_ERR_INVALID;
+  }
   rc = prepare(b, o.precision);
   if (rc) return rc;
+  if (warm) {
+    for (int i = 0; i < b.count; ++i) {
+      Problem& p = *b.inst[i];
+      const double* v0 = v0s ? v0s[i] : nullptr;
+      if (v0 == nullptr) {
+        if (!p.have_solution) {
+          set_error("instance " + std::to_string(i) + ": a warm start from the last solution "
+                    "needs an earlier solve");
+          return CMPC_ERR_INVALID;
+        }
+        rc = launch_shift_controls(p);
+        if (rc) return rc;
+      } else {
+        CMPC_HIP(hipMemcpyAsync(p.v, v0, sizeof(double) * p.n,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                p.stream));
+      }
+    }
+    CMPC_HIP(hipStreamSynchronize(b.user));
+  }
   const int mixed = o.precision == CMPC_BF16_SYRK ? 2 : (o.precision == CMPC_FP32_SYRK ? 1 : 0);
   const int refine = mixed ? o.max_refine : 0;
   const int eq = o.equilibrate < 0 ? (mixed > 0) : (o.equilibrate != 0);
@@ -406,8 +433,9 @@ static int batch_solve(Batch& b, const cmpc_options& o, cmpc_result* res) {
     if (rc) return rc;
   }
   CMPC_HIP(hipEventRecord(b.ev0, b.stream));
+  if (warm && launch_b_gamma_mv(arg(b, b.gmv), 2)) return CMPC_ERR_HIP;  // gv = Gamma v0
   if (launch_b_init(arg(b, b.init), o.tol, o.max_iter, mixed, o.mu_switch,
-                    o.refine_contract)) return CMPC_ERR_HIP;
+                    o.refine_contract, warm, o.warm_mu)) return CMPC_ERR_HIP;
   if (launch_b_prep(arg(b, b.blk))) return CMPC_ERR_HIP;  // later ones run in the update
   if (launch_b_reset(b.stream, b.d_iter)) return CMPC_ERR_HIP;
   // The publish kernel of iteration it stores (running instances + 1) into ring slot
@@ -458,6 +486,7 @@ static int batch_solve(Batch& b, const cmpc_options& o, cmpc_result* res) {
   for (int i = 0; i < b.count; ++i) {
     const IpmState& s = hs[i];
     const int status = s.done ? s.status : CMPC_MAX_ITER;
+    b.inst[i]->have_solution = status >= 0;
     if (status != CMPC_OK && (worst == CMPC_OK || status < 0)) worst = status;
     if (res) {
       cmpc_result& r = res[i];
@@ -640,6 +669,18 @@ int cmpc_batch_solve(cmpc_batch* h, const cmpc_options* opts, cmpc_result* resul
   cmpc_default_options(&o);
   if (opts) o = *opts;
   return batch_solve(*h->b, o, results);
+}
+
+int cmpc_batch_solve_warm(cmpc_batch* h, const cmpc_options* opts, const double* const* v0s,
+                          int on_device, cmpc_result* results) {
+  if (!h) {
+    set_error("NULL batch");
+    return CMPC_ERR_INVALID;
+  }
+  cmpc_options o;
+  cmpc_default_options(&o);
+  if (opts) o = *opts;
+  return batch_solve(*h->b, o, results, 1, v0s, on_device);
 }
 
 int cmpc_batch_tune(cmpc_batch* h, int precision, cmpc_tune_report* rep) {

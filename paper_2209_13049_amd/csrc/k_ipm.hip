@@ -1049,10 +1049,11 @@ __global__ __launch_bounds__(256) void ipm_init_batch_kernel(const InstView* __r
                                                              const WorkItem* __restrict__ items,
                                                              int nitems, double tol, int max_iter,
                                                              int low, double mu_switch,
-                                                             double contract) {
+                                                             double contract, int warm,
+                                                             double mu0) {
   CMPC_ITEMS_BEGIN
   ipm_init_body(bid, V.d, V.s, V.lam, V.z, V.v, V.gv, V.m, V.n, V.mx, V.st, tol, max_iter, low,
-                mu_switch, contract);
+                mu_switch, contract, warm, mu0);
   CMPC_ITEMS_END
 }
 
@@ -1103,12 +1104,16 @@ __global__ __launch_bounds__(256) void mu_rhs_batch_kernel(const InstView* __res
   CMPC_ITEMS_END
 }
 
-// gpv = Gamma pv (gate 0: the step; gate 1: the refinement product)
+// gpv = Gamma pv (gate 0: the step; gate 1: the refinement product); gate 2: gv = Gamma v
+// for every instance (the warm start, before the start point is formed)
 __global__ __launch_bounds__(256) void gamma_mv_batch_kernel(const InstView* __restrict__ views,
                                                              const WorkItem* __restrict__ items,
                                                              int nitems, int gate) {
   CMPC_ITEMS_BEGIN
-  gamma_mv_body(bid, V.Gt, V.pv, V.gpv, V.ns, V.nu, V.N, gate_of(V, gate));
+  if (gate == 2)
+    gamma_mv_body(bid, V.Gt, V.v, V.gv, V.ns, V.nu, V.N, nullptr);
+  else
+    gamma_mv_body(bid, V.Gt, V.pv, V.gpv, V.ns, V.nu, V.N, gate_of(V, gate));
   CMPC_ITEMS_END
 }
 
@@ -1195,8 +1200,9 @@ __global__ void gather_state_kernel(const InstView* __restrict__ views, int coun
 }
 
 int launch_b_init(const ListArg& L, double tol, int max_iter, int low, double mu_switch,
-                  double contract) {
-  CMPC_LAUNCH_LIST(ipm_init_batch_kernel, L, tol, max_iter, low, mu_switch, contract);
+                  double contract, int warm, double mu0) {
+  CMPC_LAUNCH_LIST(ipm_init_batch_kernel, L, tol, max_iter, low, mu_switch, contract, warm,
+                   warm ? mu0 : kMuInit);
 }
 int launch_b_prep(const ListArg& L) { CMPC_LAUNCH_LIST(prep_batch_kernel, L); }
 int launch_b_gamma_t_partial(const ListArg& L, int nv) {

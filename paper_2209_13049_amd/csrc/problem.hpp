@@ -209,12 +209,14 @@ inline int grid_for(const ListArg& L, const void* kernel) {
 // ---- work-list launchers (k_ipm.hip, k_syrk.hip, k_chol.hip); a list of length 0 launches
 // nothing.  gate / which: 0 = the solve, 1 = the refinement (see gate_of).
 int launch_b_init(const ListArg& L, double tol, int max_iter, int low, double mu_switch,
-                  double contract);
+                  double contract, int warm = 0, double mu0 = 0.0);
 int launch_b_prep(const ListArg& L);
 int launch_b_gamma_t_partial(const ListArg& L, int nv);
 int launch_b_gamma_t_reduce(const ListArg& L, int nv);
 int launch_b_hv(const ListArg& L, int gate);
 int launch_b_mu_rhs(const ListArg& L);
+// gate 0: gpv = Gamma pv under st->done; 1: the same under st->ref_skip; 2: gv = Gamma v for
+// every instance (the warm start)
 int launch_b_gamma_mv(const ListArg& L, int gate);
 int launch_b_step(const ListArg& L);
 int launch_b_update(const ListArg& L);

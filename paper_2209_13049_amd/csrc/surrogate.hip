@@ -43,6 +43,8 @@ struct Mlp {
   int* jacc = nullptr;
   int jcap = 0;
   Problem* prob = nullptr;         // the problem the policy answers (not owned)
+  cmpc_batch* fb = nullptr;        // fallback batch of copies of prob (not owned), or NULL
+  int fb_warm = 0;                 // fallback solves start from the network's answer
   size_t tsize() const { return precision == CMPC_MLP_BF16 ? 2 : 4; }
 };
 
@@ -621,6 +623,32 @@ int cmpc_judge(cmpc_mlp* h, const double* x0s, const double* u, int count, int* 
   return 0;
 }
 
+int cmpc_mlp_set_fallback(cmpc_mlp* h, cmpc_batch* batch, int warm) {
+  if (!h) {
+    set_error("NULL network");
+    return CMPC_ERR_INVALID;
+  }
+  Mlp& m = *h->m;
+  if (batch != nullptr) {
+    const int R = cmpc_batch_size(batch);
+    if (R <= 0) {
+      set_error("cmpc_mlp_set_fallback: empty batch");
+      return CMPC_ERR_INVALID;
+    }
+    for (int i = 0; i < R; ++i) {
+      const Problem& q = *cmpc_batch_instance(batch, i)->p;
+      if (q.ns != m.prob->ns || q.nu != m.prob->nu || q.N != m.prob->N) {
+        set_error("cmpc_mlp_set_fallback: instance " + std::to_string(i) +
+                  " is not a copy of the network's problem (ns, nu, N differ)");
+        return CMPC_ERR_INVALID;
+      }
+    }
+  }
+  m.fb = batch;
+  m.fb_warm = warm != 0;
+  return 0;
+}
+
 int cmpc_surrogate_solve(cmpc_mlp* h, const double* x0s, int count, double* u, int* accepted,
                          cmpc_surrogate_report* rep) {
   if (!h || !x0s || !u || count < 0) {
@@ -664,25 +692,66 @@ int cmpc_surrogate_solve(cmpc_mlp* h, const double* x0s, int count, double* u, i
   double max_vio = 0.0, max_gap = 0.0;
   cmpc_options o;
   cmpc_default_options(&o);
+  std::vector<int> rejected;
   for (int q = 0; q < count; ++q) {
     if (acc[q]) {
       ++n_acc;
       max_vio = std::max(max_vio, vio[q]);
       max_gap = std::max(max_gap, gap[q]);
-      continue;
-    }
-    // fallback: Algorithm 1 from this x0 (FP64), its controls replace the answer
-    rc = set_x0(p, x0s + (size_t)q * p.ns, 1);
-    if (rc) return rc;
-    cmpc_result r;
-    const int st = solve(p, o, &r);
-    if (st == CMPC_OK) {
-      ++fb_ok;
-      CMPC_HIP(hipMemcpyAsync(u + (size_t)q * p.n, p.v, sizeof(double) * p.n,
-                              hipMemcpyDeviceToDevice, p.stream));
     } else {
-      ++fb_fail;
-      if (st < 0) return st;
+      rejected.push_back(q);
+    }
+  }
+  if (m.fb == nullptr) {
+    // Algorithm 1 from each rejected x0 (FP64) on the network's problem, one after another;
+    // its controls replace the answer
+    for (int q : rejected) {
+      rc = set_x0(p, x0s + (size_t)q * p.ns, 1);
+      if (rc) return rc;
+      cmpc_result r;
+      if (m.fb_warm)
+        CMPC_HIP(hipMemcpyAsync(p.v, u + (size_t)q * p.n, sizeof(double) * p.n,
+                                hipMemcpyDeviceToDevice, p.stream));
+      const int st = solve(p, o, &r, m.fb_warm);
+      if (st == CMPC_OK) {
+        ++fb_ok;
+        CMPC_HIP(hipMemcpyAsync(u + (size_t)q * p.n, p.v, sizeof(double) * p.n,
+                                hipMemcpyDeviceToDevice, p.stream));
+      } else {
+        ++fb_fail;
+        if (st < 0) return st;
+      }
+    }
+  } else {
+    // the rejected queries in groups of count(batch), one batched solve per group (the last
+    // group's empty places repeat its last query; their results are not used)
+    const int R = cmpc_batch_size(m.fb);
+    std::vector<const double*> v0s(R);
+    std::vector<cmpc_result> res(R);
+    for (size_t g0 = 0; g0 < rejected.size(); g0 += R) {
+      const int len = (int)std::min<size_t>(R, rejected.size() - g0);
+      for (int i = 0; i < R; ++i) {
+        const int q = rejected[g0 + std::min(i, len - 1)];
+        cmpc_problem* inst = cmpc_batch_instance(m.fb, i);
+        rc = set_x0(*inst->p, x0s + (size_t)q * p.ns, 1);
+        if (rc) return rc;
+        v0s[i] = u + (size_t)q * p.n;
+      }
+      const int st = m.fb_warm ? cmpc_batch_solve_warm(m.fb, &o, v0s.data(), 1, res.data())
+                               : cmpc_batch_solve(m.fb, &o, res.data());
+      if (st < 0 && st != CMPC_ERR_CHOLESKY) return st;
+      for (int i = 0; i < len; ++i) {
+        const int q = rejected[g0 + i];
+        if (res[i].status == CMPC_OK) {
+          ++fb_ok;
+          Problem& ip = *cmpc_batch_instance(m.fb, i)->p;
+          CMPC_HIP(hipMemcpyAsync(u + (size_t)q * p.n, ip.v, sizeof(double) * p.n,
+                                  hipMemcpyDeviceToDevice, ip.stream));
+        } else {
+          ++fb_fail;
+        }
+      }
+      CMPC_HIP(hipStreamSynchronize(cmpc_batch_instance(m.fb, 0)->p->stream));
     }
   }
   CMPC_HIP(hipStreamSynchronize(p.stream));

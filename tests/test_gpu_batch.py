@@ -257,3 +257,32 @@ def test_batch_rebuilds_views_after_instance_calls(batch):
         ub, _ = b[i].solution(with_x=False)
         check_against_oracle(f"bf16 after singles {i}", res, ref, ub, iters_equal=False)
     condmpc.tune_clear()
+
+
+def test_batch_warm_starts(batch):
+    """cmpc_batch_solve_warm: from given controls every instance takes the oracle's warm
+    solve (reading R14) and equals the single-instance warm solve bit for bit; then from each
+    instance's last solution shifted one stage."""
+    probs, b, refs = batch
+    rng = np.random.default_rng(17)
+    v0s = [rng.uniform(-0.5, 0.5, p.n) for p in probs]
+    rc, results = b.solve_warm([torch.tensor(v, device="cuda") for v in v0s])
+    assert rc == condmpc.OK
+    ub = [b[i].solution(with_x=False)[0] for i in range(len(probs))]
+    for i, (p, res) in enumerate(zip(probs, results)):
+        ref = oracle.solve(p, v0=v0s[i])
+        check_against_oracle(f"warm {i} {p.name}", res, ref, ub[i])
+    for i in (0, 7, 10):  # the single-instance warm start through the same kernels
+        single = condmpc.Problem(probs[i])
+        single.set_x0(probs[i].x0)
+        r = single.solve_warm(v0s[i])
+        us, _ = single.solution(with_x=False)
+        single.close()
+        assert r["iters"] == results[i]["iters"] and np.array_equal(us, ub[i]), f"instance {i}"
+    rc, results = b.solve_warm()  # shift of the solution just found
+    assert rc == condmpc.OK
+    for i, (p, res) in enumerate(zip(probs, results)):
+        u, _ = b[i].solution(with_x=False)
+        from oracle import condensed_ipm as ipm
+        ref = oracle.solve(p, v0=ipm.shift_controls(ub[i], p.nu, p.N))
+        check_against_oracle(f"shift {i} {p.name}", res, ref, u, iters_equal=False)

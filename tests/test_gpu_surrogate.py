@@ -196,5 +196,25 @@ def test_surrogate_end_to_end(lib):
     # what the network gains: queries answered, with a certificate, without a solve
     assert ceiling.sum() >= nquery // 4
     assert rep["accepted"] >= ceiling.sum() // 2
+    # the same queries with the rejected ones solved together on a batch of copies of the
+    # problem, each from the network's answer (warm start): same decisions, same optima
+    fb = condmpc.Batch([prob] * 16, with_x0=False)
+    net.set_fallback(fb, warm=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u2, acc2, rep2 = net.solve(Xqd)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    print(f"[surrogate] batched warm fallback: {rep2['fallback_solved']} solved in "
+          f"{t_bat * 1e3:.1f} ms (one by one, cold: {t_sur * 1e3:.1f} ms)", flush=True)
+    assert np.array_equal(acc2, acc) and rep2["fallback_solved"] == rep["fallback_solved"]
+    u2a = u2.cpu().numpy()
+    assert np.array_equal(u2a[acc], ua[acc])
+    for k in np.flatnonzero(~acc)[::4]:
+        pk = prob.with_x0(Xq[k])
+        ref = oracle.solve(pk)
+        assert np.max(np.abs(u2a[k] - ref.v)) <= 1e-6 * max(1.0, np.max(np.abs(ref.v)))
+    net.set_fallback(None)
+    fb.close()
     net.close()
     gp.close()
