@@ -8,7 +8,8 @@ It follows Cole, Shin, Pacaud, Zavala and Anitescu, "Exploiting GPU/SIMD archite
 solving linear-quadratic MPC problems" (arXiv 2209.13049):
 
 * ``reduce_problem``  -- Section 2, eqns. (K_constraint), (x_def) and (dense): eliminate the
-  states, giving min 1/2 v'Hv + h'v + h0  s.t.  Jv <= d.
+  states, giving min 1/2 v'Hv + h'v + h0  s.t.  Jv <= d (``reduce_general`` for problems
+  with a cross weight S, rows g^l <= E x + F u <= g^u, a disturbance w or a feedback K).
 * ``condensed_step``  -- Section 3, eqns. (aug_KKT) and (cond_KKT) and the recovery
   formulas that follow them: one Newton step through the condensed matrix H + J'Sigma J,
   factored by dense Cholesky.
@@ -25,7 +26,7 @@ R1  Objective carries a 1/2 on every quadratic term (eqn. (dense) and the PDE ob
 R2  Q_f defaults to Q.
 R3  State-bound rows at t = 0 are constants and are dropped; bounds apply for t = 1..N.
     Rows whose bound is infinite are dropped.
-R4  Stabilising feedback K = 0 (v = u).
+R4  Stabilising feedback K = 0 (v = u) unless the problem gives one (``reduce_general``).
 R5  The right-hand side of eqn. (cond_KKT) is -r1 + J'r2 - J'Sigma r3 (the printed "J r2"
     is read as J'r2, which the block elimination of eqn. (aug_KKT) gives).
 R6  Sigma in the p^z formula of Algorithm 1 is Sigma_s = S^-1 Z.
@@ -79,8 +80,16 @@ class Reduced:
     h0: float
     J: np.ndarray          # inequality rows that are kept (finite bounds)
     d: np.ndarray
-    groups: np.ndarray     # 0: x <= xu, 1: -x <= -xl, 2: u <= uu, 3: -u <= -ul (kept rows)
+    groups: np.ndarray     # 0: x <= xu, 1: -x <= -xl, 2: u <= uu, 3: -u <= -ul,
+                           # 4: Ex + Fu <= gu, 5: -(Ex + Fu) <= -gl (kept rows)
     index: np.ndarray      # row index inside its group (kept rows)
+    u0: np.ndarray | None = None   # inputs u = u0 + Uv (None: u = v)
+    Uv: np.ndarray | None = None
+
+
+def inputs(red: Reduced, v: np.ndarray) -> np.ndarray:
+    """The inputs u_t = K x_t + v_t of eqn. (K_constraint), stacked (u = v when K = 0)."""
+    return v.copy() if red.Uv is None else red.u0 + red.Uv @ v
 
 
 def powers_times(A: np.ndarray, X: np.ndarray, N: int):
@@ -92,7 +101,8 @@ def powers_times(A: np.ndarray, X: np.ndarray, N: int):
 
 
 def reduce_problem(prob) -> Reduced:
-    """State elimination of Section 2 (eqn. (x_def)) with K = 0 and w = 0.
+    """State elimination of Section 2 (eqn. (x_def)) with K = 0 and w = 0 (problems with
+    more data go to ``reduce_general``).
 
     x = bA x0 + bB v, where bA stacks A^t and bB is block lower-triangular with block
     (t, j) = A^(t-1-j) B.  Rows of x_0 (t = 0) are constants and are not kept (reading R3).
@@ -102,6 +112,8 @@ def reduce_problem(prob) -> Reduced:
     J v <= d with J = [Gamma; -Gamma; I; -I],  d = [xu - c; c - xl; uu; -ul].
     Qbar is block diagonal, so it is applied block by block instead of being formed.
     """
+    if getattr(prob, "general", False):
+        return reduce_general(prob)
     A, B, Q, R, Qf = prob.A, prob.B, prob.Q, prob.R, prob.Qf
     ns, nu, N = A.shape[0], B.shape[1], int(prob.N)
     G = powers_times(A, B, N - 1)                      # G[k] = A^k B
@@ -139,6 +151,67 @@ def reduce_problem(prob) -> Reduced:
     keep = np.isfinite(d_all)
     return Reduced(Gamma=Gamma, c=c, Rbar=Rbar, H=H, h=h, h0=float(h0),
                    J=J_all[keep], d=d_all[keep], groups=g_all[keep], index=i_all[keep])
+
+
+def reduce_general(prob) -> Reduced:
+    """State elimination of Section 2 with every kind of data of eqn. (sparse).
+
+    Feedback (eqn. (K_constraint)): u_t = K x_t + v_t, so x_{t+1} = A_K x_t + B v_t + w_t with
+    A_K = A + B K, and eqn. (x_def) is x_t = c_t + Gamma_t v: c_0 = x0, c_{t+1} = A_K c_t + w_t;
+    Gamma_0 = 0, Gamma_{t+1} = A_K Gamma_t + B [block t of v] (block j of Gamma_t is
+    A_K^(t-1-j) B).  The inputs are u_t = K c_t + (K Gamma_t + [block t]) v.
+    Objective of eqn. (sparse), 1/2 convention: with z the stack of (x_t, u_t), t = 0..N-1,
+    and x_N, an affine function z = z0 + Z v, the objective is 1/2 z' W z with
+    W = blockdiag([[Q, S], [S', R]], ..., Q_f); hence H = Z' W Z, h = Z' W z0 and
+    h0 = 1/2 z0' W z0.  Inequalities: x_t in [xl, xu] for t = 1..N (reading R3), u_t in
+    [ul, uu] and E x_t + F u_t in [gl, gu] for t = 0..N-1, each an affine row of v.
+    """
+    A, B, Q, R, Qf = prob.A, prob.B, prob.Q, prob.R, prob.Qf
+    ns, nu, N = A.shape[0], B.shape[1], int(prob.N)
+    n = nu * N
+    K = np.zeros((nu, ns)) if prob.Kfb is None else np.asarray(prob.Kfb, dtype=np.float64)
+    S = np.zeros((ns, nu)) if prob.S is None else np.asarray(prob.S, dtype=np.float64)
+    w = np.zeros((N, ns)) if prob.w is None else np.asarray(prob.w, dtype=np.float64)
+    AK = A + B @ K
+    # x_t = X0[t] + XV[t] v, u_t = U0[t] + UV[t] v
+    X0 = [np.array(prob.x0, dtype=np.float64)]
+    XV = [np.zeros((ns, n))]
+    U0, UV = [], []
+    for t in range(N):
+        sel = np.zeros((nu, n))
+        sel[:, t * nu:(t + 1) * nu] = np.eye(nu)
+        U0.append(K @ X0[t])
+        UV.append(K @ XV[t] + sel)
+        X0.append(AK @ X0[t] + w[t])
+        XV.append(AK @ XV[t] + B @ sel)
+    # objective: z = (x_0, u_0, x_1, u_1, ..., x_{N-1}, u_{N-1}, x_N)
+    z0 = np.concatenate([np.concatenate([X0[t], U0[t]]) for t in range(N)] + [X0[N]])
+    Z = np.vstack([np.vstack([XV[t], UV[t]]) for t in range(N)] + [XV[N]])
+    Wst = np.block([[Q, S], [S.T, R]])
+    Wbar = sla.block_diag(*([Wst] * N + [Qf]))
+    H = Z.T @ Wbar @ Z
+    H = 0.5 * (H + H.T)
+    h = Z.T @ Wbar @ z0
+    h0 = 0.5 * z0 @ Wbar @ z0
+    Gamma = np.vstack(XV[1:])
+    c = np.concatenate(X0[1:])
+    Uv = np.vstack(UV)
+    u0 = np.concatenate(U0)
+    blocks = [(Gamma, np.tile(prob.xu, N) - c, 0), (-Gamma, c - np.tile(prob.xl, N), 1),
+              (Uv, np.tile(prob.uu, N) - u0, 2), (-Uv, u0 - np.tile(prob.ul, N), 3)]
+    if prob.E is not None:
+        E, F = np.asarray(prob.E, dtype=np.float64), np.asarray(prob.F, dtype=np.float64)
+        Cv = np.vstack([E @ XV[t] + F @ UV[t] for t in range(N)])
+        c0 = np.concatenate([E @ X0[t] + F @ U0[t] for t in range(N)])
+        blocks += [(Cv, np.tile(prob.gu, N) - c0, 4), (-Cv, c0 - np.tile(prob.gl, N), 5)]
+    J_all = np.vstack([b[0] for b in blocks])
+    d_all = np.concatenate([b[1] for b in blocks])
+    g_all = np.concatenate([np.full(b[0].shape[0], b[2]) for b in blocks])
+    i_all = np.concatenate([np.arange(b[0].shape[0]) for b in blocks])
+    keep = np.isfinite(d_all)
+    return Reduced(Gamma=Gamma, c=c, Rbar=np.kron(np.eye(N), R), H=H, h=h, h0=float(h0),
+                   J=J_all[keep], d=d_all[keep], groups=g_all[keep], index=i_all[keep],
+                   u0=u0, Uv=Uv)
 
 
 def objective(red: Reduced, v: np.ndarray) -> float:
@@ -240,6 +313,7 @@ class Result:
     gap: float
     x: np.ndarray
     history: list = field(default_factory=list)
+    u: np.ndarray | None = None   # the inputs u = K x + v (= v when K = 0)
 
 
 def initial_point(red: Reduced, mu0: float = MU_INIT, v0=None):
@@ -298,35 +372,41 @@ def solve(prob, tol: float = 1e-8, max_iter: int = 200, red: Reduced | None = No
                   obj=objective(red, v), primal_res=float(np.max(np.abs(r3), initial=0.0)),
                   dual_res=float(np.max(np.abs(r1), initial=0.0)),
                   compl_res=float(np.max(np.abs(s * z), initial=0.0)), gap=float(s @ z),
-                  x=x, history=history)
+                  x=x, history=history, u=inputs(red, v))
 
 
 def simulate(prob, u: np.ndarray) -> np.ndarray:
-    """Forward simulation x_{t+1} = A x_t + B u_t, t = 0..N-1 (eqn. (dyn) with w = 0).
+    """Forward simulation x_{t+1} = A x_t + B u_t + w_t, t = 0..N-1 (eqn. (dyn); w = 0 when
+    the problem has none), for the inputs u.
 
     Returns the states x_1..x_N stacked (length ns N).
     """
     ns, nu, N = prob.A.shape[0], prob.B.shape[1], int(prob.N)
+    w = getattr(prob, "w", None)
     x = prob.x0.copy()
     out = []
     for t in range(N):
         x = prob.A @ x + prob.B @ u[t * nu:(t + 1) * nu]
+        if w is not None:
+            x = x + w[t]
         out.append(x)
     return np.concatenate(out)
 
 
 def sparse_objective(prob, u: np.ndarray) -> float:
-    """Objective of eqn. (sparse) with the 1/2 convention (reading R1), by simulation."""
+    """Objective of eqn. (sparse) with the 1/2 convention (reading R1), by simulation, for
+    the inputs u (with the cross weight S where the problem has one)."""
     ns, nu, N = prob.A.shape[0], prob.B.shape[1], int(prob.N)
-    xs = simulate(prob, u)
-    f = 0.5 * prob.x0 @ prob.Q @ prob.x0
+    S = getattr(prob, "S", None)
+    xs = np.concatenate([prob.x0, simulate(prob, u)])
+    f = 0.0
     for t in range(N):
-        ut = u[t * nu:(t + 1) * nu]
-        f += 0.5 * ut @ prob.R @ ut
-    for t in range(1, N + 1):
-        xt = xs[(t - 1) * ns:t * ns]
-        W = prob.Qf if t == N else prob.Q
-        f += 0.5 * xt @ W @ xt
+        xt, ut = xs[t * ns:(t + 1) * ns], u[t * nu:(t + 1) * nu]
+        f += 0.5 * xt @ prob.Q @ xt + 0.5 * ut @ prob.R @ ut
+        if S is not None:
+            f += xt @ S @ ut
+    xN = xs[N * ns:]
+    f += 0.5 * xN @ prob.Qf @ xN
     return float(f)
 
 
@@ -343,6 +423,7 @@ def closed_loop(prob, steps: int, warm: bool = True, tol: float = 1e-8):
     warm, each solve after the first starts from the previous controls shifted
     (reading R14).  Returns the states x_0..x_steps, the applied inputs and the results."""
     from dataclasses import replace
+    assert not getattr(prob, "general", False), "closed_loop takes problems without S, E, F, w, K"
     nu, N = prob.B.shape[1], int(prob.N)
     x = np.array(prob.x0, dtype=np.float64)
     xs, us, results = [x.copy()], [], []

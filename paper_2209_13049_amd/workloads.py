@@ -36,11 +36,15 @@ __all__ = [
 
 @dataclass
 class LQProblem:
-    """Data of eqn. (sparse) with S = 0, E = F = 0, w = 0 (feedback gain K = 0).
+    """Data of eqn. (sparse).
 
     Arrays are float64, row-major.  ``A`` is ns x ns, ``B`` ns x nu, ``Q``/``Qf`` ns x ns,
     ``R`` nu x nu, ``xl``/``xu`` length ns, ``ul``/``uu`` length nu, ``x0`` length ns.
-    ``N`` is the horizon (the paper's T).  Infinite bounds mean "no bound".
+    ``N`` is the horizon (the paper's T).  Infinite bounds mean "no bound".  The general
+    data are optional (None: absent): the cross weight ``S`` (ns x nu), the rows
+    ``gl <= E x_t + F u_t <= gu`` (``E`` nc x ns, ``F`` nc x nu, ``gl``/``gu`` length nc), the
+    disturbance ``w`` (N x ns, w_t of eqn. (dyn)) and the stabilising feedback ``Kfb``
+    (nu x ns) of eqn. (K_constraint), u_t = Kfb x_t + v_t.
     """
 
     A: np.ndarray
@@ -56,6 +60,21 @@ class LQProblem:
     N: int
     name: str = ""
     meta: dict = field(default_factory=dict)
+    S: np.ndarray | None = None
+    E: np.ndarray | None = None
+    F: np.ndarray | None = None
+    gl: np.ndarray | None = None
+    gu: np.ndarray | None = None
+    w: np.ndarray | None = None
+    Kfb: np.ndarray | None = None
+
+    @property
+    def general(self) -> bool:
+        return any(a is not None for a in (self.S, self.E, self.F, self.w, self.Kfb))
+
+    @property
+    def nc(self) -> int:
+        return 0 if self.E is None else int(self.E.shape[0])
 
     @property
     def ns(self) -> int:
@@ -72,7 +91,8 @@ class LQProblem:
     def with_x0(self, x0) -> "LQProblem":
         return LQProblem(self.A, self.B, self.Q, self.R, self.Qf, self.xl, self.xu, self.ul,
                          self.uu, np.ascontiguousarray(x0, dtype=np.float64), self.N,
-                         self.name, dict(self.meta))
+                         self.name, dict(self.meta), self.S, self.E, self.F, self.gl, self.gu,
+                         self.w, self.Kfb)
 
 
 def _f64(a):
@@ -227,6 +247,64 @@ def heat3d(m: int, N: int, *, setpoint: float = 400.0, name: str = "", **table) 
 
 
 # Named workloads (sizes of the benchmark and parity cases).
+def general_random(ns: int, nu: int, nc: int, N: int, seed: int, *, rho: float = 1.05,
+                   bound_x: float = 0.6, bound_u: float = 1.0, bound_g: float = 0.25,
+                   w_scale: float = 0.02, x0_scale: float = 0.3, feedback: bool = True,
+                   cross: bool = True) -> LQProblem:
+    """A random instance of eqn. (sparse) with every kind of data: an A of spectral radius
+    rho (above 1: open-loop unstable), a joint weight [[Q, S], [S', R]] > 0, nc rows
+    gl <= E x + F u <= gu, a disturbance w_t and (feedback) the stabilising gain of the
+    infinite-horizon LQR of (A, B, Q, R) as Kfb, so that A + B Kfb is stable (the reason
+    eqn. (K_constraint) introduces it)."""
+    import scipy.linalg as sla
+    rng = np.random.default_rng([77, ns, nu, nc, N, seed])
+    A = rng.normal(size=(ns, ns))
+    A *= rho / max(1e-12, np.max(np.abs(np.linalg.eigvals(A))))
+    B = rng.normal(size=(ns, nu))
+    M = rng.normal(size=(ns + nu, ns + nu))
+    Wj = M @ M.T / (ns + nu) + 0.3 * np.eye(ns + nu)
+    Q, R = Wj[:ns, :ns].copy(), Wj[ns:, ns:].copy()
+    S = Wj[:ns, ns:].copy() if cross else None
+    Kfb = None
+    if feedback:
+        P = sla.solve_discrete_are(A, B, Q, R)
+        Kfb = -np.linalg.solve(R + B.T @ P @ B, B.T @ P @ A)
+    E = rng.normal(size=(nc, ns)) / np.sqrt(ns) if nc > 0 else None
+    F = rng.normal(size=(nc, nu)) / np.sqrt(nu) if nc > 0 else None
+    gl = np.full(nc, -bound_g) if nc > 0 else None
+    gu = np.full(nc, bound_g) if nc > 0 else None
+    w = w_scale * rng.normal(size=(N, ns)) if w_scale > 0 else None
+    x0 = rng.uniform(-x0_scale, x0_scale, ns)
+    return LQProblem(A=_f64(A), B=_f64(B), Q=_f64(Q), R=_f64(R), Qf=_f64(2.0 * Q),
+                     xl=np.full(ns, -bound_x), xu=np.full(ns, bound_x), ul=np.full(nu, -bound_u),
+                     uu=np.full(nu, bound_u), x0=_f64(x0), N=N,
+                     name=f"general_{ns}_{nu}_{nc}_{N}_{seed}",
+                     S=None if S is None else _f64(S), E=None if E is None else _f64(E),
+                     F=None if F is None else _f64(F), gl=gl, gu=gu,
+                     w=None if w is None else _f64(w), Kfb=None if Kfb is None else _f64(Kfb))
+
+
+def heat1d_general(ns: int, nu: int, N: int, seed=(6, 0), *, kgain: float = 0.5,
+                   cross: float = 0.02, src: float = 0.004, gbound: float = 0.15) -> LQProblem:
+    """The 1-D heat workload with the general data: a proportional feedback Kfb =
+    -kgain B' (each actuator pulls against the temperature under it; A + B Kfb stays
+    stable), a small cross weight S = cross B, a constant heat source w_t = src * (the sum of
+    the actuator bumps, normalised), and two stage rows: the total actuation
+    |sum_j u_j| <= gbound (E = 0, F = 1') and the mean temperature |mean(x)| <= gbound / 4
+    (E = 1'/ns, F = 0)."""
+    p = heat1d(ns, nu, N, seed=seed, xu=0.3, x0_range=(-0.25, 0.25))
+    B = p.B
+    bump = B.sum(axis=1)
+    w = np.tile(src * bump / max(1e-12, np.max(bump)), (N, 1))
+    E = np.vstack([np.zeros(ns), np.full(ns, 1.0 / ns)])
+    F = np.vstack([np.ones(nu), np.zeros(nu)])
+    g = np.array([gbound, gbound / 4.0])
+    return LQProblem(A=p.A, B=B, Q=p.Q, R=p.R, Qf=p.Qf, xl=p.xl, xu=p.xu, ul=p.ul, uu=p.uu,
+                     x0=p.x0, N=N, name=f"heat1d_general_{ns}_{nu}_{N}", S=_f64(cross * B),
+                     E=_f64(E), F=_f64(F), gl=_f64(-g), gu=_f64(g), w=_f64(w),
+                     Kfb=_f64(-kgain * B.T))
+
+
 CONFIG_SMALL = dict(ns=50, nu=5, N=10)       # K is 50 x 50, 500 state rows
 CONFIG_1D = dict(ns=1000, nu=10, N=50)       # K is 500 x 500, 50,000 state rows
 CONFIG_2D = dict(g=70, nu_per_edge=5, N=100)  # K is 2000 x 2000, 490,000 state rows

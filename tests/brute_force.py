@@ -205,3 +205,190 @@ def augmented_step(H, h, J, d, v, s, lam, mu, z):
     M[n + m:, n:n + m] = np.eye(m)
     sol = np.linalg.solve(M, -np.concatenate([r1, r2, r3]))
     return sol[:n], sol[n:n + m], sol[n + m:]
+
+
+# ---------------------------------------------------------------- general data (S, E, F, w, K)
+# Written from eqn. (sparse) directly, with the states as variables; they share nothing with
+# the oracle's elimination.
+
+def simulate_general(prob, v):
+    """Trajectory under u_t = K x_t + v_t (eqn. (K_constraint)) and
+    x_{t+1} = A x_t + B u_t + w_t (eqn. (dyn)): states x_0..x_N (rows) and inputs u_0..u_{N-1}."""
+    ns, nu, N = prob.A.shape[0], prob.B.shape[1], int(prob.N)
+    K = np.zeros((nu, ns)) if prob.Kfb is None else prob.Kfb
+    xs = [np.array(prob.x0, dtype=np.float64)]
+    us = []
+    for t in range(N):
+        u = K @ xs[-1] + v[t * nu:(t + 1) * nu]
+        us.append(u)
+        x = prob.A @ xs[-1] + prob.B @ u
+        if prob.w is not None:
+            x = x + prob.w[t]
+        xs.append(x)
+    return np.array(xs), np.array(us)
+
+
+def objective_general(prob, xs, us):
+    """Objective of eqn. (sparse), 1/2 convention: sum_t 1/2 [x;u]'[[Q, S], [S', R]][x;u] +
+    1/2 x_N' Q_f x_N."""
+    S = np.zeros((prob.A.shape[0], prob.B.shape[1])) if prob.S is None else prob.S
+    f = 0.0
+    for t in range(int(prob.N)):
+        x, u = xs[t], us[t]
+        f += 0.5 * x @ prob.Q @ x + x @ S @ u + 0.5 * u @ prob.R @ u
+    return float(f + 0.5 * xs[-1] @ prob.Qf @ xs[-1])
+
+
+def constraint_values(prob, xs, us):
+    """Left sides minus right sides of every inequality of eqn. (sparse), by kind:
+    {0: x - xu, 1: xl - x (t = 1..N), 2: u - uu, 3: ul - u, 4: Ex + Fu - gu,
+    5: gl - (Ex + Fu) (t = 0..N-1)}, each stacked over t."""
+    N = int(prob.N)
+    X = xs[1:]
+    out = {0: (X - prob.xu).ravel(), 1: (prob.xl - X).ravel(), 2: (us - prob.uu).ravel(),
+           3: (prob.ul - us).ravel()}
+    if prob.E is not None:
+        g = np.array([prob.E @ xs[t] + prob.F @ us[t] for t in range(N)])
+        out[4] = (g - prob.gu).ravel()
+        out[5] = (prob.gl - g).ravel()
+    return out
+
+
+def riccati_cross(prob):
+    """Unconstrained minimiser with a cross weight (no feedback, no disturbance): the
+    backward recursion P_N = Q_f, L_t = (R + B'P B)^-1 (B'P A + S'),
+    P_t = Q + A'P A - (A'P B + S) L_t, u_t = -L_t x_t, f* = 1/2 x0' P_0 x0."""
+    A, B, Q, R, Qf, N = prob.A, prob.B, prob.Q, prob.R, prob.Qf, int(prob.N)
+    S = prob.S
+    P = Qf.copy()
+    gains = [None] * N
+    for t in range(N - 1, -1, -1):
+        L = np.linalg.solve(R + B.T @ P @ B, B.T @ P @ A + S.T)
+        gains[t] = L
+        P = Q + A.T @ P @ A - (A.T @ P @ B + S) @ L
+        P = 0.5 * (P + P.T)
+    x = prob.x0.copy()
+    u = []
+    for t in range(N):
+        ut = -gains[t] @ x
+        u.append(ut)
+        x = A @ x + B @ ut
+    return np.concatenate(u), float(0.5 * prob.x0 @ P @ prob.x0)
+
+
+def sparse_active_set(prob):
+    """Exact minimiser of eqn. (sparse) in its own variables y = [u_0..u_{N-1}, x_1..x_N]
+    (the dynamics as equality constraints, the feedback gain plays no part) by enumerating
+    which bound of every bounded quantity (x_t,i, u_t,j, (E x_t + F u_t)_k) is active.
+    Returns (u*, f*).  Tiny sizes only (3^quantities equality-constrained solves)."""
+    A, B, Q, R, Qf = prob.A, prob.B, prob.Q, prob.R, prob.Qf
+    ns, nu, N = A.shape[0], B.shape[1], int(prob.N)
+    S = np.zeros((ns, nu)) if prob.S is None else prob.S
+    w = np.zeros((N, ns)) if prob.w is None else prob.w
+    x0 = prob.x0
+    nU, nX = nu * N, ns * N
+    ny = nU + nX
+    ui = lambda t: slice(t * nu, (t + 1) * nu)                 # noqa: E731
+    xi = lambda t: slice(nU + (t - 1) * ns, nU + t * ns)       # t = 1..N  # noqa: E731
+    P = np.zeros((ny, ny))
+    q = np.zeros(ny)
+    const = 0.5 * x0 @ Q @ x0
+    for t in range(N):
+        P[ui(t), ui(t)] += R
+        if t == 0:
+            q[ui(0)] += S.T @ x0
+        else:
+            P[xi(t), xi(t)] += Q
+            P[xi(t), ui(t)] += S
+            P[ui(t), xi(t)] += S.T
+    P[xi(N), xi(N)] += Qf
+    Aeq = np.zeros((nX, ny))
+    beq = np.zeros(nX)
+    for t in range(N):
+        r = slice(t * ns, (t + 1) * ns)
+        Aeq[r, xi(t + 1)] = np.eye(ns)
+        Aeq[r, ui(t)] = -B
+        if t == 0:
+            beq[r] = A @ x0 + w[0]
+        else:
+            Aeq[r, xi(t)] = -A
+            beq[r] = w[t]
+    rows, rhs, pairs = [], [], []
+
+    def add_pair(a, a0, lo, hi):
+        """a y + a0 in [lo, hi]: rows a y <= hi - a0 and -a y <= a0 - lo."""
+        up = lw = None
+        if np.isfinite(hi):
+            up = len(rows)
+            rows.append(a)
+            rhs.append(hi - a0)
+        if np.isfinite(lo):
+            lw = len(rows)
+            rows.append(-a)
+            rhs.append(a0 - lo)
+        if up is not None or lw is not None:
+            pairs.append((up, lw))
+
+    for t in range(1, N + 1):
+        for i in range(ns):
+            a = np.zeros(ny)
+            a[xi(t).start + i] = 1.0
+            add_pair(a, 0.0, prob.xl[i], prob.xu[i])
+    for t in range(N):
+        for j in range(nu):
+            a = np.zeros(ny)
+            a[ui(t).start + j] = 1.0
+            add_pair(a, 0.0, prob.ul[j], prob.uu[j])
+    if prob.E is not None:
+        for t in range(N):
+            for k in range(prob.E.shape[0]):
+                a = np.zeros(ny)
+                a[ui(t)] = prob.F[k]
+                a0 = 0.0
+                if t == 0:
+                    a0 = prob.E[k] @ x0
+                else:
+                    a[xi(t)] = prob.E[k]
+                add_pair(a, a0, prob.gl[k], prob.gu[k])
+    C, dC = np.array(rows), np.array(rhs)
+    best = None
+    for choice in itertools.product((0, 1, 2), repeat=len(pairs)):
+        act = []
+        for (up, lw), c in zip(pairs, choice):
+            if c == 1:
+                if up is None:
+                    break
+                act.append(up)
+            elif c == 2:
+                if lw is None:
+                    break
+                act.append(lw)
+        else:
+            k = len(act)
+            Geq = np.vstack([Aeq, C[act]]) if k else Aeq
+            if np.linalg.matrix_rank(Geq, tol=1e-9) < nX + k:
+                continue      # dependent active rows: covered by a smaller active set
+            M = np.zeros((ny + nX + k, ny + nX + k))
+            M[:ny, :ny] = P
+            M[:ny, ny:ny + nX] = Aeq.T
+            M[ny:ny + nX, :ny] = Aeq
+            if k:
+                M[:ny, ny + nX:] = C[act].T
+                M[ny + nX:, :ny] = C[act]
+            b = np.concatenate([-q, beq, dC[act]])
+            try:
+                sol = np.linalg.solve(M, b)
+            except np.linalg.LinAlgError:
+                continue
+            if not np.all(np.isfinite(sol)):
+                continue
+            y, lam = sol[:ny], sol[ny + nX:]
+            scale = 1.0 + np.max(np.abs(dC))
+            if (np.all(C @ y <= dC + 1e-10 * scale) and np.all(lam >= -1e-10)
+                    and np.max(np.abs(Aeq @ y - beq)) <= 1e-10 * (1.0 + np.max(np.abs(beq)))):
+                f = 0.5 * y @ P @ y + q @ y + const
+                if best is None or f < best[1] - 1e-12:
+                    best = (y[:nU].copy(), float(f))
+    if best is None:
+        raise RuntimeError("no optimal active set found")
+    return best

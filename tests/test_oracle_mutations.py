@@ -14,6 +14,7 @@ import pytest
 
 import brute_force as bf
 import test_oracle_barrier as tb
+import test_oracle_general as tg
 from paper_2209_13049_amd import workloads as W
 from test_oracle_pins import random_stable, _binding_case, _pairs, _interior_point
 
@@ -69,6 +70,22 @@ MUTATIONS = {
     "warm_mu_cold_value": ("WARM_MU_INIT = 1e-3\nS_INIT_MIN", "WARM_MU_INIT = 0.1\nS_INIT_MIN"),
     "closed_loop_last_input": ("u0 = r.v[:nu].copy()", "u0 = r.v[-nu:].copy()"),
     "closed_loop_no_input": ("x = prob.A @ x + prob.B @ u0", "x = prob.A @ x"),
+    # the elimination with general data (S, E/F rows, w, feedback K)
+    "general_w_dropped": ("X0.append(AK @ X0[t] + w[t])", "X0.append(AK @ X0[t])"),
+    "general_open_loop_powers": ("AK = A + B @ K", "AK = A"),
+    "general_feedback_dropped_from_inputs": ("UV.append(K @ XV[t] + sel)", "UV.append(sel)"),
+    "general_cross_half_dropped": ("Wst = np.block([[Q, S], [S.T, R]])",
+                                   "Wst = np.block([[Q, 0.0 * S], [S.T, R]])"),
+    "general_terminal_weight_Q": ("Wbar = sla.block_diag(*([Wst] * N + [Qf]))",
+                                  "Wbar = sla.block_diag(*([Wst] * N + [Q]))"),
+    "general_F_dropped": ("Cv = np.vstack([E @ XV[t] + F @ UV[t] for t in range(N)])",
+                          "Cv = np.vstack([E @ XV[t] for t in range(N)])"),
+    "general_g_lower_sign": ("(-Cv, c0 - np.tile(prob.gl, N), 5)",
+                             "(-Cv, c0 + np.tile(prob.gl, N), 5)"),
+    "general_input_lower_sign": ("(-Uv, u0 - np.tile(prob.ul, N), 3)",
+                                 "(-Uv, u0 + np.tile(prob.ul, N), 3)"),
+    "general_stage_offset": ("sel[:, t * nu:(t + 1) * nu] = np.eye(nu)",
+                             "sel[:, max(t - 1, 0) * nu:max(t, 1) * nu] = np.eye(nu)"),
 }
 
 
@@ -197,10 +214,50 @@ def check_closed_loop_lqr(m):
         assert np.max(np.abs(xs[k + 1] - x)) <= 1e-7
 
 
+def check_general_simulation(m):
+    for args in tg.CASES[:2]:
+        p = tg.case(*args)
+        red = m.reduce_problem(p)
+        v = np.random.default_rng(3).normal(size=p.n)
+        xs, us = bf.simulate_general(p, v)
+        np.testing.assert_allclose(red.c + red.Gamma @ v, xs[1:].ravel(), rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(m.inputs(red, v), us.ravel(), rtol=1e-11, atol=1e-12)
+
+
+def check_general_objective(m):
+    p = tg.case(*tg.CASES[0])
+    red = m.reduce_problem(p)
+    v = np.random.default_rng(4).normal(size=p.n)
+    xs, us = bf.simulate_general(p, v)
+    assert abs(m.objective(red, v) - bf.objective_general(p, xs, us)) <= 1e-11
+
+
+def check_general_rows(m):
+    p = tg.case(*tg.CASES[1])
+    red = m.reduce_problem(p)
+    v = np.random.default_rng(5).normal(size=p.n)
+    xs, us = bf.simulate_general(p, v)
+    vals = bf.constraint_values(p, xs, us)
+    got = red.J @ v - red.d
+    for g, want in vals.items():
+        np.testing.assert_allclose(got[red.groups == g], want[red.index[red.groups == g]],
+                                   rtol=1e-11, atol=1e-12)
+
+
+def check_general_active_set(m):
+    for args in tg.TIGHT[:3]:
+        p = tg.tight_case(*args)
+        u_ex, f_ex = bf.sparse_active_set(p)
+        r = m.solve(p, max_iter=60)
+        assert r.status == 0
+        assert np.max(np.abs(r.u - u_ex)) <= 1e-5
+
+
 CHECKS = [check_simulation, check_objective, check_full_space, check_ftb, check_riccati,
           check_active_set, check_tight_converges, check_linear_residual_decay,
           check_barrier_rule, check_scalar_mu_sequence, check_shift, check_warm_start_point,
-          check_closed_loop_lqr]
+          check_closed_loop_lqr, check_general_simulation, check_general_objective,
+          check_general_rows, check_general_active_set]
 
 
 def run_checks(m):
