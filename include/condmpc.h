@@ -60,14 +60,24 @@ extern "C" {
 
 typedef struct cmpc_problem cmpc_problem;
 
-/* Problem data of eqn. (sparse) restricted to S = 0, E = F = 0, w = 0 (host pointers).
- * A: ns x ns, B: ns x nu, Q, Qf: ns x ns (Qf may be NULL -> Q), R: nu x nu symmetric
- * positive definite.  xl, xu: length ns; ul, uu: length nu; an infinite bound drops its
- * rows (+INFINITY upper, -INFINITY lower).  N >= 1 is the horizon (the paper's T). */
+/* Problem data of eqn. (sparse).  A: ns x ns, B: ns x nu, Q, Qf: ns x ns (Qf may be NULL ->
+ * Q), R: nu x nu symmetric positive definite.  xl, xu: length ns; ul, uu: length nu; an
+ * infinite bound drops its rows (+INFINITY upper, -INFINITY lower).  N >= 1 is the horizon
+ * (the paper's T).  The general data may be NULL / 0 (absent): the cross weight S (ns x nu,
+ * stage cost 1/2 [x;u]'[[Q, S], [S', R]][x;u], which must be positive semidefinite), the nc
+ * rows gl <= E x_t + F u_t <= gu for t = 0..N-1 (E nc x ns, F nc x nu, gl, gu length nc),
+ * the disturbance w (N x ns, row t is w_t of eqn. (dyn)) and the stabilising feedback Kfb
+ * (nu x ns) of eqn. (K_constraint), u_t = Kfb x_t + v_t: the decision variable becomes v,
+ * the input bounds rows of J (Kfb Gamma + I), and Gamma is formed with A + B Kfb.  All
+ * pointers are host memory, or device memory if data_on_device is nonzero (the library
+ * reads them once during cmpc_problem_create). */
 typedef struct {
   int ns, nu, N;
   const double *A, *B, *Q, *R, *Qf;
   const double *xl, *xu, *ul, *uu;
+  int nc;
+  const double *S, *E, *F, *gl, *gu, *w, *Kfb;
+  int data_on_device;
 } cmpc_lq_desc;
 
 typedef struct {
@@ -145,7 +155,9 @@ void cmpc_problem_destroy(cmpc_problem* p);
 int cmpc_problem_info(const cmpc_problem* p, cmpc_info* info);
 
 /* n = nu N (size of K), mx = ns N (rows of Gamma), m = 2 mx + 2 n (inequality rows of
- * eqn. (dense) before rows with infinite bounds are dropped).  Any output may be NULL. */
+ * eqn. (dense) before rows with infinite bounds are dropped).  Any output may be NULL.  With
+ * general data the rows of the input bounds (under a feedback) and of E x + F u are carried
+ * as extra rows of each stage of Gamma: mx = (ns + nz) N with nz = (Kfb ? nu : 0) + nc. */
 int cmpc_problem_dims(const cmpc_problem* p, int* n, int* mx, int* m);
 
 /* Set the initial state (length ns; host or device pointer by on_device) and form the
@@ -169,8 +181,9 @@ int cmpc_solve(cmpc_problem* p, const cmpc_options* opts, cmpc_result* res);
 int cmpc_solve_warm(cmpc_problem* p, const cmpc_options* opts, const double* v0, int on_device,
                     cmpc_result* res);
 
-/* Copy out the last solve's controls u = v (length nu N) and, if x != NULL, the states
- * x_1..x_N = c + Gamma v (length ns N).  Host or device pointers by on_device. */
+/* Copy out the last solve's inputs u_t = Kfb x_t + v_t (= v without a feedback; length
+ * nu N) and, if x != NULL, the states x_1..x_N = c + Gamma v (length ns N, the problem's own
+ * ns).  Host or device pointers by on_device. */
 int cmpc_get_solution(const cmpc_problem* p, double* u, double* x, int on_device);
 
 /* Copy out the current iterate: v (n), s, lambda, z (m each, rows in the order
@@ -211,7 +224,7 @@ int cmpc_potrf(double* K, int n, int ld, void* stream, int* info);
 /* cmpc_potrf for callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): the same factorisation, kernels and
  * results, but its scratch (the 64 x 64 tile inverses and the status flags) is a fixed
- * file-scope device array of the library, 2 MiB per device, held until the process ends; the
+ * file-scope device array of the library, about 2 MiB per device, held until the process ends; the
  * call allocates nothing.  n <= CMPC_POTRF_NOALLOC_MAX_N, else CMPC_ERR_INVALID.  The
  * stream's device (the current device if stream is NULL) is the one used.  Every call on a
  * device shares that device's array: calls that overlap on one device (other streams or

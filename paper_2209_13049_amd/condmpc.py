@@ -39,7 +39,9 @@ _dp = ctypes.POINTER(ctypes.c_double)
 class LQDesc(ctypes.Structure):
     _fields_ = [("ns", ctypes.c_int), ("nu", ctypes.c_int), ("N", ctypes.c_int),
                 ("A", _dp), ("B", _dp), ("Q", _dp), ("R", _dp), ("Qf", _dp),
-                ("xl", _dp), ("xu", _dp), ("ul", _dp), ("uu", _dp)]
+                ("xl", _dp), ("xu", _dp), ("ul", _dp), ("uu", _dp),
+                ("nc", ctypes.c_int), ("S", _dp), ("E", _dp), ("F", _dp), ("gl", _dp),
+                ("gu", _dp), ("w", _dp), ("Kfb", _dp), ("data_on_device", ctypes.c_int)]
 
 
 LOG_FN = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_void_p)
@@ -219,17 +221,42 @@ def _desc(prob):
     A, B, Q, R, Qf, xl, xu, ul, uu = keep
     d = LQDesc(ns=A.shape[0], nu=B.shape[1], N=int(prob.N), A=_ptr(A), B=_ptr(B), Q=_ptr(Q),
                R=_ptr(R), Qf=_ptr(Qf), xl=_ptr(xl), xu=_ptr(xu), ul=_ptr(ul), uu=_ptr(uu))
+    for name in ("S", "E", "F", "gl", "gu", "w", "Kfb"):
+        a = getattr(prob, name, None)
+        if a is not None:
+            a = _f64(a)
+            keep.append(a)
+            setattr(d, name, _ptr(a))
+    if getattr(prob, "E", None) is not None:
+        d.nc = int(np.shape(prob.E)[0])
     return d, keep
 
 
-class Problem:
-    """A reduced LQ-MPC problem resident on the GPU (wraps cmpc_problem)."""
+def _desc_device(prob):
+    """The same descriptor with every array in device memory (data_on_device = 1)."""
+    import torch
+    d, keep = _desc(prob)
+    dev = []
+    for name, _ in LQDesc._fields_:
+        ptr = getattr(d, name)
+        if isinstance(ptr, _dp) and ptr:
+            a = next(k for k in keep if k.ctypes.data == ctypes.cast(ptr, ctypes.c_void_p).value)
+            t = torch.from_numpy(a).to("cuda")
+            dev.append(t)
+            setattr(d, name, ctypes.cast(ctypes.c_void_p(t.data_ptr()), _dp))
+    d.data_on_device = 1
+    return d, keep + dev
 
-    def __init__(self, prob, stream=None, _handle=None):
+
+class Problem:
+    """A reduced LQ-MPC problem resident on the GPU (wraps cmpc_problem).  device_data: hand
+    the library device copies of the data (data_on_device = 1)."""
+
+    def __init__(self, prob, stream=None, _handle=None, device_data=False):
         lib = load()
         self._borrowed = _handle is not None
         if _handle is None:
-            d, self._keep = _desc(prob)
+            d, self._keep = _desc_device(prob) if device_data else _desc(prob)
             self._h = ctypes.c_void_p()
             st = _stream() if stream is None else ctypes.c_void_p(stream)
             _check(lib.cmpc_problem_create(ctypes.byref(d), st, ctypes.byref(self._h)))
@@ -296,8 +323,10 @@ class Problem:
         return r.as_dict()
 
     def solution(self, with_x=True):
+        """(u, x): the inputs u_t = K x_t + v_t (= v without a feedback) and the states
+        x_1..x_N (ns N, the problem's own states)."""
         u = np.empty(self.n)
-        x = np.empty(self.mx) if with_x else None
+        x = np.empty(self.ns * self.N) if with_x else None
         _check(load().cmpc_get_solution(self._h, u.ctypes.data_as(ctypes.c_void_p),
                                         x.ctypes.data_as(ctypes.c_void_p) if with_x else None, 0))
         return u, x

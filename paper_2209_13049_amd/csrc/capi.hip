@@ -15,12 +15,12 @@ void set_error(const std::string& msg) { g_error = msg; }
 
 int launch_convert_gamma(Problem& p, int precision);
 
-// ---- the scratch of cmpc_potrf_noalloc: the tile inverses W_k of the factorisation
-// (4096 doubles per 64-column block) and three status flags, in one file-scope device array
-// of fixed size.  Host code never passes the array's name to a kernel or a copy: it is a
+// ---- the scratch of cmpc_potrf_noalloc: the tile inverses W_k of the factorisation and
+// their condition figures (4104 doubles per 64-column block) and three status flags, in one
+// file-scope device array of fixed size.  Host code never passes the array's name to a kernel or a copy: it is a
 // host-side stand-in, not a device address.  Each device's copy is looked up once with
 // hipGetSymbolAddress (that device current) and that address is used from then on.
-constexpr size_t kNoAllocWallDoubles = 4096 * (size_t)((CMPC_POTRF_NOALLOC_MAX_N + 63) / 64);
+constexpr size_t kNoAllocWallDoubles = (4096 + 8) * (size_t)((CMPC_POTRF_NOALLOC_MAX_N + 63) / 64);
 static __device__ __align__(256) double scratch[kNoAllocWallDoubles + 8];
 
 namespace {
@@ -93,6 +93,8 @@ void free_problem(Problem* p) {
   if (p->a_col) hipFree(p->a_col);
   if (p->a_val) hipFree(p->a_val);
   if (p->red_part) hipFree(p->red_part);
+  if (p->Sx) hipFree(p->Sx);
+  if (p->wdist) hipFree(p->wdist);
   if (p->G32) hipFree(p->G32);
   if (p->G16) hipFree(p->G16);
   if (p->st) hipFree(p->st);
@@ -117,7 +119,7 @@ static int upload(double** dst, const double* src, size_t len, hipStream_t s) {
   return 0;
 }
 
-int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
+static int create_standard(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
   if (!desc || !out) {
     set_error("NULL argument");
     return CMPC_ERR_INVALID;
@@ -185,6 +187,7 @@ int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
   }
   Problem* p = new Problem();
   p->ns = ns;
+  p->ns_real = ns;
   p->nu = nu;
   p->N = N;
   p->n = nu * N;
@@ -332,32 +335,246 @@ int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
   return 0;
 }
 
+// ---- general data of eqn. (sparse) (cross weight S, rows gl <= E x + F u <= gu, disturbance
+// w, feedback u = K x + v of eqn. (K_constraint)) folded into the form the kernels solve.
+// With v the decision variable, x_{t+1} = A_K x_t + B v_t + w_t (A_K = A + B K), and every
+// stage row that is not a bound on x_t -- the input bounds under a feedback (u_t = K x_t +
+// v_t) and E x_t + F u_t = (E + F K) x_t + F v_t -- is the value y_{t+1} = M x_t + P v_t of
+// nz extra state components, M = [K; E + F K], P = [I; F].  Their bounds [ul; gl], [uu; gu]
+// on y_1..y_N are exactly those rows for t = 0..N-1, so J and the condensed matrix are the
+// paper's (rows reordered).  The stage cost in (x, v) is 1/2 x'Q~x + x'S~v + 1/2 v'Rv with
+// Q~ = Q + S K + K'S' + K'R K and S~ = S + K'R; the extra components carry no cost.
+struct GeneralData {
+  bool any = false, feedback = false;
+  int ns_real = 0, nz = 0;
+  std::vector<double> A, B, Q, Qf, R, xl, xu, ul, uu, S, w;
+  cmpc_lq_desc std_desc{};
+};
+
+static int host_copy(const double* src, size_t len, bool on_device, std::vector<double>& dst) {
+  dst.resize(len);
+  if (len == 0) return 0;
+  if (on_device) {
+    CMPC_HIP(hipMemcpy(dst.data(), src, sizeof(double) * len, hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(dst.data(), src, sizeof(double) * len);
+  }
+  return 0;
+}
+
+static int fold_general(const cmpc_lq_desc& d, GeneralData& g) {
+  const int ns = d.ns, nu = d.nu, N = d.N, nc = d.nc;
+  const bool dev = d.data_on_device != 0;
+  g.any = dev || d.S || d.w || d.Kfb || nc > 0;
+  if (!g.any) return 0;
+  if (ns <= 0 || nu <= 0 || N <= 0 || nc < 0) {
+    set_error("ns, nu and N must be positive and nc >= 0");
+    return CMPC_ERR_INVALID;
+  }
+  if (!d.A || !d.B || !d.Q || !d.R || !d.xl || !d.xu || !d.ul || !d.uu ||
+      (nc > 0 && (!d.E || !d.F || !d.gl || !d.gu))) {
+    set_error("NULL problem data");
+    return CMPC_ERR_INVALID;
+  }
+  std::vector<double> A, B, Q, Qf, R, xl, xu, ul, uu, S, E, F, gl, gu, w, K;
+  int rc = 0;
+  rc = rc ? rc : host_copy(d.A, (size_t)ns * ns, dev, A);
+  rc = rc ? rc : host_copy(d.B, (size_t)ns * nu, dev, B);
+  rc = rc ? rc : host_copy(d.Q, (size_t)ns * ns, dev, Q);
+  rc = rc ? rc : host_copy(d.Qf ? d.Qf : d.Q, (size_t)ns * ns, dev, Qf);
+  rc = rc ? rc : host_copy(d.R, (size_t)nu * nu, dev, R);
+  rc = rc ? rc : host_copy(d.xl, ns, dev, xl);
+  rc = rc ? rc : host_copy(d.xu, ns, dev, xu);
+  rc = rc ? rc : host_copy(d.ul, nu, dev, ul);
+  rc = rc ? rc : host_copy(d.uu, nu, dev, uu);
+  if (d.S) rc = rc ? rc : host_copy(d.S, (size_t)ns * nu, dev, S);
+  if (nc > 0) {
+    rc = rc ? rc : host_copy(d.E, (size_t)nc * ns, dev, E);
+    rc = rc ? rc : host_copy(d.F, (size_t)nc * nu, dev, F);
+    rc = rc ? rc : host_copy(d.gl, nc, dev, gl);
+    rc = rc ? rc : host_copy(d.gu, nc, dev, gu);
+  }
+  if (d.w) rc = rc ? rc : host_copy(d.w, (size_t)N * ns, dev, w);
+  if (d.Kfb) rc = rc ? rc : host_copy(d.Kfb, (size_t)nu * ns, dev, K);
+  if (rc) return rc;
+  for (const std::vector<double>* v : {&S, &E, &F, &w, &K})
+    if (!all_finite(v->data(), v->size())) {
+      set_error("non-finite entry in S, E, F, w or Kfb");
+      return CMPC_ERR_NONFINITE;
+    }
+  for (int k = 0; k < nc; ++k)
+    if (std::isnan(gl[k]) || std::isnan(gu[k]) || gl[k] > gu[k]) {
+      set_error("invalid bounds of the rows E x + F u (need gl <= gu)");
+      return std::isnan(gl[k]) || std::isnan(gu[k]) ? CMPC_ERR_NONFINITE : CMPC_ERR_INVALID;
+    }
+  g.feedback = !K.empty();
+  if (K.empty()) K.assign((size_t)nu * ns, 0.0);
+  if (S.empty()) S.assign((size_t)ns * nu, 0.0);
+  const int nz = (g.feedback ? nu : 0) + nc, na = ns + nz;
+  g.ns_real = ns;
+  g.nz = nz;
+  auto at = [](std::vector<double>& M, int ld, int i, int j) -> double& {
+    return M[(size_t)i * ld + j];
+  };
+  // A_K = A + B K, M = [K; E + F K] (nz x ns), P = [I; F] (nz x nu)
+  std::vector<double> AK(A), Mz((size_t)nz * ns, 0.0), Pz((size_t)nz * nu, 0.0);
+  for (int i = 0; i < ns; ++i)
+    for (int j = 0; j < ns; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < nu; ++k) acc += B[(size_t)i * nu + k] * K[(size_t)k * ns + j];
+      at(AK, ns, i, j) += acc;
+    }
+  int r0 = 0;
+  if (g.feedback) {
+    for (int k = 0; k < nu; ++k) {
+      for (int j = 0; j < ns; ++j) at(Mz, ns, k, j) = K[(size_t)k * ns + j];
+      at(Pz, nu, k, k) = 1.0;
+    }
+    r0 = nu;
+  }
+  for (int c = 0; c < nc; ++c) {
+    for (int j = 0; j < ns; ++j) {
+      double acc = E[(size_t)c * ns + j];
+      for (int k = 0; k < nu; ++k) acc += F[(size_t)c * nu + k] * K[(size_t)k * ns + j];
+      at(Mz, ns, r0 + c, j) = acc;
+    }
+    for (int k = 0; k < nu; ++k) at(Pz, nu, r0 + c, k) = F[(size_t)c * nu + k];
+  }
+  // augmented A' = [[A_K, 0], [M, 0]], B' = [B; P]
+  g.A.assign((size_t)na * na, 0.0);
+  g.B.assign((size_t)na * nu, 0.0);
+  for (int i = 0; i < ns; ++i) {
+    for (int j = 0; j < ns; ++j) at(g.A, na, i, j) = at(AK, ns, i, j);
+    for (int k = 0; k < nu; ++k) at(g.B, nu, i, k) = B[(size_t)i * nu + k];
+  }
+  for (int r = 0; r < nz; ++r) {
+    for (int j = 0; j < ns; ++j) at(g.A, na, ns + r, j) = at(Mz, ns, r, j);
+    for (int k = 0; k < nu; ++k) at(g.B, nu, ns + r, k) = at(Pz, nu, r, k);
+  }
+  // Q~ = Q + S K + K'S' + K'R K, S~ = S + K'R (ns x nu); Q' = blkdiag(Q~, 0), Qf' likewise
+  g.Q.assign((size_t)na * na, 0.0);
+  g.Qf.assign((size_t)na * na, 0.0);
+  for (int i = 0; i < ns; ++i)
+    for (int j = 0; j < ns; ++j) {
+      double sk = 0.0, ks = 0.0, krk = 0.0;
+      for (int k = 0; k < nu; ++k) {
+        sk += S[(size_t)i * nu + k] * K[(size_t)k * ns + j];
+        ks += K[(size_t)k * ns + i] * S[(size_t)j * nu + k];
+        double rk = 0.0;
+        for (int l = 0; l < nu; ++l) rk += R[(size_t)k * nu + l] * K[(size_t)l * ns + j];
+        krk += K[(size_t)k * ns + i] * rk;
+      }
+      at(g.Q, na, i, j) = Q[(size_t)i * ns + j] + sk + ks + krk;
+      at(g.Qf, na, i, j) = Qf[(size_t)i * ns + j];
+    }
+  g.S.assign((size_t)na * nu, 0.0);
+  bool cross = false;
+  for (int i = 0; i < ns; ++i)
+    for (int k = 0; k < nu; ++k) {
+      double v = S[(size_t)i * nu + k];
+      for (int l = 0; l < nu; ++l) v += K[(size_t)l * ns + i] * R[(size_t)l * nu + k];
+      at(g.S, nu, i, k) = v;
+      cross = cross || v != 0.0;
+    }
+  if (!cross) g.S.clear();
+  // bounds: x' in [xl; ul (feedback); gl], v free under a feedback
+  g.xl = xl;
+  g.xu = xu;
+  if (g.feedback) {
+    g.xl.insert(g.xl.end(), ul.begin(), ul.end());
+    g.xu.insert(g.xu.end(), uu.begin(), uu.end());
+    g.ul.assign(nu, -INFINITY);
+    g.uu.assign(nu, INFINITY);
+  } else {
+    g.ul = ul;
+    g.uu = uu;
+  }
+  g.xl.insert(g.xl.end(), gl.begin(), gl.end());
+  g.xu.insert(g.xu.end(), gu.begin(), gu.end());
+  g.R = R;
+  if (!w.empty()) {
+    g.w.assign((size_t)N * na, 0.0);
+    for (int t = 0; t < N; ++t)
+      for (int i = 0; i < ns; ++i) g.w[(size_t)t * na + i] = w[(size_t)t * ns + i];
+  }
+  cmpc_lq_desc& sd = g.std_desc;
+  std::memset(&sd, 0, sizeof(sd));
+  sd.ns = na;
+  sd.nu = nu;
+  sd.N = N;
+  sd.A = g.A.data();
+  sd.B = g.B.data();
+  sd.Q = g.Q.data();
+  sd.Qf = g.Qf.data();
+  sd.R = g.R.data();
+  sd.xl = g.xl.data();
+  sd.xu = g.xu.data();
+  sd.ul = g.ul.data();
+  sd.uu = g.uu.data();
+  return 0;
+}
+
+
+int create(const cmpc_lq_desc* desc, hipStream_t stream, Problem** out) {
+  if (!desc || !out) {
+    set_error("NULL argument");
+    return CMPC_ERR_INVALID;
+  }
+  *out = nullptr;
+  GeneralData g;
+  int rc = fold_general(*desc, g);
+  if (rc) return rc;
+  if (!g.any) return create_standard(desc, stream, out);
+  Problem* p = nullptr;
+  rc = create_standard(&g.std_desc, stream, &p);
+  if (rc) return rc;
+  p->ns_real = g.ns_real;
+  p->nz = g.nz;
+  p->feedback = g.feedback;
+  if (!g.S.empty()) {
+    rc = upload(&p->Sx, g.S.data(), g.S.size(), stream);
+    if (!rc) rc = launch_cross_hessian(*p, p->Sx);
+  }
+  if (!rc && !g.w.empty()) rc = upload(&p->wdist, g.w.data(), g.w.size(), stream);
+  if (!rc && hipStreamSynchronize(stream) != hipSuccess) rc = CMPC_ERR_HIP;
+  if (rc) {
+    free_problem(p);
+    return rc;
+  }
+  *out = p;
+  return 0;
+}
+
 int set_x0(Problem& p, const double* x0, int on_device) {
+  const int nr = p.ns_real;  // the problem's own states; the extra stage rows start at 0
   if (!on_device) {
-    for (int i = 0; i < p.ns; ++i)
+    for (int i = 0; i < nr; ++i)
       if (!std::isfinite(x0[i])) {
         set_error("x0 has a non-finite entry");
         return CMPC_ERR_NONFINITE;
       }
     if (p.xl_host.empty()) {
-      p.xl_host.resize(p.ns);
-      p.xu_host.resize(p.ns);
-      CMPC_HIP(hipMemcpy(p.xl_host.data(), p.xl, sizeof(double) * p.ns, hipMemcpyDeviceToHost));
-      CMPC_HIP(hipMemcpy(p.xu_host.data(), p.xu, sizeof(double) * p.ns, hipMemcpyDeviceToHost));
+      p.xl_host.resize(nr);
+      p.xu_host.resize(nr);
+      CMPC_HIP(hipMemcpy(p.xl_host.data(), p.xl, sizeof(double) * nr, hipMemcpyDeviceToHost));
+      CMPC_HIP(hipMemcpy(p.xu_host.data(), p.xu, sizeof(double) * nr, hipMemcpyDeviceToHost));
     }
-    for (int i = 0; i < p.ns; ++i)
+    for (int i = 0; i < nr; ++i)
       if (x0[i] < p.xl_host[i] || x0[i] > p.xu_host[i]) {
         set_error("x0 violates a state bound");
         return CMPC_ERR_X0_BOUNDS;
       }
   }
-  CMPC_HIP(hipMemcpyAsync(p.x0, x0, sizeof(double) * p.ns,
+  CMPC_HIP(hipMemcpyAsync(p.x0, x0, sizeof(double) * nr,
                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p.stream));
+  if (nr < p.ns)
+    CMPC_HIP(hipMemsetAsync(p.x0 + nr, 0, sizeof(double) * (p.ns - nr), p.stream));
   // device x0: validated on the device; a bad x0 makes the next solve return the error
   if (launch_check_x0(p)) return CMPC_ERR_HIP;
-  if (launch_free_response(p)) return CMPC_ERR_HIP;  // c_t = A^t x0
+  if (launch_free_response(p)) return CMPC_ERR_HIP;  // c_t = A c_{t-1} + w_{t-1}, c_0 = x0
   if (launch_block_diag_weight(p, p.c, p.qc)) return CMPC_ERR_HIP;
   if (launch_gamma_t(p, p.qc, 1, p.h, nullptr)) return CMPC_ERR_HIP;
+  if (p.Sx != nullptr && launch_h_cross(p)) return CMPC_ERR_HIP;  // + S~' c_t on stage t
   if (launch_h0(p)) return CMPC_ERR_HIP;
   if (launch_make_d(p)) return CMPC_ERR_HIP;
   if (!on_device) CMPC_HIP(hipStreamSynchronize(p.stream));  // host x0 buffer may be reused
@@ -673,13 +890,30 @@ int cmpc_get_solution(const cmpc_problem* h, double* u, double* x, int on_device
   }
   Problem& p = *h->p;
   const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  if (u) CMPC_HIP(hipMemcpyAsync(u, p.v, sizeof(double) * p.n, k, p.stream));
-  if (x) {
+  const bool folded = p.ns_real != p.ns || p.feedback;
+  if (!folded) {
+    if (u) CMPC_HIP(hipMemcpyAsync(u, p.v, sizeof(double) * p.n, k, p.stream));
+    if (x) {
+      if (launch_gamma_mv(p, p.v, p.tmpmx, nullptr)) return CMPC_ERR_HIP;
+      hipLaunchKernelGGL(add_vec_kernel, dim3(ceil_div(p.mx, 256)), dim3(256), 0, p.stream, p.c,
+                         p.tmpmx, p.tmpmx, p.mx);
+      CMPC_LAUNCH_CHECK();
+      CMPC_HIP(hipMemcpyAsync(x, p.tmpmx, sizeof(double) * p.mx, k, p.stream));
+    }
+  } else if (u || x) {
+    // the states with the extra stage rows, then the problem's own states and inputs
     if (launch_gamma_mv(p, p.v, p.tmpmx, nullptr)) return CMPC_ERR_HIP;
     hipLaunchKernelGGL(add_vec_kernel, dim3(ceil_div(p.mx, 256)), dim3(256), 0, p.stream, p.c,
                        p.tmpmx, p.tmpmx, p.mx);
     CMPC_LAUNCH_CHECK();
-    CMPC_HIP(hipMemcpyAsync(x, p.tmpmx, sizeof(double) * p.mx, k, p.stream));
+    double* ud = u ? (on_device ? u : p.tmpn) : nullptr;
+    double* xd = x ? (on_device ? x : p.gpv) : nullptr;
+    if (launch_unfold_solution(p, p.tmpmx, ud, xd)) return CMPC_ERR_HIP;
+    if (u && !on_device)
+      CMPC_HIP(hipMemcpyAsync(u, p.tmpn, sizeof(double) * p.n, hipMemcpyDeviceToHost, p.stream));
+    if (x && !on_device)
+      CMPC_HIP(hipMemcpyAsync(x, p.gpv, sizeof(double) * (size_t)p.ns_real * p.N,
+                              hipMemcpyDeviceToHost, p.stream));
   }
   CMPC_HIP(hipStreamSynchronize(p.stream));
   return 0;
@@ -796,7 +1030,7 @@ int cmpc_potrf(double* K, int n, int ld, void* stream, int* info) {
   int* flags = nullptr;  // done, info, status
   double* Wall = nullptr;
   CMPC_HIP(hipMalloc(&flags, 3 * sizeof(int)));
-  if (hipMalloc(&Wall, sizeof(double) * 4096 * (size_t)ceil_div(n, 64)) != hipSuccess) {
+  if (hipMalloc(&Wall, sizeof(double) * wall_doubles(n)) != hipSuccess) {
     hipFree(flags);
     set_error("out of device memory");
     return CMPC_ERR_NOMEM;
@@ -865,9 +1099,9 @@ int cmpc_potrs(const double* L, int n, int ld, double* b, void* stream) {
   }
   hipStream_t s = (hipStream_t)stream;
   double* Wall = nullptr;
-  CMPC_HIP(hipMalloc(&Wall, sizeof(double) * (4096 * (size_t)ceil_div(n, 64) + n)));
+  CMPC_HIP(hipMalloc(&Wall, sizeof(double) * (wall_doubles(n) + n)));
   int rc = launch_tri_inv(s, L, n, ld, Wall);
-  if (!rc) rc = launch_potrs(s, L, n, ld, Wall, b, b, Wall + 4096 * (size_t)ceil_div(n, 64), nullptr);
+  if (!rc) rc = launch_potrs(s, L, n, ld, Wall, b, b, Wall + wall_doubles(n), nullptr);
   if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = CMPC_ERR_HIP;
   hipFree(Wall);
   return rc;

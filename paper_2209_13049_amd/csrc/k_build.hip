@@ -212,7 +212,8 @@ int launch_h0(Problem& p) {
 // state in LDS and steps through the horizon.
 __global__ __launch_bounds__(1024) void free_response_csr_kernel(
     const int* __restrict__ rowptr, const int* __restrict__ col, const double* __restrict__ val,
-    const double* __restrict__ x0, double* __restrict__ c, int ns, int N) {
+    const double* __restrict__ x0, double* __restrict__ c, int ns, int N,
+    const double* __restrict__ w) {
   extern __shared__ double buf[];  // 2 ns
   double* cur = buf;
   double* nxt = buf + ns;
@@ -222,6 +223,7 @@ __global__ __launch_bounds__(1024) void free_response_csr_kernel(
     for (int i = threadIdx.x; i < ns; i += blockDim.x) {
       double acc = 0.0;
       for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) acc = fma(val[e], cur[col[e]], acc);
+      if (w != nullptr) acc += w[(long long)(t - 1) * ns + i];
       nxt[i] = acc;
       c[(long long)(t - 1) * ns + i] = acc;
     }
@@ -232,19 +234,29 @@ __global__ __launch_bounds__(1024) void free_response_csr_kernel(
   }
 }
 
+__global__ void add_into_kernel(double* __restrict__ y, const double* __restrict__ w, int len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) y[i] += w[i];
+}
+
+// c_t = A c_{t-1} + w_{t-1} (w = NULL: 0), c_0 = x0, t = 1..N (eqn. (dyn) with v = 0).
 int launch_free_response(Problem& p) {
   if (p.a_rowptr != nullptr) {
     hipLaunchKernelGGL(free_response_csr_kernel, dim3(1), dim3(1024),
                        sizeof(double) * 2 * (size_t)p.ns, p.stream, p.a_rowptr, p.a_col, p.a_val,
-                       p.x0, p.c, p.ns, p.N);
+                       p.x0, p.c, p.ns, p.N, (const double*)p.wdist);
     CMPC_LAUNCH_CHECK();
     return 0;
   }
-  if (launch_gemv(p.stream, p.A, p.x0, p.c, p.ns, p.ns)) return CMPC_ERR_HIP;
-  for (int t = 2; t <= p.N; ++t)
-    if (launch_gemv(p.stream, p.A, p.c + (size_t)(t - 2) * p.ns, p.c + (size_t)(t - 1) * p.ns,
-                    p.ns, p.ns))
-      return CMPC_ERR_HIP;
+  for (int t = 1; t <= p.N; ++t) {
+    double* ct = p.c + (size_t)(t - 1) * p.ns;
+    if (launch_gemv(p.stream, p.A, t == 1 ? p.x0 : ct - p.ns, ct, p.ns, p.ns)) return CMPC_ERR_HIP;
+    if (p.wdist != nullptr) {
+      hipLaunchKernelGGL(add_into_kernel, dim3(ceil_div(p.ns, 256)), dim3(256), 0, p.stream, ct,
+                         p.wdist + (size_t)(t - 1) * p.ns, p.ns);
+      CMPC_LAUNCH_CHECK();
+    }
+  }
   return 0;
 }
 
@@ -265,8 +277,98 @@ __global__ void check_x0_kernel(const double* __restrict__ x0, const double* __r
 }
 
 int launch_check_x0(Problem& p) {
-  hipLaunchKernelGGL(check_x0_kernel, dim3(1), dim3(256), 0, p.stream, p.x0, p.xl, p.xu, p.ns,
-                     p.st);
+  hipLaunchKernelGGL(check_x0_kernel, dim3(1), dim3(256), 0, p.stream, p.x0, p.xl, p.xu,
+                     p.ns_real, p.st);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// ---- the cross weight S~ of the stage cost (general data, see fold_general in capi.hip):
+// 1/2 x_t'Q~x_t + x_t'S~ v_t + 1/2 v_t'R v_t with x_t = c_t + Gamma_t v adds
+// H(j, t) += G_{t-1-j}' S~ (and the transposed block at (t, j)) for j < t <= N-1, and
+// h(stage t) += S~' c_t for t = 0..N-1 (c_0 = x0).
+__global__ void cross_blocks_kernel(const double* __restrict__ G, const double* __restrict__ S,
+                                    double* __restrict__ C, int ns, int nu, int N) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // (m, a, b)
+  if (e >= (long long)N * nu * nu) return;
+  const int m = (int)(e / ((long long)nu * nu));
+  const int ab = (int)(e - (long long)m * nu * nu), a = ab / nu, b = ab - a * nu;
+  const double* Gm = G + (long long)m * ns * nu;
+  double acc = 0.0;
+  for (int i = 0; i < ns; ++i) acc = fma(Gm[(long long)i * nu + a], S[(long long)i * nu + b], acc);
+  C[e] = acc;  // C_m = G_m' S~ (nu x nu)
+}
+
+__global__ void add_cross_kernel(const double* __restrict__ C, double* __restrict__ H, int nu,
+                                 int N) {
+  const int n = nu * N;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * n) return;
+  const int r = (int)(e / n), c = (int)(e - (long long)r * n);
+  const int j = r / nu, t = c / nu, a = r - j * nu, b = c - t * nu;
+  if (j < t && t <= N - 1)
+    H[e] += C[((long long)(t - 1 - j) * nu + a) * nu + b];
+  else if (t < j && j <= N - 1)
+    H[e] += C[((long long)(j - 1 - t) * nu + b) * nu + a];
+}
+
+int launch_cross_hessian(Problem& p, const double* S) {
+  double* C = nullptr;
+  CMPC_HIP(hipMalloc(&C, sizeof(double) * (size_t)p.N * p.nu * p.nu));
+  hipLaunchKernelGGL(cross_blocks_kernel, dim3(ceil_div((long long)p.N * p.nu * p.nu, 256)),
+                     dim3(256), 0, p.stream, p.G, S, C, p.ns, p.nu, p.N);
+  hipLaunchKernelGGL(add_cross_kernel, dim3(ceil_div((long long)p.n * p.n, 256)), dim3(256), 0,
+                     p.stream, C, p.H, p.nu, p.N);
+  const hipError_t e = hipGetLastError();
+  hipStreamSynchronize(p.stream);
+  hipFree(C);
+  if (e != hipSuccess) {
+    set_error(std::string("cross-weight Hessian: ") + hipGetErrorString(e));
+    return CMPC_ERR_HIP;
+  }
+  return 0;
+}
+
+__global__ void h_cross_kernel(const double* __restrict__ S, const double* __restrict__ x0,
+                               const double* __restrict__ c, double* __restrict__ h, int ns,
+                               int nu, int N) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;  // (t, b)
+  if (e >= nu * N) return;
+  const int t = e / nu, b = e - t * nu;
+  const double* ct = t == 0 ? x0 : c + (long long)(t - 1) * ns;
+  double acc = 0.0;
+  for (int i = 0; i < ns; ++i) acc = fma(S[(long long)i * nu + b], ct[i], acc);
+  h[e] += acc;
+}
+
+int launch_h_cross(Problem& p) {
+  hipLaunchKernelGGL(h_cross_kernel, dim3(ceil_div(p.n, 256)), dim3(256), 0, p.stream, p.Sx,
+                     p.x0, p.c, p.h, p.ns, p.nu, p.N);
+  CMPC_LAUNCH_CHECK();
+  return 0;
+}
+
+// The problem's own states and inputs from xa = c + Gamma v (states x_1..x_N with the extra
+// stage rows): x_t = the first ns_real components of xa_t; with a feedback the inputs are the
+// first nu extra components of xa_{t+1} (they hold K x_t + v_t), else u = v.
+__global__ void unfold_solution_kernel(const double* __restrict__ xa, const double* __restrict__ v,
+                                       double* __restrict__ u, double* __restrict__ x, int ns,
+                                       int ns_real, int nu, int N, int feedback) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x != nullptr && e < (long long)ns_real * N) {
+    const int t = (int)(e / ns_real), i = (int)(e - (long long)t * ns_real);
+    x[e] = xa[(long long)t * ns + i];
+  }
+  if (u != nullptr && e < (long long)nu * N) {
+    const int t = (int)(e / nu), k = (int)(e - (long long)t * nu);
+    u[e] = feedback ? xa[(long long)t * ns + ns_real + k] : v[e];
+  }
+}
+
+int launch_unfold_solution(Problem& p, const double* xa, double* u, double* x) {
+  const long long len = std::max<long long>((long long)p.ns_real * p.N, p.n);
+  hipLaunchKernelGGL(unfold_solution_kernel, dim3(ceil_div(len, 256)), dim3(256), 0, p.stream,
+                     xa, p.v, u, x, p.ns, p.ns_real, p.nu, p.N, p.feedback ? 1 : 0);
   CMPC_LAUNCH_CHECK();
   return 0;
 }

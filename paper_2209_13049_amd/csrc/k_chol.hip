@@ -10,6 +10,11 @@
 //                 j > k  : A_ij -= X_i X_j'  (also MFMA);
 //                 (k+1, k+1) additionally factors its updated tile at once and forms W_{k+1},
 //                 so the next launch finds the next pivot block ready (look-ahead).
+// Where a diagonal tile is ill-conditioned (max|L_kk| max|W_k| above kRefineCond, figures
+// stored beside W_k by the workgroup that formed it) every panel product of that tile column
+// takes one step of iterative refinement against L_kk (refine_panel), so that the panel is as
+// accurate as a triangular solve; the redundant copies of a panel in different workgroups stay
+// identical.
 // A diagonal tile is factored by 4 wavefronts (wavefront w owns columns 16w..16w+15, lane
 // = row) with one barrier per column, and inverted by forward substitution with 4 lanes per
 // column (no barriers).  The inverses W_k are kept (nt x 64 x 64) so that the triangular
@@ -78,19 +83,16 @@ __device__ inline void load_w_tiles(const double* __restrict__ Wk, Tile& Wt,
   }
 }
 
-// acc (per wavefront: its 32 x 32 quadrant, 2 x 2 blocks of 16 x 16) = A B'
-__device__ inline void mma_abt(const Tile& A, const Tile& B, d4 (&acc)[2][2], int wr, int wc,
-                               int li, int lk) {
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0, 0, 0, 0};
+// acc (per wavefront: its 32 x 32 quadrant, 2 x 2 blocks of 16 x 16) += A B' (neg: -= A B')
+__device__ inline void mma_abt_add(const Tile& A, const Tile& B, d4 (&acc)[2][2], int wr, int wc,
+                                   int li, int lk, bool neg = false) {
   for (int ks = 0; ks < 16; ++ks) {
     double xa[2], xb[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       xa[q] = A[32 * wr + 16 * q + li][4 * ks + lk];
       xb[q] = B[32 * wc + 16 * q + li][4 * ks + lk];
+      if (neg) xa[q] = -xa[q];
     }
 #pragma unroll
     for (int ib = 0; ib < 2; ++ib)
@@ -98,6 +100,16 @@ __device__ inline void mma_abt(const Tile& A, const Tile& B, d4 (&acc)[2][2], in
       for (int jb = 0; jb < 2; ++jb)
         acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ib], xb[jb], acc[ib][jb], 0, 0, 0);
   }
+}
+
+// acc = A B'
+__device__ inline void mma_abt(const Tile& A, const Tile& B, d4 (&acc)[2][2], int wr, int wc,
+                               int li, int lk) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0, 0, 0, 0};
+  mma_abt_add(A, B, acc, wr, wc, li, lk);
 }
 
 // Store a quadrant accumulator into an LDS tile (row = 32 wr + 16 ib + lk + 4 v).
@@ -352,6 +364,95 @@ __device__ inline void load_w(const double* __restrict__ Wk, Tile& W) {
   }
 }
 
+// A factor tile (lower triangle of K at (r0, r0); the rest of the tile as 0) into T.
+__device__ inline void load_lower_tile(const double* __restrict__ K, int ld, int n, int r0,
+                                       Tile& T) {
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int i = e >> 6, j = e & 63;
+    v[q] = (j <= i && r0 + i < n) ? K[(long long)(r0 + i) * ld + r0 + j] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    T[e >> 6][e & 63] = v[q];
+  }
+}
+
+// Condition figures of a factored diagonal tile (factor T, inverse W, both in LDS): wavefront
+// w stores the largest |L_ij| and |W_ij| among its threads' entries in slot[2w], slot[2w+1].
+// A panel formed with the explicit inverse, A W', has a relative error up to about
+// 64 eps max|L| max|W|; a triangular solve's error does not grow with that product.
+__device__ inline void write_cond(const Tile& T, const Tile& W, double* __restrict__ slot) {
+  double ml = 0.0, mw = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int i = e >> 6, j = e & 63;
+    ml = fmax(ml, fabs(T[i][j]));
+    if ((j >> 4) <= (i >> 4)) mw = fmax(mw, fabs(W[i][j]));  // blocks above are not written
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    ml = fmax(ml, __shfl_xor(ml, off, 64));
+    mw = fmax(mw, __shfl_xor(mw, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    slot[2 * (threadIdx.x >> 6)] = ml;
+    slot[2 * (threadIdx.x >> 6) + 1] = mw;
+  }
+}
+
+// Panels of a tile column whose max|L| max|W| exceeds this are refined (refine_panel): below
+// it the inverse-based panel loses at most about three digits more than a triangular solve.
+constexpr double kRefineCond = 1e3;
+
+__device__ inline bool panel_needs_refine(const double* __restrict__ slot) {
+  const double ml = fmax(fmax(slot[0], slot[2]), fmax(slot[4], slot[6]));
+  const double mw = fmax(fmax(slot[1], slot[3]), fmax(slot[5], slot[7]));
+  return ml * mw > kRefineCond;
+}
+
+// One step of iterative refinement of the panel X = A W' of tile column k0 / 64 (W = L_kk^-1,
+// L_kk the factor tile at (k0, k0) of K): X <- X + (A - X L_kk') W'.  On entry acc holds X,
+// the product of Xa (= A) with Wt (= W), and likewise accb for Xb when two is set; on exit
+// acc (accb) hold the refined panel, Wt holds W again and Xa, Xb hold scratch.  The step
+// brings the panel's error down to that of a triangular solve (Higham, Accuracy and
+// Stability of Numerical Algorithms, Ch. 12: one step of refinement in the working
+// precision makes a solver with a small enough forward error backward stable).
+__device__ __forceinline__ void refine_panel(const double* __restrict__ K, int ld, int n, int k0,
+                             const double* __restrict__ Wk, Tile& Wt, Tile& Xa,
+                             d4 (&acc)[2][2], Tile& Xb, d4 (&accb)[2][2], bool two, int wr,
+                             int wc, int li, int lk) {
+  d4 r[2][2], rb[2][2];  // A at this thread's accumulator positions, then the residual
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 32 * wr + 16 * ib + lk + 4 * v, j = 32 * wc + 16 * jb + li;
+        r[ib][jb][v] = Xa[i][j];
+        rb[ib][jb][v] = two ? Xb[i][j] : 0.0;
+      }
+  __syncthreads();  // the products that read Xa, Xb and Wt are complete
+  store_acc(Xa, acc, wr, wc, li, lk);
+  if (two) store_acc(Xb, accb, wr, wc, li, lk);
+  load_lower_tile(K, ld, n, k0, Wt);
+  __syncthreads();
+  mma_abt_add(Xa, Wt, r, wr, wc, li, lk, true);  // R = A - X L_kk'
+  if (two) mma_abt_add(Xb, Wt, rb, wr, wc, li, lk, true);
+  __syncthreads();
+  store_acc(Xa, r, wr, wc, li, lk);
+  if (two) store_acc(Xb, rb, wr, wc, li, lk);
+  load_w(Wk, Wt);
+  __syncthreads();
+  mma_abt_add(Xa, Wt, acc, wr, wc, li, lk);  // X += R W'
+  if (two) mma_abt_add(Xb, Wt, accb, wr, wc, li, lk);
+}
+
 // Pivot failure: a low-precision K (mixed modes) is formed again one precision level higher
 // (done = 2 skips the rest of the iteration); otherwise the breakdown is reported.
 __device__ inline void chol_fail(int col, int* done, int* info, int* status, int* lowflag) {
@@ -380,6 +481,7 @@ __device__ __forceinline__ void chol_first_body(int bid, double* __restrict__ K,
     return;
   }
   write_w(Wall, W);
+  write_cond(T, W, Wall + 4096 * (long long)((n + 63) >> 6));
 }
 
 __global__ __launch_bounds__(256) void chol_first_kernel(double* __restrict__ K, int ld, int n,
@@ -389,15 +491,19 @@ __global__ __launch_bounds__(256) void chol_first_kernel(double* __restrict__ K,
 }
 
 // Forward substitution for row block j on one 256-thread workgroup (4 lanes per row):
-// y_j = W_j (S b_j - sum_{m<j} L_jm y_m), the y_m of earlier blocks read from y.
+// y_j = W_j (S b_j - sum_{m<j} L_jm y_m), the y_m of earlier blocks read from y.  Where the
+// diagonal tile is ill-conditioned (its condition figures, as for the panels) the block takes
+// one step of refinement, y_j += W_j (r - L_jj y_j), so that its error is that of a
+// substitution with L_jj.
 __device__ __forceinline__ void fwd_block_body(int j, const double* __restrict__ L, int ld, int n,
                                                const double* __restrict__ Wall,
                                                const double* __restrict__ b,
                                                const double* __restrict__ eq,
                                                double* __restrict__ y) {
-  __shared__ double rs[64];
+  __shared__ double rs[64], yj[64];
   const int t = threadIdx.x, i = t >> 2, g = t & 3;
   const int j0 = 64 * j, rows = min(64, n - j0);
+  const bool refine = panel_needs_refine(Wall + 4096 * (long long)((n + 63) >> 6) + 8 * j);
   double acc = 0.0;
   if (i < rows) {
     const double* row = L + (long long)(j0 + i) * ld;
@@ -421,6 +527,25 @@ __device__ __forceinline__ void fwd_block_body(int j, const double* __restrict__
   for (int q = g; q < 64; q += 4) v = fma(W[q], rs[q], v);
   v += dpp_f64<0xB1>(v);
   v += dpp_f64<0x4E>(v);
+  if (refine) {  // uniform
+    if (g == 0) yj[i] = v;
+    __syncthreads();
+    double e = 0.0;  // (L_jj y_j)_i, lower triangle
+    if (i < rows) {
+      const double* row = L + (long long)(j0 + i) * ld + j0;
+      for (int q = g; q <= i; q += 4) e = fma(row[q], yj[q], e);
+    }
+    e += dpp_f64<0xB1>(e);
+    e += dpp_f64<0x4E>(e);
+    if (g == 0) rs[i] = i < rows ? rs[i] - e : 0.0;  // every read of rs preceded the barrier
+    __syncthreads();
+    double d = 0.0;
+#pragma unroll
+    for (int q = g; q < 64; q += 4) d = fma(W[q], rs[q], d);
+    d += dpp_f64<0xB1>(d);
+    d += dpp_f64<0x4E>(d);
+    v += d;
+  }
   if (g == 0 && i < rows) y[j0 + i] = v;
 }
 
@@ -448,6 +573,7 @@ __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, 
   }
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
   const int wr = wave >> 1, wc = wave & 1;
+  double* cond = Wall + 4096 * (long long)nt;  // condition figures, 8 per tile
   int b = bid;
   d4 acc[2][2];
   const int npanel = k >= 1 ? nt - k : 0;
@@ -457,6 +583,9 @@ __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, 
     load_tile(K, ld, n, r0, c0, Xi);
     __syncthreads();
     mma_abt(Xi, Wt, acc, wr, wc, li, lk);
+    if (panel_needs_refine(cond + 8 * (k - 1)))  // uniform: one value for the workgroup
+      refine_panel(K, ld, n, c0, Wall + (long long)(k - 1) * 4096, Wt, Xi, acc, Xj, acc, false,
+                   wr, wc, li, lk);
     __syncthreads();
     store_acc(Xi, acc, wr, wc, li, lk);
     __syncthreads();
@@ -481,6 +610,9 @@ __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, 
   mma_abt(Xi, Wt, acc, wr, wc, li, lk);  // X_i = A_ik W_k'
   d4 accj[2][2];
   if (!diag) mma_abt(Xj, Wt, accj, wr, wc, li, lk);  // X_j
+  if (panel_needs_refine(cond + 8 * k))  // the same decision as the panel's own launch
+    refine_panel(K, ld, n, k0, Wall + (long long)k * 4096, Wt, Xi, acc, Xj, accj, !diag, wr, wc,
+                 li, lk);
   __syncthreads();
   store_acc(Xi, acc, wr, wc, li, lk);
   if (!diag) store_acc(Xj, accj, wr, wc, li, lk);
@@ -527,6 +659,7 @@ __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, 
     return;
   }
   write_w(Wall + (long long)(k + 1) * 4096, Xi);
+  write_cond(Xj, Xi, cond + 8 * (k + 1));
 }
 
 __global__ __launch_bounds__(256) void chol_step_kernel(double* __restrict__ K, int ld, int n,
@@ -558,7 +691,8 @@ int launch_potrf(hipStream_t s, double* K, int n, int ld, double* Wall, int* don
   return 0;
 }
 
-// Inverses of the diagonal tiles of an existing factor (for a standalone solve).
+// Inverses of the diagonal tiles of an existing factor and their condition figures (for a
+// standalone solve; one workgroup per tile, grid = ceil(n / 64)).
 __global__ __launch_bounds__(256) void tri_inv_kernel(const double* __restrict__ L, int ld, int n,
                                                       double* __restrict__ Wall) {
   __shared__ Tile T, W;
@@ -577,6 +711,7 @@ __global__ __launch_bounds__(256) void tri_inv_kernel(const double* __restrict__
   __syncthreads();
   inv64(T, W, rdiag);
   write_w(Wall + (long long)blockIdx.x * 4096, W);
+  write_cond(T, W, Wall + 4096 * (long long)gridDim.x + 8 * blockIdx.x);
 }
 
 int launch_tri_inv(hipStream_t s, const double* L, int n, int ld, double* Wall) {
@@ -610,18 +745,53 @@ __device__ inline void tile_mv64(const double* __restrict__ M, const double* u, 
   if (p == 0) v[r] = acc;
 }
 
+// v = L_kk^-1 u (trans: L_kk^-T u) for diagonal block k (rows k0 .. k0 + 63 of L, the part
+// past n as identity) with its inverse W_k: v = W u, and where the tile is ill-conditioned one
+// step of refinement v += W (u - L_kk v).  u, v, e (scratch) in LDS; ends with a barrier.
+__device__ inline void tile_solve64(const double* __restrict__ Wk, const double* __restrict__ L,
+                                    int ld, int n, int k0, bool refine, double* u, double* v,
+                                    double* e, bool trans) {
+  tile_mv64(Wk, u, v, trans);
+  __syncthreads();
+  if (!refine) return;
+  const int r = threadIdx.x >> 2, p = threadIdx.x & 3;
+  double acc = 0.0;  // (L_kk v)_r or (L_kk' v)_r over the valid rows
+  if (k0 + r < n) {
+    if (!trans) {
+      for (int m = p; m <= r; m += 4) acc = fma(L[(long long)(k0 + r) * ld + k0 + m], v[m], acc);
+    } else {
+      for (int m = r + p; m < 64 && k0 + m < n; m += 4)
+        acc = fma(L[(long long)(k0 + m) * ld + k0 + r], v[m], acc);
+    }
+  }
+  acc += __shfl_xor(acc, 1, 64);
+  acc += __shfl_xor(acc, 2, 64);
+  if (p == 0) e[r] = k0 + r < n ? u[r] - acc : 0.0;
+  __syncthreads();
+  double d = 0.0;
+  if (!trans) {
+    for (int m = p; m < 64; m += 4) d = fma(Wk[r * 64 + m], e[m], d);
+  } else {
+    for (int m = p; m < 64; m += 4) d = fma(Wk[m * 64 + r], e[m], d);
+  }
+  d += __shfl_xor(d, 1, 64);
+  d += __shfl_xor(d, 2, 64);
+  if (p == 0) v[r] += d;
+  __syncthreads();
+}
+
 __device__ __forceinline__ void trsv_fwd_step_body(int bid, const double* __restrict__ L, int ld,
                                                            int n, const double* __restrict__ Wall,
                                                            double* __restrict__ b,
                                                            double* __restrict__ y, int k,
                                                            const int* __restrict__ done) {
-  __shared__ double bk[64], yk[64];
+  __shared__ double bk[64], yk[64], ek[64];
   if (done != nullptr && *done) return;
   const int k0 = 64 * k, t = threadIdx.x;
+  const bool refine = panel_needs_refine(Wall + 4096 * (long long)((n + 63) >> 6) + 8 * k);
   if (t < 64) bk[t] = (k0 + t < n) ? b[k0 + t] : 0.0;
   __syncthreads();
-  tile_mv64(Wall + (long long)k * 4096, bk, yk, false);
-  __syncthreads();
+  tile_solve64(Wall + (long long)k * 4096, L, ld, n, k0, refine, bk, yk, ek, false);
   if (bid == 0 && t < 64 && k0 + t < n) y[k0 + t] = yk[t];
   const int i0 = k0 + 64 * (1 + (int)bid);
   if (i0 >= n) return;
@@ -650,13 +820,13 @@ __device__ __forceinline__ void trsv_bwd_step_body(int bid, const double* __rest
                                                            double* __restrict__ y,
                                                            double* __restrict__ x, int k,
                                                            const int* __restrict__ done) {
-  __shared__ double ykk[64], xk[64];
+  __shared__ double ykk[64], xk[64], ek[64];
   if (done != nullptr && *done) return;
   const int k0 = 64 * k, t = threadIdx.x;
+  const bool refine = panel_needs_refine(Wall + 4096 * (long long)((n + 63) >> 6) + 8 * k);
   if (t < 64) ykk[t] = (k0 + t < n) ? y[k0 + t] : 0.0;
   __syncthreads();
-  tile_mv64(Wall + (long long)k * 4096, ykk, xk, true);
-  __syncthreads();
+  tile_solve64(Wall + (long long)k * 4096, L, ld, n, k0, refine, ykk, xk, ek, true);
   if (bid == 0 && t < 64 && k0 + t < n) x[k0 + t] = xk[t];
   const int j = bid;
   if (j >= k) return;
@@ -735,26 +905,114 @@ int launch_equilibrate(hipStream_t s, double* K, int n, int ld, double* eq, cons
   return 0;
 }
 
+// Bit k set: diagonal tile k is ill-conditioned (its condition figures exceed kRefineCond), and
+// the substitutions with it take one step of refinement.  nt <= 64.  Wavefront 0 forms the
+// mask and lane 0 stores it; it is read after the caller's next barrier.
+__device__ inline void refine_mask(const double* __restrict__ Wall, int nt,
+                                   unsigned long long* mask) {
+  if (threadIdx.x < 64) {
+    const int k = threadIdx.x;
+    const bool f = k < nt && panel_needs_refine(Wall + 4096 * (long long)nt + 8 * k);
+    const unsigned long long m = __ballot(f);
+    if (k == 0) *mask = m;
+  }
+}
+
+// The 16 lanes of each DPP row get the sum of the row's values.
+__device__ inline double rowsum16(double x) {
+  x += dpp_f64<0xB1>(x);   // quad_perm: lane ^ 1
+  x += dpp_f64<0x4E>(x);   // quad_perm: lane ^ 2
+  x += dpp_f64<0x124>(x);  // row_ror:4
+  x += dpp_f64<0x128>(x);  // row_ror:8
+  return x;
+}
+
+// One step of refinement of the forward block y_k = W_k r (r in rs, y_k in ys[k0 ..]) on 1024
+// threads, row i of the block on the 16 lanes g of a DPP row: y_k += W_k (r - L_kk y_k); wrow:
+// the lane's entries (i, g + 16 q) of W_k.  Begins and ends after a barrier.
+__device__ inline void refine_fwd_block(const double* __restrict__ L, int ld, int n, int k0,
+                                        const double (&wrow)[4], double* ys, const double* rs,
+                                        double* es) {
+  const int t = threadIdx.x, i = t >> 4, g = t & 15;
+  const bool valid = k0 + i < n;
+  double a = 0.0;
+  if (valid) {
+    const double* row = L + (long long)(k0 + i) * ld + k0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (g + 16 * q <= i) a = fma(row[g + 16 * q], ys[k0 + g + 16 * q], a);
+  }
+  a = rowsum16(a);
+  if (g == 0) es[i] = valid ? rs[i] - a : 0.0;
+  __syncthreads();
+  double d = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) d = fma(wrow[q], es[g + 16 * q], d);
+  d = rowsum16(d);
+  if (g == 0 && valid) ys[k0 + i] += d;
+  __syncthreads();
+}
+
+// The same for the backward block x_k = W_k' r, column i of the block on lane i of wavefront
+// g: x_k += W_k' (r - L_kk' x_k); wcol: the lane's entries (g + 16 q, i) of W_k.
+__device__ inline void refine_bwd_block(const double* __restrict__ L, int ld, int n, int k0,
+                                        const double (&wcol)[4], double* ys, const double* rs,
+                                        double* es, double (*red)[65]) {
+  const int t = threadIdx.x, i = t & 63, g = t >> 6;
+  double a = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int m = g + 16 * q;
+    if (m >= i && k0 + m < n) a = fma(L[(long long)(k0 + m) * ld + k0 + i], ys[k0 + m], a);
+  }
+  red[g][i] = a;
+  __syncthreads();
+  if (g == 0) {
+    double sum = 0.0;
+    for (int q = 0; q < 16; ++q) sum += red[q][i];
+    es[i] = k0 + i < n ? rs[i] - sum : 0.0;
+  }
+  __syncthreads();
+  double d = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) d = fma(wcol[q], es[g + 16 * q], d);
+  red[g][i] = d;
+  __syncthreads();
+  if (g == 0 && k0 + i < n) {
+    double sum = 0.0;
+    for (int q = 0; q < 16; ++q) sum += red[q][i];
+    ys[k0 + i] += sum;
+  }
+  __syncthreads();
+}
+
+// The one-workgroup solves' start: ys <- S b (zero past n; the fused forward pass's y below
+// block kf) and the refinement mask (no barrier: the caller's next one publishes both).
+__device__ inline void potrs_prologue(const double* __restrict__ Wall, const double* __restrict__ b,
+                                      const double* __restrict__ eq,
+                                      const double* __restrict__ yf, int n, int nt, int kf,
+                                      double* ys, unsigned long long* mask) {
+  refine_mask(Wall, nt, mask);
+  for (int i = threadIdx.x; i < 64 * nt; i += 1024)
+    ys[i] = i < 64 * kf ? yf[i] : (i < n ? (eq ? eq[i] * b[i] : b[i]) : 0.0);
+}
+
 // Both triangular solves in one workgroup of 1024 threads (16 wavefronts), the vector held in
-// LDS: forward, for each 64-row block k, r = b_k - L_k,<k y_<k (16 lanes per row, a row
-// segment of 16 consecutive columns per load) and y_k = W_k r; backward, for k from the last
-// block down, r = y_k - L_>k,k' x_>k (a wavefront per 16th of the rows, 64 consecutive
-// columns per load) and x_k = W_k' r.  Partial sums are reduced in a fixed order.  One launch
-// replaces 2 ceil(n/64) + 2 launches of the block-step kernels.  eq != NULL: x = S (..)^-1 S b.
+// LDS (ys, filled by the caller; blocks below kf already hold y): forward, for each 64-row
+// block k, r = b_k - L_k,<k y_<k (16 lanes per row, a row segment of 16 consecutive columns per
+// load) and y_k = W_k r; backward, for k from the last block down, r = y_k - L_>k,k' x_>k (a
+// wavefront per 16th of the rows, 64 consecutive columns per load) and x_k = W_k' r.  Blocks
+// whose bit is set in refm take one step of refinement after each product.  Partial sums are
+// reduced in a fixed order.  One launch replaces 2 ceil(n/64) + 2 launches of the block-step
+// kernels.  eq != NULL: x = S (..)^-1 S b.
 __device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, int ld, int n,
                                                   const double* __restrict__ Wall,
-                                                  const double* __restrict__ b,
                                                   double* __restrict__ x,
-                                                  const double* __restrict__ eq,
-                                                  const int* __restrict__ gate, double* ys,
-                                                  double* rs, double (*red)[65],
-                                                  const double* __restrict__ yf) {
-  if (gate != nullptr && *gate) return;
+                                                  const double* __restrict__ eq, double* ys,
+                                                  double* rs, double (*red)[65], int kf,
+                                                  unsigned long long refm, double* es) {
   const int t = threadIdx.x;
   const int nt = (n + 63) >> 6;
-  const int kf = yf ? max(0, nt - 2) : 0;  // blocks whose y the fused forward pass computed
-  for (int i = t; i < n; i += 1024) ys[i] = i < 64 * kf ? yf[i] : (eq ? eq[i] * b[i] : b[i]);
-  __syncthreads();
   // ---- forward: L y = b
   {
     const int i = t >> 4, g = t & 15;  // row of the block, column phase
@@ -793,6 +1051,7 @@ __device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, 
       v += __shfl_xor(v, 8, 64);
       if (g == 0 && i < rows) ys[k0 + i] = v;
       __syncthreads();
+      if ((refm >> k) & 1ull) refine_fwd_block(L, ld, n, k0, wv, ys, rs, es);
     }
   }
   // ---- backward: L' x = y (x overwrites y block by block)
@@ -836,18 +1095,10 @@ __device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, 
         ys[k0 + i] = sum;
       }
       __syncthreads();
+      if ((refm >> k) & 1ull) refine_bwd_block(L, ld, n, k0, wv, ys, rs, es, red);
     }
   }
   for (int i = t; i < n; i += 1024) x[i] = eq ? eq[i] * ys[i] : ys[i];
-}
-
-// The 16 lanes of each DPP row get the sum of the row's values.
-__device__ inline double rowsum16(double x) {
-  x += dpp_f64<0xB1>(x);   // quad_perm: lane ^ 1
-  x += dpp_f64<0x4E>(x);   // quad_perm: lane ^ 2
-  x += dpp_f64<0x124>(x);  // row_ror:4
-  x += dpp_f64<0x128>(x);  // row_ror:8
-  return x;
 }
 
 // The same two substitutions for n <= 64 NT with NT <= 8 block steps, unrolled so that the
@@ -860,23 +1111,25 @@ __device__ __forceinline__ void potrs_pipe_body(const double* __restrict__ L, in
                                                 const double* __restrict__ Wall,
                                                 const double* __restrict__ b,
                                                 double* __restrict__ x,
-                                                const double* __restrict__ eq,
-                                                const int* __restrict__ gate, double* ys,
+                                                const double* __restrict__ eq, double* ys,
                                                 double* rs, double (*red)[65],
-                                                const double* __restrict__ yf) {
-  if (gate != nullptr && *gate) return;
+                                                const double* __restrict__ yf, double* es,
+                                                unsigned long long* mask) {
   const int t = threadIdx.x;
   const int kf = yf ? (NT > 2 ? NT - 2 : 0) : 0;  // blocks done by the fused forward pass
-  for (int i = t; i < 64 * NT; i += 1024)
-    ys[i] = i < 64 * kf ? yf[i] : (i < n ? (eq ? eq[i] * b[i] : b[i]) : 0.0);
+  potrs_prologue(Wall, b, eq, yf, n, NT, kf, ys, mask);
   double lr[4 * NT];
   double wv[4];
   {  // ---- forward: L y = b, row i of block k on 16 lanes (a DPP row), column phase g; with
      // yf only the blocks from kf on (their loads still issued one step ahead)
     const int i = t >> 4, g = t & 15;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) wv[q] = Wall[i * 64 + g + 16 * q];
+    for (int q = 0; q < 4; ++q) wv[q] = Wall[(long long)kf * 4096 + i * 64 + g + 16 * q];
     __syncthreads();
+    if (*mask != 0ull) {  // a tile to refine: the looped form (uniform)
+      potrs_single_body(L, ld, n, Wall, x, eq, ys, rs, red, kf, *mask, es);
+      return;
+    }
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
       const int k0 = 64 * k;
@@ -955,7 +1208,8 @@ __device__ __forceinline__ void potrs_pipe_body(const double* __restrict__ L, in
   for (int i = t; i < n; i += 1024) x[i] = eq ? eq[i] * ys[i] : ys[i];
 }
 
-// One workgroup solves: the pipelined form up to 8 block steps, the looped form beyond.
+// One workgroup solves: the pipelined form up to 8 block steps, the looped form beyond (and
+// wherever a diagonal tile needs refinement).
 __device__ __forceinline__ void potrs_one_body(const double* __restrict__ L, int ld, int n,
                                                const double* __restrict__ Wall,
                                                const double* __restrict__ b,
@@ -964,18 +1218,25 @@ __device__ __forceinline__ void potrs_one_body(const double* __restrict__ L, int
                                                const int* __restrict__ gate,
                                                const double* __restrict__ yf) {
   extern __shared__ double ys[];  // 64 ceil(n / 64)
-  __shared__ double rs[64];
+  __shared__ double rs[64], es[64];
   __shared__ double red[16][65];
+  __shared__ unsigned long long mask;
+  if (gate != nullptr && *gate) return;
   switch ((n + 63) >> 6) {
-    case 1: potrs_pipe_body<1>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
-    case 2: potrs_pipe_body<2>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
-    case 3: potrs_pipe_body<3>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
-    case 4: potrs_pipe_body<4>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
-    case 5: potrs_pipe_body<5>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
-    case 6: potrs_pipe_body<6>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
-    case 7: potrs_pipe_body<7>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
-    case 8: potrs_pipe_body<8>(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
-    default: potrs_single_body(L, ld, n, Wall, b, x, eq, gate, ys, rs, red, yf); break;
+    case 1: potrs_pipe_body<1>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
+    case 2: potrs_pipe_body<2>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
+    case 3: potrs_pipe_body<3>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
+    case 4: potrs_pipe_body<4>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
+    case 5: potrs_pipe_body<5>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
+    case 6: potrs_pipe_body<6>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
+    case 7: potrs_pipe_body<7>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
+    case 8: potrs_pipe_body<8>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
+    default: {
+      const int nt = (n + 63) >> 6, kf = yf ? nt - 2 : 0;
+      potrs_prologue(Wall, b, eq, yf, n, nt, kf, ys, &mask);
+      __syncthreads();
+      potrs_single_body(L, ld, n, Wall, x, eq, ys, rs, red, kf, mask, es);
+    }
   }
 }
 

@@ -40,7 +40,7 @@ int ipm_alloc_work(Problem& p) {
   p.gt_chunks = gt_chunk_count(p.ns, p.nu, p.N);
   CMPC_HIP(hipMalloc(&p.gt_part, sizeof(double) * 3 * kGtJ * (size_t)p.gt_chunks));
   CMPC_HIP(hipMalloc(&p.red_part, sizeof(double) * 1024));
-  CMPC_HIP(hipMalloc(&p.Wdiag, sizeof(double) * 4096 * (size_t)ceil_div(p.n, 64)));
+  CMPC_HIP(hipMalloc(&p.Wdiag, sizeof(double) * wall_doubles(p.n)));
   CMPC_HIP(hipMalloc(&p.st, sizeof(IpmState)));
   CMPC_HIP(hipMemset(p.st, 0, sizeof(IpmState)));
   return 0;

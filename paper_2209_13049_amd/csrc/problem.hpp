@@ -59,6 +59,12 @@ struct SyrkPlan {
 
 struct Problem {
   int ns = 0, nu = 0, N = 0, n = 0, mx = 0, m = 0;
+  // general data folded in (capi.hip: fold_general): ns counts the problem's own ns_real
+  // states and nz extra stage rows (input bounds under a feedback, E x + F u)
+  int ns_real = 0, nz = 0;
+  bool feedback = false;          // u = K x + v: the inputs are the first nu extra rows
+  double* Sx = nullptr;           // cross weight S~ (ns x nu) of the stage cost, or NULL
+  double* wdist = nullptr;        // disturbance w_t (N x ns), or NULL
   hipStream_t stream = nullptr;
   bool q_diag = false;
   // problem data (device)
@@ -252,6 +258,13 @@ int launch_make_d(Problem& p);
 int launch_h0(Problem& p);
 int launch_free_response(Problem& p);
 int launch_check_x0(Problem& p);
+// h += S~' c_t on the block of stage t (t = 0..N-1, c_0 = x0): the linear part of the cross
+// term of the stage cost
+int launch_h_cross(Problem& p);
+// H(j, t) += G_{t-1-j}' S~ and its transpose (0 <= j < t <= N-1): the quadratic part
+int launch_cross_hessian(Problem& p, const double* S);
+// u (inputs, nu N) and x (the problem's own states, ns_real N) from v and xa = c + Gamma v
+int launch_unfold_solution(Problem& p, const double* xa, double* u, double* x);
 int launch_rbar(Problem& p, double* Hb);
 int launch_mirror_lower(hipStream_t s, double* H, int n);
 int launch_dense_gamma(Problem& p, double* dense);
@@ -270,7 +283,9 @@ int launch_syrk(Problem& p, int precision, const double* Drow, const double* Hba
 int launch_convert_gamma(Problem& p, int precision);
 
 // ---- Cholesky (k_chol.hip) ----
-// Wall: ceil(n/64) x 64 x 64 doubles receiving the inverses of the diagonal factor tiles
+// Wall: wall_doubles(n) doubles: the inverses of the diagonal factor tiles (ceil(n/64) x 64 x
+// 64), then 8 per tile of condition figures (per wavefront max |L_kk| and max |W_k|) that
+// decide whether the panel of that tile column is refined
 // ev_start / ev_stop (optional): timing events attached to the first and last dispatch.
 // lowflag (optional): if it is set when a pivot fails, it is cleared and *done = 2 (redo the
 // iteration in FP64) instead of reporting the breakdown.
@@ -283,6 +298,7 @@ int launch_potrf(hipStream_t s, double* K, int n, int ld, double* Wall, int* don
                  int* lowflag = nullptr, const double* fb = nullptr, const double* feq = nullptr,
                  double* fy = nullptr);
 constexpr int kPotrsSingleMax = 4096;  // one-workgroup solves (and the fused forward) up to here
+inline size_t wall_doubles(int n) { return (4096 + 8) * (size_t)((n + 63) / 64); }
 // Row block whose forward substitution Cholesky launch k (0 <= k < nt) runs, or -1: row block
 // j's row of L is complete after launch j (panel L_j,j-1), so block 0 runs in launch 0 and
 // block j >= 1 in launch j + 1; the last two blocks are left to the solve kernel.

@@ -302,6 +302,10 @@ static int create_mlp(Problem* p, int hidden, int depth, int precision, const fl
     set_error("surrogate: precision must be CMPC_MLP_BF16 or CMPC_MLP_FP32");
     return CMPC_ERR_INVALID;
   }
+  if (p->ns_real != p->ns || p->feedback || p->Sx != nullptr || p->wdist != nullptr) {
+    set_error("surrogate judge: problems with S, E/F rows, w or a feedback are not supported");
+    return CMPC_ERR_INVALID;
+  }
   if (!p->q_diag) {
     set_error("surrogate judge: Q and Q_f must be diagonal");
     return CMPC_ERR_INVALID;
