@@ -163,6 +163,45 @@ def batch_leg(steps: int, count: int = 512):
     return out
 
 
+def headline_batch_leg(count: int, steps: int):
+    """`count` instances of the headline workload (the same A, B, weights and bounds; x0 of
+    instances 0 .. count-1) solved together in FP64 by one batch (graph-replayed iterations,
+    converged instances predicated off): throughput, and the first three instances against
+    the same solves on the single-instance path (iterations and objectives)."""
+    import torch
+    from paper_2209_13049_amd import condmpc
+    from paper_2209_13049_amd import workloads as W
+    probs = [W.heat1d_config("1d", instance=k) for k in range(count)]
+    b = condmpc.Batch(probs)
+    rc, res = b.solve()  # warm-up: work lists and graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(steps):
+        rc, res = b.solve()
+        if rc != condmpc.OK:
+            raise RuntimeError(f"headline batch returned {rc}: {condmpc.load().cmpc_last_error()}")
+        iters += max(r["iters"] for r in res)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    single = condmpc.Problem(probs[0])
+    diffs, same_iters = [], True
+    for k in range(min(3, count)):
+        single.set_x0(probs[k].x0)
+        r = single.solve()
+        same_iters = same_iters and r["iters"] == res[k]["iters"]
+        diffs.append(abs(r["obj"] - res[k]["obj"]) / max(1.0, abs(r["obj"])))
+    single.close()
+    b.close()
+    return {"workload": f"heat1d_ns1000_nu10_N50 x {count} (x0 of instances 0..{count - 1})",
+            "instances": count, "precision": "fp64", "solves_per_s": count * steps / el,
+            "ms_per_batch": el * 1e3 / steps, "ms_per_batch_iter": el * 1e3 / max(1, iters),
+            "max_iters": max(r["iters"] for r in res),
+            "converged": sum(r["status"] == condmpc.OK for r in res),
+            "single_path_check": {"instances": min(3, count), "same_iters": same_iters,
+                                  "max_obj_rel_diff": max(diffs)}}
+
+
 def surrogate_leg(ntrain: int, nquery: int, epochs: int, replicas: int = 64):
     """Config-2 problem (ns = 1000, nu N = 500) with smooth random x0 fields: the batched IPM
     generates (x0, u*) pairs, the BF16 network (1000 -> 4 x 1024 GELU -> 500) trains on the
@@ -412,6 +451,9 @@ def main():
                     help="timed solves of the 512-instance batch (0 = skip the batch leg; off by "
                          "default: its FP32 solve after FP32 tuning faulted the GPU once and the "
                          "cause is not found)")
+    ap.add_argument("--headline-batch", type=int, default=32,
+                    help="instances of the headline workload solved as one batch (0: skip)")
+    ap.add_argument("--headline-batch-steps", type=int, default=5)
     ap.add_argument("--surrogate-train", type=int, default=8192,
                     help="IPM-generated training pairs of the surrogate (0 = skip the leg)")
     ap.add_argument("--surrogate-queries", type=int, default=4096)
@@ -558,6 +600,10 @@ def main():
             return r["iters"], r["obj"], r["primal_res"], r["dual_res"]
         out["cpu_baseline"] = cpu_baseline(args.cpu_solves, gpu_solve)
     prob.close()
+    if args.headline_batch > 0:
+        hb = headline_batch_leg(args.headline_batch, args.headline_batch_steps)
+        hb["speedup_vs_single"] = hb["solves_per_s"] / main_run["solves_per_s"]
+        out["headline_batch"] = hb
     if args.heat2d_solves > 0:
         out["heat2d"] = heat2d_leg(args.heat2d_solves)
     if args.paper_solves > 0:

@@ -278,7 +278,7 @@ __device__ inline void write_tile_lower(double* __restrict__ K, int ld, int n, i
 // so that the stores drain while the inverse is formed.
 __device__ __forceinline__ bool chol_inv64(Tile& T, Tile& W, double* colb, double* piv, int nvalid,
                                            int* bad, double* __restrict__ K, int ld, int n, int r0,
-                                           int c0) {
+                                           int c0, double* __restrict__ cslot) {
   __shared__ double pan[3 * 64 * kPW], pinv[3 * kPW];
   const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
   // ---- factorisation: wavefront w holds panels w, w+4, ... of row `lane` in registers
@@ -311,11 +311,16 @@ __device__ __forceinline__ bool chol_inv64(Tile& T, Tile& W, double* colb, doubl
   }
   const double cb = recip(sqrt(pj));  // 1 / L_jj of column `lane`
   if (w == 0) colb[lane] = cb;
+  double ml = 0.0;
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
     const int k = 4 * kPW * (kk / kPW) + kPW * w + (kk % kPW);
-    T[i][k] = (k <= i) ? r[kk] * readlane_f64(cb, k) : 0.0;
+    const double x = (k <= i) ? r[kk] * readlane_f64(cb, k) : 0.0;
+    T[i][k] = x;
+    ml = fmax(ml, fabs(x));
   }
+  ml = wave_max(ml);
+  if (lane == 0) cslot[2 * w] = ml;
   __syncthreads();
   write_tile_lower(K, ld, n, r0, c0, T, true);
   inv64(T, W, colb);
@@ -340,17 +345,21 @@ __device__ inline void write_tile_lower(double* __restrict__ K, int ld, int n, i
 }
 
 // W_k to global memory; its 16 x 16 blocks above the diagonal are zero by definition and are
-// written as zeros without being read.
-__device__ inline void write_w(double* __restrict__ Wk, const Tile& W) {
-  double v[16];
+// written as zeros without being read.  Wavefront w stores the largest |entry| it wrote to
+// cslot[2w + 1].
+__device__ inline void write_w(double* __restrict__ Wk, const Tile& W, double* __restrict__ cslot) {
+  double v[16], mw = 0.0;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int e = threadIdx.x + 256 * q;
     const int i = e >> 6, j = e & 63;
     v[q] = (j >> 4) <= (i >> 4) ? W[i][j] : 0.0;
+    mw = fmax(mw, fabs(v[q]));
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) Wk[threadIdx.x + 256 * q] = v[q];
+  mw = wave_max(mw);
+  if ((threadIdx.x & 63) == 0) cslot[2 * (threadIdx.x >> 6) + 1] = mw;
 }
 
 __device__ inline void load_w(const double* __restrict__ Wk, Tile& W) {
@@ -381,30 +390,11 @@ __device__ inline void load_lower_tile(const double* __restrict__ K, int ld, int
   }
 }
 
-// Condition figures of a factored diagonal tile (factor T, inverse W, both in LDS): wavefront
-// w stores the largest |L_ij| and |W_ij| among its threads' entries in slot[2w], slot[2w+1].
-// A panel formed with the explicit inverse, A W', has a relative error up to about
-// 64 eps max|L| max|W|; a triangular solve's error does not grow with that product.
-__device__ inline void write_cond(const Tile& T, const Tile& W, double* __restrict__ slot) {
-  double ml = 0.0, mw = 0.0;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    const int i = e >> 6, j = e & 63;
-    ml = fmax(ml, fabs(T[i][j]));
-    if ((j >> 4) <= (i >> 4)) mw = fmax(mw, fabs(W[i][j]));  // blocks above are not written
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    ml = fmax(ml, __shfl_xor(ml, off, 64));
-    mw = fmax(mw, __shfl_xor(mw, off, 64));
-  }
-  if ((threadIdx.x & 63) == 0) {
-    slot[2 * (threadIdx.x >> 6)] = ml;
-    slot[2 * (threadIdx.x >> 6) + 1] = mw;
-  }
-}
-
+// Condition figures of a factored diagonal tile, 8 doubles beside the inverses: wavefront w
+// stores the largest |L_ij| among the factor entries it scales (slot[2w], chol_inv64) and the
+// largest |W_ij| among the inverse entries it writes (slot[2w+1], write_w).  A panel formed
+// with the explicit inverse, A W', has a relative error up to about 64 eps max|L| max|W|; a
+// triangular solve's error does not grow with that product.
 // Panels of a tile column whose max|L| max|W| exceeds this are refined (refine_panel): below
 // it the inverse-based panel loses at most about three digits more than a triangular solve.
 constexpr double kRefineCond = 1e3;
@@ -476,12 +466,12 @@ __device__ __forceinline__ void chol_first_body(int bid, double* __restrict__ K,
   load_tile(K, ld, n, 0, 0, T);
   __syncthreads();
   const int nvalid = n < 64 ? n : 64;
-  if (!chol_inv64(T, W, colb, piv, nvalid, &bad, K, ld, n, 0, 0)) {
+  double* cslot = Wall + 4096 * (long long)((n + 63) >> 6);  // tile 0's condition figures
+  if (!chol_inv64(T, W, colb, piv, nvalid, &bad, K, ld, n, 0, 0, cslot)) {
     if (threadIdx.x == 0) chol_fail(bad + 1, done, info, status, lowflag);
     return;
   }
-  write_w(Wall, W);
-  write_cond(T, W, Wall + 4096 * (long long)((n + 63) >> 6));
+  write_w(Wall, W, cslot);
 }
 
 __global__ __launch_bounds__(256) void chol_first_kernel(double* __restrict__ K, int ld, int n,
@@ -654,12 +644,11 @@ __device__ __forceinline__ void chol_step_body(int bid, double* __restrict__ K, 
         Xj[32 * wr + 16 * ib + lk + 4 * v][32 * wc + 16 * jb + li] -= acc[ib][jb][v];
   __syncthreads();
   const int nvalid = n - r0 < 64 ? n - r0 : 64;
-  if (!chol_inv64(Xj, Xi, colb, piv, nvalid, &bad, K, ld, n, r0, c0)) {
+  if (!chol_inv64(Xj, Xi, colb, piv, nvalid, &bad, K, ld, n, r0, c0, cond + 8 * (k + 1))) {
     if (threadIdx.x == 0) chol_fail(r0 + bad + 1, done, info, status, lowflag);
     return;
   }
-  write_w(Wall + (long long)(k + 1) * 4096, Xi);
-  write_cond(Xj, Xi, cond + 8 * (k + 1));
+  write_w(Wall + (long long)(k + 1) * 4096, Xi, cond + 8 * (k + 1));
 }
 
 __global__ __launch_bounds__(256) void chol_step_kernel(double* __restrict__ K, int ld, int n,
@@ -709,9 +698,13 @@ __global__ __launch_bounds__(256) void tri_inv_kernel(const double* __restrict__
   // the diagonal entries of valid rows are not rewritten above
   if (threadIdx.x < 64) rdiag[threadIdx.x] = threadIdx.x < nvalid ? recip(T[threadIdx.x][threadIdx.x]) : 1.0;
   __syncthreads();
+  double* cslot = Wall + 4096 * (long long)gridDim.x + 8 * blockIdx.x;
+  double ml = 0.0;
+  for (int e = threadIdx.x; e < 4096; e += 256) ml = fmax(ml, fabs(T[e >> 6][e & 63]));
+  ml = wave_max(ml);
+  if ((threadIdx.x & 63) == 0) cslot[2 * (threadIdx.x >> 6)] = ml;
   inv64(T, W, rdiag);
-  write_w(Wall + (long long)blockIdx.x * 4096, W);
-  write_cond(T, W, Wall + 4096 * (long long)gridDim.x + 8 * blockIdx.x);
+  write_w(Wall + (long long)blockIdx.x * 4096, W, cslot);
 }
 
 int launch_tri_inv(hipStream_t s, const double* L, int n, int ld, double* Wall) {
