@@ -221,6 +221,9 @@ def surrogate_leg(ntrain: int, nquery: int, epochs: int, replicas: int = 64):
 
     def batched_ipm(k_lo, k_hi):
         for k0 in range(k_lo, k_hi, replicas):
+            if (k0 - k_lo) % (100 * replicas) == 0 and k_hi - k_lo > 20 * replicas:
+                print(f"[surrogate] IPM pairs {k0 - k_lo} / {k_hi - k_lo}", file=sys.stderr,
+                      flush=True)
             k1 = min(k_hi, k0 + replicas)
             for i in range(replicas):
                 b[i].set_x0(X[min(k0 + i, k1 - 1)])

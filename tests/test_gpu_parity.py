@@ -538,3 +538,41 @@ def test_heat2d_70x70_full_size(lib):
     f64 = objs[condmpc.FP64]
     for prec in (condmpc.FP32_SYRK, condmpc.BF16_SYRK):
         assert abs(objs[prec] - f64) <= 1e-8 * max(1.0, abs(f64))
+
+
+def test_cube_m13_T250_full_size(lib):
+    """The paper's largest 3-D cube shape (m = 13 nodes per dimension, T = 250: ns = 2197,
+    K 1500 x 1500, 549,250 state rows; Table 2's shape), in the configuration the benchmark's
+    paper-shapes leg times.  Too large for the oracle's dense reduction, so checked through
+    properties the oracle computes one by one on the CPU: the objective of the returned
+    controls by forward simulation equals the reported one, states and controls keep their
+    bounds, the FP64 KKT residuals meet the bar, and the FP32- and BF16-start solves reach the
+    FP64 objective within 1e-8."""
+    p = W.heat3d(13, 250)
+    print(f"[cube full] ns {p.ns} nu {p.nu} N {p.N}", flush=True)
+    gp = condmpc.Problem(p)
+    gp.set_x0(p.x0)
+    objs = {}
+    try:
+        for prec in (condmpc.FP64, condmpc.FP32_SYRK, condmpc.BF16_SYRK):
+            res = gp.solve(precision=prec)
+            u, _ = gp.solution(with_x=False)
+            f_sim = oracle.sparse_objective(p, u)
+            x = oracle.simulate(p, u)
+            viol = max(float(np.max(x - np.tile(p.xu, p.N))),
+                       float(np.max(np.tile(p.xl, p.N) - x)),
+                       float(np.max(u - np.tile(p.uu, p.N))),
+                       float(np.max(np.tile(p.ul, p.N) - u)))
+            print(f"[cube full] prec {prec}: status {res['status']} iters {res['iters']} obj "
+                  f"{res['obj']:.12e} simulated {f_sim:.12e} violation {viol:.2e} switch "
+                  f"{res['precision_switch_iter']} refine {res['refine_steps']}", flush=True)
+            assert res["status"] == condmpc.OK
+            assert abs(res["obj"] - f_sim) <= 1e-10 * max(1.0, abs(f_sim))
+            assert viol <= 1e-9
+            assert res["primal_res"] <= 1e-8 and res["dual_res"] <= 1e-8
+            objs[prec] = res["obj"]
+    finally:
+        gp.close()
+    f64 = objs[condmpc.FP64]
+    for prec in (condmpc.FP32_SYRK, condmpc.BF16_SYRK):
+        assert abs(objs[prec] - f64) <= 1e-8 * max(1.0, abs(f64))
