@@ -135,29 +135,39 @@ __device__ inline d4 mma16(const double* A, const double* B, d4 c, int li, int l
 
 
 // Inverse W = L^-1 of the lower-triangular tile T, given rdiag[j] = 1 / T[j][j] (T and rdiag
-// visible to the whole workgroup).  Wavefront b inverts the diagonal 16 x 16 block b by
-// forward substitution (4 lanes per column); after one barrier it forms the blocks below in
-// its column, W_ib = -W_ii (sum_{k=b}^{i-1} L_ik W_kb) for i = b+1, b+2, ..., as MFMA products,
-// which need the diagonal inverses and only its own earlier blocks (no further barrier).  The
-// blocks above the diagonal are not written (write_w emits them as zeros).
+// visible to the whole workgroup), in 16 x 16 blocks W_ij.  Phase 1: wavefront b inverts the
+// diagonal block b by forward substitution (4 lanes per column, the block's entries loaded into
+// registers first).  Then, with W = [[W_A, 0], [W_BA, W_B]] for the 32 x 32 halves A, B:
+// W_BA = -W_B (L_BA W_A), whose 2 x 2 blocks of products run on the four wavefronts in three
+// phases separated by barriers (phase 2: W_10 = -W_11 L_10 W_00, W_32 = -W_33 L_32 W_22 and the
+// parts of L_BA W_A that need only W_00, W_11; phase 3: the rest of L_BA W_A; phase 4: the four
+// blocks of W_BA), a dependent chain of five 16 x 16 products instead of nine.  The products
+// L_BA W_A are kept in the upper blocks of W, which W does not use (write_w emits them as zeros).
 __device__ void inv64(const Tile& T, Tile& W, const double* rdiag) {
-  __shared__ double S[4][16 * 65];  // per-wavefront 16 x 16 scratch
+  __shared__ double S[2][16 * 65];  // per-wavefront 16 x 16 scratch (wavefronts 0, 1)
   const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
-  {  // diagonal block w
+  {  // phase 1: diagonal block w
     const int c = lane >> 2, p = lane & 3, o = 16 * w;
+    double lv[16][4];  // L[o + ii][o + 4 kk + p] for 4 kk + p < ii
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii)
+#pragma unroll
+      for (int kk = 0; kk <= (ii >> 2); ++kk) {
+        const int k = 4 * kk + p;
+        lv[ii][kk] = k < ii ? T[o + ii][o + (k < 16 ? k : 15)] : 0.0;
+      }
+    double rd[16];
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) rd[ii] = rdiag[o + ii];
     double wv[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ii = 0; ii < 16; ++ii) {
       double part = 0.0;
 #pragma unroll
-      for (int kk = 0; kk <= (ii >> 2); ++kk) {
-        const int k = 4 * kk + p;
-        const double lk = T[o + ii][o + (k < 16 ? k : 15)];
-        part = fma(k < ii ? lk : 0.0, wv[kk], part);
-      }
+      for (int kk = 0; kk <= (ii >> 2); ++kk) part = fma(lv[ii][kk], wv[kk], part);
       part += dpp_f64<0xB1>(part);  // lane ^ 1 within the quad
       part += dpp_f64<0x4E>(part);  // lane ^ 2
-      const double val = (ii >= c) ? (((ii == c) ? 1.0 : 0.0) - part) * rdiag[o + ii] : 0.0;
+      const double val = (ii >= c) ? (((ii == c) ? 1.0 : 0.0) - part) * rd[ii] : 0.0;
       if (p == (ii & 3)) wv[ii >> 2] = val;
     }
 #pragma unroll
@@ -165,24 +175,54 @@ __device__ void inv64(const Tile& T, Tile& W, const double* rdiag) {
   }
   __syncthreads();
   const int li = lane & 15, lk = lane >> 4;
-  double* Sw = S[w];
-  const int j = w;
-  for (int ii = j + 1; ii < 4; ++ii) {  // block (ii, j), after (ii - 1, j)
-    d4 acc = d4{0, 0, 0, 0};
-    for (int k = j; k < ii; ++k) acc = mma16(&T[16 * ii][16 * k], &W[16 * k][16 * j], acc, li, lk);
+  const d4 zero = d4{0, 0, 0, 0};
+  // the blocks of L_BA W_A: P20 -> W(0,1), P21 -> W(0,2), P30 -> W(0,3), P31 -> W(1,2)
+  double* P20 = &W[0][16];
+  double* P21 = &W[0][32];
+  double* P30 = &W[0][48];
+  double* P31 = &W[16][32];
+  auto store = [&](double* dst, const d4& acc, double sign) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Sw[(lk + 4 * v) * 65 + li] = acc[v];
+    for (int v = 0; v < 4; ++v) dst[(lk + 4 * v) * 65 + li] = sign * acc[v];
+  };
+  d4 keep = zero;  // wavefronts 2, 3: L_20 W_00 or L_30 W_00, completed in phase 3
+  // phase 2
+  if (w <= 1) {
+    const int i = w == 0 ? 1 : 3, j = w == 0 ? 0 : 2;  // W_ij = -W_ii L_ij W_jj
+    double* Sw = S[w];
+    store(Sw, mma16(&T[16 * i][16 * j], &W[16 * j][16 * j], zero, li, lk), 1.0);
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
-    acc = mma16(&W[16 * ii][16 * ii], Sw, d4{0, 0, 0, 0}, li, lk);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) W[16 * ii + lk + 4 * v][16 * j + li] = -acc[v];
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+    store(&W[16 * i][16 * j], mma16(&W[16 * i][16 * i], Sw, zero, li, lk), -1.0);
+  } else {
+    const int r = w == 2 ? 2 : 3;  // row block of L_BA
+    keep = mma16(&T[16 * r][0], &W[0][0], zero, li, lk);                      // L_r0 W_00
+    store(w == 2 ? P21 : P31, mma16(&T[16 * r][16], &W[16][16], zero, li, lk), 1.0);  // L_r1 W_11
+  }
+  __syncthreads();
+  // phase 3: P_r0 = L_r0 W_00 + L_r1 W_10
+  if (w >= 2) {
+    const int r = w == 2 ? 2 : 3;
+    store(w == 2 ? P20 : P30, mma16(&T[16 * r][16], &W[16][0], keep, li, lk), 1.0);
+  }
+  __syncthreads();
+  // phase 4: W_BA = -W_B P: W_20 = -W_22 P20, W_21 = -W_22 P21, W_30 = -(W_32 P20 + W_33 P30),
+  // W_31 = -(W_32 P21 + W_33 P31)
+  {
+    const int col = w & 1;  // 0: column block 0, 1: column block 1
+    const double* Pa = col == 0 ? P20 : P21;
+    d4 acc;
+    if (w <= 1) {
+      acc = mma16(&W[32][32], Pa, zero, li, lk);
+      store(&W[32][16 * col], acc, -1.0);
+    } else {
+      acc = mma16(&W[48][32], Pa, zero, li, lk);
+      acc = mma16(&W[48][48], col == 0 ? P30 : P31, acc, li, lk);
+      store(&W[48][16 * col], acc, -1.0);
+    }
   }
   __syncthreads();
 }
-
 
 // Right-looking factorisation of the tile in 16 panels of 4 columns, one barrier per panel.
 // Panels are dealt round robin: wavefront W holds panels W, W+4, W+8, W+12 (local panel m =
