@@ -581,6 +581,15 @@ def main():
                      args.precision == "fp64" else None,
                      "flops_per_launch": info["syrk_flops"],
                      "avg_launch_us": main_run["syrk_avg_launch_us"]},
+        # the Cholesky factorisation (chol_first + one chol_step launch per 64-column step), the
+        # largest share of the iteration's time: n^3/3 FLOPs per factorisation over its
+        # event-timed duration (first dispatch to last); latency-bound at this size
+        "roofline_potrf": {"bound": "mfma", "kernel": "chol_first + chol_step",
+                           "achieved": info["potrf_flops"] / (main_run["ms_per_iter_potrf"] / 1e3)
+                           / 1e12, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                           "frac": info["potrf_flops"] / (main_run["ms_per_iter_potrf"] / 1e3)
+                           / 1e12 / PEAK["fp64"], "flops_per_factorisation": info["potrf_flops"],
+                           "avg_factorisation_us": main_run["ms_per_iter_potrf"] * 1e3},
     }
     if other_run is not None:
         rel = [abs(a - b) / max(1.0, abs(b)) for a, b in zip(other_run["objs"], main_run["objs"])]
