@@ -225,7 +225,10 @@ static int create_standard(const cmpc_lq_desc* desc, hipStream_t stream, Problem
       }
       rowptr[i + 1] = (int)col.size();
     }
+    int maxnnz = 0;
+    for (int i = 0; i < ns; ++i) maxnnz = std::max(maxnnz, rowptr[i + 1] - rowptr[i]);
     if ((double)col.size() <= 0.25 * (double)ns * ns && ns <= 4096 && !col.empty()) {
+      p->a_maxnnz = maxnnz;
       if (hipMalloc(&p->a_rowptr, sizeof(int) * (ns + 1)) != hipSuccess ||
           hipMalloc(&p->a_col, sizeof(int) * col.size()) != hipSuccess) {
         free_problem(p);

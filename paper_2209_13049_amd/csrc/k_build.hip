@@ -234,6 +234,54 @@ __global__ __launch_bounds__(1024) void free_response_csr_kernel(
   }
 }
 
+// The same with each thread's rows of A (R rows, at most kRowNnz nonzeros each) held in
+// registers for the whole horizon, so a step reads only the state in LDS; each row's sum is
+// formed over its own entries in the CSR order, as above.
+constexpr int kRowNnz = 8;
+template <int R>
+__global__ __launch_bounds__(1024) void free_response_reg_kernel(
+    const int* __restrict__ rowptr, const int* __restrict__ col, const double* __restrict__ val,
+    const double* __restrict__ x0, double* __restrict__ c, int ns, int N,
+    const double* __restrict__ w) {
+  extern __shared__ double buf[];  // 2 ns
+  double* cur = buf;
+  double* nxt = buf + ns;
+  double a[R][kRowNnz];
+  int ac[R][kRowNnz], cnt[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = threadIdx.x + 1024 * r;
+    const int b = i < ns ? rowptr[i] : 0, e = i < ns ? rowptr[i + 1] : 0;
+    cnt[r] = e - b;
+#pragma unroll
+    for (int k = 0; k < kRowNnz; ++k) {
+      a[r][k] = b + k < e ? val[b + k] : 0.0;
+      ac[r][k] = b + k < e ? col[b + k] : 0;
+    }
+  }
+  for (int i = threadIdx.x; i < ns; i += 1024) cur[i] = x0[i];
+  __syncthreads();
+  for (int t = 1; t <= N; ++t) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = threadIdx.x + 1024 * r;
+      if (i < ns) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRowNnz; ++k)
+          if (k < cnt[r]) acc = fma(a[r][k], cur[ac[r][k]], acc);
+        if (w != nullptr) acc += w[(long long)(t - 1) * ns + i];
+        nxt[i] = acc;
+        c[(long long)(t - 1) * ns + i] = acc;
+      }
+    }
+    __syncthreads();
+    double* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+}
+
 __global__ void add_into_kernel(double* __restrict__ y, const double* __restrict__ w, int len) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) y[i] += w[i];
@@ -241,6 +289,23 @@ __global__ void add_into_kernel(double* __restrict__ y, const double* __restrict
 
 // c_t = A c_{t-1} + w_{t-1} (w = NULL: 0), c_0 = x0, t = 1..N (eqn. (dyn) with v = 0).
 int launch_free_response(Problem& p) {
+  if (p.a_rowptr != nullptr && p.a_maxnnz <= kRowNnz) {
+    const size_t lds = sizeof(double) * 2 * (size_t)p.ns;
+    const int R = ceil_div(p.ns, 1024);  // 1..4: the CSR copy exists for ns <= 4096
+    const double* w = p.wdist;
+    switch (R) {
+      case 1: hipLaunchKernelGGL(free_response_reg_kernel<1>, dim3(1), dim3(1024), lds, p.stream,
+                                 p.a_rowptr, p.a_col, p.a_val, p.x0, p.c, p.ns, p.N, w); break;
+      case 2: hipLaunchKernelGGL(free_response_reg_kernel<2>, dim3(1), dim3(1024), lds, p.stream,
+                                 p.a_rowptr, p.a_col, p.a_val, p.x0, p.c, p.ns, p.N, w); break;
+      case 3: hipLaunchKernelGGL(free_response_reg_kernel<3>, dim3(1), dim3(1024), lds, p.stream,
+                                 p.a_rowptr, p.a_col, p.a_val, p.x0, p.c, p.ns, p.N, w); break;
+      default: hipLaunchKernelGGL(free_response_reg_kernel<4>, dim3(1), dim3(1024), lds, p.stream,
+                                  p.a_rowptr, p.a_col, p.a_val, p.x0, p.c, p.ns, p.N, w); break;
+    }
+    CMPC_LAUNCH_CHECK();
+    return 0;
+  }
   if (p.a_rowptr != nullptr) {
     hipLaunchKernelGGL(free_response_csr_kernel, dim3(1), dim3(1024),
                        sizeof(double) * 2 * (size_t)p.ns, p.stream, p.a_rowptr, p.a_col, p.a_val,

@@ -83,6 +83,7 @@ struct Problem {
   double *K = nullptr;           // n x n workspace (lower triangle = condensed matrix / factor)
   int *a_rowptr = nullptr, *a_col = nullptr;  // CSR copy of A when it is sparse
   double* a_val = nullptr;
+  int a_maxnnz = 0;  // most nonzeros in a row of that copy
   double *red_part = nullptr;    // 1024 partial sums
   double *x0 = nullptr, *c = nullptr, *qc = nullptr, *h = nullptr, *d = nullptr;
   bool have_x0 = false;
