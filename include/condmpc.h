@@ -23,7 +23,8 @@
  *
  * Readings of the paper that the library implements (Algorithm 1 leaves them open):
  *   objective with 1/2 on every quadratic term; Q_f = Q when NULL; state bounds for
- *   t = 1..N only (x_0 is data); feedback gain K = 0 (v = u); right-hand side
+ *   t = 1..N only (x_0 is data); feedback gain Kfb = 0 (v = u) unless one is given;
+ *   general data folded into extra stage components (cmpc_lq_desc); right-hand side
  *   -r1 + J'r2 - J'Sigma r3; start mu = 0.1, v = 0, s = max(d - Jv, 1e-2),
  *   lambda = z = mu/s; monotone barrier rule (kappa_eps = 10, kappa_mu = 0.2,
  *   theta_mu = 1.5, mu_min = tol/10); fraction-to-boundary step lengths alpha (v, s,
