@@ -145,23 +145,26 @@ __device__ inline d4 mma16(const double* A, const double* B, d4 c, int li, int l
 // L_BA W_A are kept in the upper blocks of W, which W does not use (write_w emits them as zeros).
 __device__ void inv64(const Tile& T, Tile& W, const double* rdiag) {
   __shared__ double S[2][16 * 65];  // per-wavefront 16 x 16 scratch (wavefronts 0, 1)
+  __shared__ double S8[4][64];       // per-wavefront 8 x 8 scratch of phase 1
   const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
-  {  // phase 1: diagonal block w
-    const int c = lane >> 2, p = lane & 3, o = 16 * w;
-    double lv[16][4];  // L[o + ii][o + 4 kk + p] for 4 kk + p < ii
+  {  // phase 1: diagonal block w as two 8 x 8 halves by substitution (lanes 0-31 the upper
+     // left one, lanes 32-63 the lower right one; 4 lanes per column), then the 8 x 8 block
+     // between them, W_BA = -W_B L_BA W_A, one entry per lane
+    const int h = lane >> 5, q = lane & 31, c = q >> 2, p = q & 3, o = 16 * w + 8 * h;
+    double lv[8][2];  // L[o + ii][o + 4 kk + p] for 4 kk + p < ii
 #pragma unroll
-    for (int ii = 0; ii < 16; ++ii)
+    for (int ii = 0; ii < 8; ++ii)
 #pragma unroll
       for (int kk = 0; kk <= (ii >> 2); ++kk) {
         const int k = 4 * kk + p;
-        lv[ii][kk] = k < ii ? T[o + ii][o + (k < 16 ? k : 15)] : 0.0;
+        lv[ii][kk] = k < ii ? T[o + ii][o + k] : 0.0;
       }
-    double rd[16];
+    double rd[8];
 #pragma unroll
-    for (int ii = 0; ii < 16; ++ii) rd[ii] = rdiag[o + ii];
-    double wv[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int ii = 0; ii < 8; ++ii) rd[ii] = rdiag[o + ii];
+    double wv[2] = {0.0, 0.0};
 #pragma unroll
-    for (int ii = 0; ii < 16; ++ii) {
+    for (int ii = 0; ii < 8; ++ii) {
       double part = 0.0;
 #pragma unroll
       for (int kk = 0; kk <= (ii >> 2); ++kk) part = fma(lv[ii][kk], wv[kk], part);
@@ -171,7 +174,21 @@ __device__ void inv64(const Tile& T, Tile& W, const double* rdiag) {
       if (p == (ii & 3)) wv[ii >> 2] = val;
     }
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) W[o + 4 * kk + p][o + c] = wv[kk];
+    for (int kk = 0; kk < 2; ++kk) W[o + 4 * kk + p][o + c] = wv[kk];
+    const int b0 = 16 * w, r = lane >> 3, cc = lane & 7;
+    W[b0 + r][b0 + 8 + cc] = 0.0;  // the diagonal block's upper right 8 x 8
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    double sacc = 0.0;  // (L_BA W_A)[r][cc]
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sacc = fma(T[b0 + 8 + r][b0 + k], W[b0 + k][b0 + cc], sacc);
+    S8[w][r * 8 + cc] = sacc;
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    double wacc = 0.0;  // (W_B S)[r][cc]
+#pragma unroll
+    for (int k = 0; k < 8; ++k) wacc = fma(W[b0 + 8 + r][b0 + 8 + k], S8[w][k * 8 + cc], wacc);
+    W[b0 + 8 + r][b0 + cc] = -wacc;
   }
   __syncthreads();
   const int li = lane & 15, lk = lane >> 4;
