@@ -1060,7 +1060,8 @@ __device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, 
                                                   double* __restrict__ x,
                                                   const double* __restrict__ eq, double* ys,
                                                   double* rs, double (*red)[65], int kf,
-                                                  unsigned long long refm, double* es) {
+                                                  unsigned long long refm, double* es,
+                                                  int accumulate) {
   const int t = threadIdx.x;
   const int nt = (n + 63) >> 6;
   // ---- forward: L y = b
@@ -1148,7 +1149,10 @@ __device__ __forceinline__ void potrs_single_body(const double* __restrict__ L, 
       if ((refm >> k) & 1ull) refine_bwd_block(L, ld, n, k0, wv, ys, rs, es, red);
     }
   }
-  for (int i = t; i < n; i += 1024) x[i] = eq ? eq[i] * ys[i] : ys[i];
+  for (int i = t; i < n; i += 1024) {
+    const double v = eq ? eq[i] * ys[i] : ys[i];
+    x[i] = accumulate ? x[i] + v : v;
+  }
 }
 
 // The same two substitutions for n <= 64 NT with NT <= 8 block steps, unrolled so that the
@@ -1164,7 +1168,7 @@ __device__ __forceinline__ void potrs_pipe_body(const double* __restrict__ L, in
                                                 const double* __restrict__ eq, double* ys,
                                                 double* rs, double (*red)[65],
                                                 const double* __restrict__ yf, double* es,
-                                                unsigned long long* mask) {
+                                                unsigned long long* mask, int accumulate) {
   const int t = threadIdx.x;
   const int kf = yf ? (NT > 2 ? NT - 2 : 0) : 0;  // blocks done by the fused forward pass
   potrs_prologue(Wall, b, eq, yf, n, NT, kf, ys, mask);
@@ -1177,7 +1181,7 @@ __device__ __forceinline__ void potrs_pipe_body(const double* __restrict__ L, in
     for (int q = 0; q < 4; ++q) wv[q] = Wall[(long long)kf * 4096 + i * 64 + g + 16 * q];
     __syncthreads();
     if (*mask != 0ull) {  // a tile to refine: the looped form (uniform)
-      potrs_single_body(L, ld, n, Wall, x, eq, ys, rs, red, kf, *mask, es);
+      potrs_single_body(L, ld, n, Wall, x, eq, ys, rs, red, kf, *mask, es, accumulate);
       return;
     }
 #pragma unroll
@@ -1255,7 +1259,10 @@ __device__ __forceinline__ void potrs_pipe_body(const double* __restrict__ L, in
       __syncthreads();
     }
   }
-  for (int i = t; i < n; i += 1024) x[i] = eq ? eq[i] * ys[i] : ys[i];
+  for (int i = t; i < n; i += 1024) {
+    const double v = eq ? eq[i] * ys[i] : ys[i];
+    x[i] = accumulate ? x[i] + v : v;
+  }
 }
 
 // One workgroup solves: the pipelined form up to 8 block steps, the looped form beyond (and
@@ -1266,26 +1273,26 @@ __device__ __forceinline__ void potrs_one_body(const double* __restrict__ L, int
                                                double* __restrict__ x,
                                                const double* __restrict__ eq,
                                                const int* __restrict__ gate,
-                                               const double* __restrict__ yf) {
+                                               const double* __restrict__ yf, int accumulate) {
   extern __shared__ double ys[];  // 64 ceil(n / 64)
   __shared__ double rs[64], es[64];
   __shared__ double red[16][65];
   __shared__ unsigned long long mask;
   if (gate != nullptr && *gate) return;
   switch ((n + 63) >> 6) {
-    case 1: potrs_pipe_body<1>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
-    case 2: potrs_pipe_body<2>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
-    case 3: potrs_pipe_body<3>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
-    case 4: potrs_pipe_body<4>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
-    case 5: potrs_pipe_body<5>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
-    case 6: potrs_pipe_body<6>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
-    case 7: potrs_pipe_body<7>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
-    case 8: potrs_pipe_body<8>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask); break;
+    case 1: potrs_pipe_body<1>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask, accumulate); break;
+    case 2: potrs_pipe_body<2>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask, accumulate); break;
+    case 3: potrs_pipe_body<3>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask, accumulate); break;
+    case 4: potrs_pipe_body<4>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask, accumulate); break;
+    case 5: potrs_pipe_body<5>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask, accumulate); break;
+    case 6: potrs_pipe_body<6>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask, accumulate); break;
+    case 7: potrs_pipe_body<7>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask, accumulate); break;
+    case 8: potrs_pipe_body<8>(L, ld, n, Wall, b, x, eq, ys, rs, red, yf, es, &mask, accumulate); break;
     default: {
       const int nt = (n + 63) >> 6, kf = yf ? nt - 2 : 0;
       potrs_prologue(Wall, b, eq, yf, n, nt, kf, ys, &mask);
       __syncthreads();
-      potrs_single_body(L, ld, n, Wall, x, eq, ys, rs, red, kf, mask, es);
+      potrs_single_body(L, ld, n, Wall, x, eq, ys, rs, red, kf, mask, es, accumulate);
     }
   }
 }
@@ -1296,8 +1303,9 @@ __global__ __launch_bounds__(1024) void potrs_single_kernel(const double* __rest
                                                             double* __restrict__ x,
                                                             const double* __restrict__ eq,
                                                             const int* __restrict__ gate,
-                                                            const double* __restrict__ yf) {
-  potrs_one_body(L, ld, n, Wall, b, x, eq, gate, yf);
+                                                            const double* __restrict__ yf,
+                                                            int accumulate) {
+  potrs_one_body(L, ld, n, Wall, b, x, eq, gate, yf, accumulate);
 }
 
 // x = (L L')^-1 b (eq != NULL: x = S (L L')^-1 S b).  work: n doubles of scratch (the reduced
@@ -1305,11 +1313,11 @@ __global__ __launch_bounds__(1024) void potrs_single_kernel(const double* __rest
 // form (the vector in LDS, at most 32 KB).
 int launch_potrs(hipStream_t s, const double* L, int n, int ld, const double* Wall,
                  const double* b, double* x, double* work, const int* done, const double* eq,
-                 const double* yf) {
+                 const double* yf, int accumulate) {
   if (n <= kPotrsSingleMax) {
     hipLaunchKernelGGL(potrs_single_kernel, dim3(1), dim3(1024),
                        sizeof(double) * 64 * (size_t)ceil_div(n, 64), s, L,
-                       ld, n, Wall, b, x, eq, done, yf);
+                       ld, n, Wall, b, x, eq, done, yf, accumulate);
     CMPC_LAUNCH_CHECK();
     return 0;
   }
@@ -1437,7 +1445,7 @@ __global__ __launch_bounds__(1024) void potrs_single_batch_kernel(
   const WorkItem it = items[blockIdx.x];
   const InstView& V = views[it.inst];
   potrs_one_body(V.K, V.n, V.n, V.Wdiag, which ? V.ref_res : V.rhs, which ? V.ref_dlt : V.pv,
-                 eq ? V.eqs : nullptr, gate_of(V, which), fused && !which ? V.tmpn : nullptr);
+                 eq ? V.eqs : nullptr, gate_of(V, which), fused && !which ? V.tmpn : nullptr, 0);
 }
 
 int launch_b_potrs_single(const ListArg& L, int which, int eq, int nmax, int fused) {

@@ -212,7 +212,8 @@ int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int
 __device__ __forceinline__ void gamma_mv_body(int bid, const double* __restrict__ Gt,
                                               const double* __restrict__ x,
                                               double* __restrict__ y, int ns, int nu, int N,
-                                              const int* __restrict__ done) {
+                                              const int* __restrict__ done,
+                                              const double* __restrict__ scale = nullptr) {
   __shared__ double red[4][kMvT][64];
   if (done != nullptr && *done) return;
   const int nbx = (ns + 63) >> 6;
@@ -261,22 +262,27 @@ __device__ __forceinline__ void gamma_mv_body(int bid, const double* __restrict_
   __syncthreads();
   if (w < kMvT) {  // wavefront w writes row block t_hi - w
     const int t = t_hi - w;
-    if (t >= 1 && i < ns)
-      y[(long long)(t - 1) * ns + i] =
-          ((red[0][w][lane] + red[1][w][lane]) + red[2][w][lane]) + red[3][w][lane];
+    if (t >= 1 && i < ns) {
+      const long long r = (long long)(t - 1) * ns + i;
+      const double val = ((red[0][w][lane] + red[1][w][lane]) + red[2][w][lane]) + red[3][w][lane];
+      y[r] = scale != nullptr ? val * scale[r] : val;
+    }
   }
 }
 
+// y = Gamma x, or with scale != NULL y = scale o (Gamma x)
 __global__ __launch_bounds__(256) void gamma_mv_kernel(const double* __restrict__ Gt,
                                                        const double* __restrict__ x,
                                                        double* __restrict__ y, int ns, int nu,
-                                                       int N, const int* __restrict__ done) {
-  gamma_mv_body(blockIdx.x, Gt, x, y, ns, nu, N, done);
+                                                       int N, const int* __restrict__ done,
+                                                       const double* __restrict__ scale) {
+  gamma_mv_body(blockIdx.x, Gt, x, y, ns, nu, N, done, scale);
 }
 
-int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done) {
+int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done,
+                    const double* scale) {
   hipLaunchKernelGGL(gamma_mv_kernel, dim3(gmv_blocks(p.ns, p.N)), dim3(256), 0, p.stream, p.Gt,
-                     x, y, p.ns, p.nu, p.N, done);
+                     x, y, p.ns, p.nu, p.N, done, scale);
   CMPC_LAUNCH_CHECK();
   return 0;
 }
@@ -931,15 +937,22 @@ __global__ void axpy_gated_kernel(double* __restrict__ y, const double* __restri
   axpy_gated_body(blockIdx.x, y, x, len, skip);
 }
 
+// gt_part != NULL: Gamma'(D_x o Gamma p) is added up here from the Gamma' pass's partials (the
+// order of gamma_t_reduce), instead of being read from gtp.
 __device__ __forceinline__ void refine_check_body(int bid, 
     const double* __restrict__ rhs, const double* __restrict__ Hp, const double* __restrict__ gtp,
     const double* __restrict__ Du, const double* __restrict__ p, double* __restrict__ res, int n,
-    IpmState* st) {
+    IpmState* st, const double* __restrict__ gt_part = nullptr, int ns = 0, int nu = 0) {
   __shared__ double sh2[2][4];
   if (st->ref_skip || st->done) return;
   double nr = 0.0, nb = 0.0;
   for (int c = threadIdx.x; c < n; c += 256) {
-    const double r = rhs[c] - (Hp[c] + gtp[c] + Du[c] * p[c]);
+    double g[1];
+    if (gt_part != nullptr)
+      gamma_t_column<1>(gt_part, c, ns, nu, g);
+    else
+      g[0] = gtp[c];
+    const double r = rhs[c] - (Hp[c] + g[0] + Du[c] * p[c]);
     res[c] = r;
     nr = fmax(nr, fabs(r));
     nb = fmax(nb, fabs(rhs[c]));
@@ -971,21 +984,26 @@ __device__ __forceinline__ void refine_check_body(int bid,
 __global__ __launch_bounds__(256) void refine_check_kernel(
     const double* __restrict__ rhs, const double* __restrict__ Hp, const double* __restrict__ gtp,
     const double* __restrict__ Du, const double* __restrict__ p, double* __restrict__ res, int n,
-    IpmState* st) {
-  refine_check_body(blockIdx.x, rhs, Hp, gtp, Du, p, res, n, st);
+    IpmState* st, const double* __restrict__ gt_part, int ns, int nu) {
+  refine_check_body(blockIdx.x, rhs, Hp, gtp, Du, p, res, n, st, gt_part, ns, nu);
 }
 
+// One refinement step in four launches (the same arithmetic as the batch form's eight):
+// D_x o Gamma p (the scaling fused into the Gamma pass); the Gamma' pass's partials beside
+// H p; the residual with the partials added up in the check; p += (L L')^-1 res in the solve.
 int launch_refine_step(Problem& p) {
   const int* skip = &p.st->ref_skip;
-  if (launch_gamma_mv(p, p.pv, p.gpv, skip)) return CMPC_ERR_HIP;
-  hipLaunchKernelGGL(scale_by_kernel, dim3(ceil_div(p.mx, 256)), dim3(256), 0, p.stream, p.gpv,
-                     p.Dx, p.mx, skip);
+  if (launch_gamma_mv(p, p.pv, p.gpv, skip, p.Dx)) return CMPC_ERR_HIP;
+  hipLaunchKernelGGL(gamma_t_hv_kernel<1>, dim3(p.gt_chunks + ceil_div(p.n, 4)), dim3(256), 0,
+                     p.stream, p.Gt, p.gpv, (long long)p.mx, p.gt_part, p.ns, p.nu, p.N,
+                     p.gt_chunks, p.H, p.pv, p.Hv, p.n, skip);
   CMPC_LAUNCH_CHECK();
-  if (launch_gamma_t(p, p.gpv, 1, p.ref_gt, skip)) return CMPC_ERR_HIP;
-  if (launch_hv(p, p.pv, p.Hv, skip)) return CMPC_ERR_HIP;
   hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(256), 0, p.stream, p.rhs, p.Hv, p.ref_gt,
-                     p.Du, p.pv, p.ref_res, p.n, p.st);
+                     p.Du, p.pv, p.ref_res, p.n, p.st, p.gt_part, p.ns, p.nu);
   CMPC_LAUNCH_CHECK();
+  if (p.n <= kPotrsSingleMax)  // pv += the correction, in the solve's own store
+    return launch_potrs(p.stream, p.K, p.n, p.n, p.Wdiag, p.ref_res, p.pv, p.tmpn, skip,
+                        p.eq_on ? p.eqs : nullptr, nullptr, 1);
   if (launch_potrs(p.stream, p.K, p.n, p.n, p.Wdiag, p.ref_res, p.ref_dlt, p.tmpn, skip,
                    p.eq_on ? p.eqs : nullptr))
     return CMPC_ERR_HIP;

@@ -311,9 +311,10 @@ __host__ __device__ inline int fwd_block_at(int k, int nt) {
 // eq != NULL: L is the factor of the equilibrated S K S (S = diag(eq)) and x = S (L L')^-1 S b.
 // yf != NULL (n <= kPotrsSingleMax): y of every row block but the last two is already in yf
 // (launch_potrf's fused forward substitution with the same b and eq).
+// accumulate (n <= kPotrsSingleMax, x distinct from b): x += (L L')^-1 b instead.
 int launch_potrs(hipStream_t s, const double* L, int n, int ld, const double* Wall,
                  const double* b, double* x, double* work, const int* done,
-                 const double* eq = nullptr, const double* yf = nullptr);
+                 const double* eq = nullptr, const double* yf = nullptr, int accumulate = 0);
 // Diagonal equilibration in place: eq_i = K_ii^-1/2, K_ij <- eq_i K_ij eq_j (lower triangle).
 int launch_equilibrate(hipStream_t s, double* K, int n, int ld, double* eq, const int* done);
 int launch_tri_inv(hipStream_t s, const double* L, int n, int ld, double* Wall);
@@ -321,7 +322,9 @@ int launch_tri_inv(hipStream_t s, const double* L, int n, int ld, double* Wall);
 // ---- IPM vector kernels (k_ipm.hip) ----
 int ipm_alloc_work(Problem& p);
 int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int* done);
-int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done);
+// y = Gamma x (scale != NULL: y = scale o Gamma x)
+int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done,
+                    const double* scale = nullptr);
 // warm = 0: the cold start; warm = 1: start from the controls already in p.v with barrier
 // parameter mu0 (Gamma v is formed first).
 int launch_ipm_init(Problem& p, const cmpc_options& o, int warm = 0, double mu0 = 0.0);
