@@ -300,15 +300,16 @@ static int enqueue_iteration(Batch& b, int mixed, int refine, int eq) {
     if (launch_b_chol_step(arg(b, b.chol[k]), k, mixed, b.nmax <= kPotrsSingleMax, eq))
       return CMPC_ERR_HIP;
   if (enqueue_potrs(b, 0, eq)) return CMPC_ERR_HIP;
+  // refinement rounds in the single-instance step's arithmetic: D_x o Gamma p in the Gamma
+  // pass, the Gamma' partials added up in the check, and (one-workgroup solves) the
+  // correction added to p in the solve's store
   for (int r = 0; r < refine; ++r) {
     if (launch_b_gamma_mv(arg(b, b.gmv), 1)) return CMPC_ERR_HIP;
-    if (launch_b_scale_by(arg(b, b.mx256))) return CMPC_ERR_HIP;
     if (launch_b_gamma_t_partial(arg(b, b.gt), 1)) return CMPC_ERR_HIP;
-    if (launch_b_gamma_t_reduce(arg(b, b.n256), 1)) return CMPC_ERR_HIP;
     if (launch_b_hv(arg(b, b.n4), 1)) return CMPC_ERR_HIP;
     if (launch_b_refine_check(arg(b, b.one))) return CMPC_ERR_HIP;
     if (enqueue_potrs(b, 1, eq)) return CMPC_ERR_HIP;
-    if (launch_b_axpy(arg(b, b.n256))) return CMPC_ERR_HIP;
+    if (b.nmax > kPotrsSingleMax && launch_b_axpy(arg(b, b.n256))) return CMPC_ERR_HIP;
   }
   if (launch_b_gamma_mv(arg(b, b.gmv), 0)) return CMPC_ERR_HIP;
   if (launch_b_step(arg(b, b.blk))) return CMPC_ERR_HIP;

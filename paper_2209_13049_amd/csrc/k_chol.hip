@@ -1444,8 +1444,9 @@ __global__ __launch_bounds__(1024) void potrs_single_batch_kernel(
   if ((int)blockIdx.x >= nitems) return;
   const WorkItem it = items[blockIdx.x];
   const InstView& V = views[it.inst];
-  potrs_one_body(V.K, V.n, V.n, V.Wdiag, which ? V.ref_res : V.rhs, which ? V.ref_dlt : V.pv,
-                 eq ? V.eqs : nullptr, gate_of(V, which), fused && !which ? V.tmpn : nullptr, 0);
+  // which = 1: pv += the correction (the refinement's axpy in the solve's own store)
+  potrs_one_body(V.K, V.n, V.n, V.Wdiag, which ? V.ref_res : V.rhs, V.pv, eq ? V.eqs : nullptr,
+                 gate_of(V, which), fused && !which ? V.tmpn : nullptr, which);
 }
 
 int launch_b_potrs_single(const ListArg& L, int which, int eq, int nmax, int fused) {

@@ -1130,8 +1130,9 @@ __global__ __launch_bounds__(256) void gamma_mv_batch_kernel(const InstView* __r
   CMPC_ITEMS_BEGIN
   if (gate == 2)
     gamma_mv_body(bid, V.Gt, V.v, V.gv, V.ns, V.nu, V.N, nullptr);
-  else
-    gamma_mv_body(bid, V.Gt, V.pv, V.gpv, V.ns, V.nu, V.N, gate_of(V, gate));
+  else  // the refinement's pass (gate 1) is scaled by D_x, as in the single-instance step
+    gamma_mv_body(bid, V.Gt, V.pv, V.gpv, V.ns, V.nu, V.N, gate_of(V, gate),
+                  gate == 1 ? V.Dx : nullptr);
   CMPC_ITEMS_END
 }
 
@@ -1169,7 +1170,8 @@ __global__ __launch_bounds__(256) void scale_by_batch_kernel(const InstView* __r
 __global__ __launch_bounds__(256) void refine_check_batch_kernel(
     const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems) {
   CMPC_ITEMS_BEGIN
-  refine_check_body(bid, V.rhs, V.Hv, V.ref_gt, V.Du, V.pv, V.ref_res, V.n, V.st);
+  refine_check_body(bid, V.rhs, V.Hv, V.ref_gt, V.Du, V.pv, V.ref_res, V.n, V.st, V.gt_part,
+                    V.ns, V.nu);
   CMPC_ITEMS_END
 }
 
