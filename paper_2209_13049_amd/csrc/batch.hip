@@ -99,7 +99,7 @@ struct Batch {
   std::vector<InstView> hviews;  // host copy of `views` as uploaded by build_lists
   WorkItem* items = nullptr;
   size_t items_cap = 0;
-  List init, blk, gt, n4, one, syrk, fin, n256, gmv, mx256;
+  List init, blk, gt, n4, one, syrk, fin, n256, gmv;
   std::vector<List> chol, fwd, bwd;
   int ntmax = 0, nmax = 0;
   bool lists_valid = false;
@@ -183,7 +183,6 @@ static InstView view_of(const Problem& p) {
   v.tmpn = p.tmpn;
   v.ref_res = p.ref_res;
   v.ref_dlt = p.ref_dlt;
-  v.ref_gt = p.ref_gt;
   v.norm_part = p.norm_part;
   v.alpha_part = p.alpha_part;
   v.gt_part = p.gt_part;
@@ -222,7 +221,6 @@ static int build_lists(Batch& b) {
   add(b.fin, [&](const InstView& v) { return v.nt * (v.nt + 1) / 2 * 16; });
   add(b.n256, [](const InstView& v) { return ceil_div(v.n, 256); });
   add(b.gmv, [](const InstView& v) { return gmv_blocks(v.ns, v.N); });
-  add(b.mx256, [](const InstView& v) { return ceil_div(v.mx, 256); });
   b.ntmax = 0;
   b.nmax = 0;
   for (const InstView& v : hv) {

@@ -84,7 +84,7 @@ void free_problem(Problem* p) {
                      &p->lam, &p->z,  &p->gv,   &p->pv,    &p->ps,   &p->plam, &p->pz,
                      &p->gpv, &p->rhs, &p->Dx,  &p->Du,    &p->wx,   &p->wu,   &p->gt,
                      &p->Hv, &p->tmpn, &p->tmpn2, &p->tmpmx, &p->norm_part, &p->alpha_part,
-                     &p->gt_part, &p->Wdiag, &p->ref_res, &p->ref_dlt, &p->ref_gt, &p->eqs};
+                     &p->gt_part, &p->Wdiag, &p->ref_res, &p->ref_dlt, &p->eqs};
   for (double** b : bufs) {
     if (*b) hipFree(*b);
     *b = nullptr;

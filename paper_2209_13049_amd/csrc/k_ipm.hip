@@ -23,7 +23,7 @@ int ipm_alloc_work(Problem& p) {
   double** vecs_n[] = {&p.v, &p.pv, &p.rhs, &p.Du, &p.Hv, &p.h, &p.tmpn, &p.eqs};
   for (double** q : vecs_n) CMPC_HIP(hipMalloc(q, sizeof(double) * n));
   CMPC_HIP(hipMalloc(&p.tmpn2, sizeof(double) * nmax));
-  double** vecs_r[] = {&p.ref_res, &p.ref_dlt, &p.ref_gt};
+  double** vecs_r[] = {&p.ref_res, &p.ref_dlt};
   for (double** q : vecs_r) CMPC_HIP(hipMalloc(q, sizeof(double) * n));
   double** vecs_m[] = {&p.s, &p.lam, &p.z, &p.ps, &p.plam, &p.pz, &p.d};
   for (double** q : vecs_m) CMPC_HIP(hipMalloc(q, sizeof(double) * m));
@@ -913,18 +913,6 @@ int launch_sigma_fold(Problem& p, const double* sigma) {
 //   res = rhs - K p;  stop when |res| <= 1e-12 |rhs|;  else p += (L L')^-1 res.
 // A step that does not shrink |res| by 10x counts as not contracting; after two the SYRK
 // moves one precision level up (BF16 -> FP32 -> FP64) from the next iteration on.  Every kernel is gated by st->ref_skip.
-__device__ __forceinline__ void scale_by_body(int bid, double* __restrict__ x, const double* __restrict__ w, int len,
-                                const int* __restrict__ skip) {
-  if (*skip) return;
-  const int i = bid * blockDim.x + threadIdx.x;
-  if (i < len) x[i] *= w[i];
-}
-
-__global__ void scale_by_kernel(double* __restrict__ x, const double* __restrict__ w, int len,
-                                const int* __restrict__ skip) {
-  scale_by_body(blockIdx.x, x, w, len, skip);
-}
-
 __device__ __forceinline__ void axpy_gated_body(int bid, double* __restrict__ y, const double* __restrict__ x, int len,
                                   const int* __restrict__ skip) {
   if (*skip) return;
@@ -939,19 +927,17 @@ __global__ void axpy_gated_kernel(double* __restrict__ y, const double* __restri
 
 // gt_part != NULL: Gamma'(D_x o Gamma p) is added up here from the Gamma' pass's partials (the
 // order of gamma_t_reduce), instead of being read from gtp.
+// Gamma'(D_x o Gamma p) enters as the Gamma' pass's per-chunk partials, added up here.
 __device__ __forceinline__ void refine_check_body(int bid, 
-    const double* __restrict__ rhs, const double* __restrict__ Hp, const double* __restrict__ gtp,
+    const double* __restrict__ rhs, const double* __restrict__ Hp,
     const double* __restrict__ Du, const double* __restrict__ p, double* __restrict__ res, int n,
-    IpmState* st, const double* __restrict__ gt_part = nullptr, int ns = 0, int nu = 0) {
+    IpmState* st, const double* __restrict__ gt_part, int ns, int nu) {
   __shared__ double sh2[2][4];
   if (st->ref_skip || st->done) return;
   double nr = 0.0, nb = 0.0;
   for (int c = threadIdx.x; c < n; c += 256) {
     double g[1];
-    if (gt_part != nullptr)
-      gamma_t_column<1>(gt_part, c, ns, nu, g);
-    else
-      g[0] = gtp[c];
+    gamma_t_column<1>(gt_part, c, ns, nu, g);
     const double r = rhs[c] - (Hp[c] + g[0] + Du[c] * p[c]);
     res[c] = r;
     nr = fmax(nr, fabs(r));
@@ -982,13 +968,13 @@ __device__ __forceinline__ void refine_check_body(int bid,
 }
 
 __global__ __launch_bounds__(256) void refine_check_kernel(
-    const double* __restrict__ rhs, const double* __restrict__ Hp, const double* __restrict__ gtp,
+    const double* __restrict__ rhs, const double* __restrict__ Hp,
     const double* __restrict__ Du, const double* __restrict__ p, double* __restrict__ res, int n,
     IpmState* st, const double* __restrict__ gt_part, int ns, int nu) {
-  refine_check_body(blockIdx.x, rhs, Hp, gtp, Du, p, res, n, st, gt_part, ns, nu);
+  refine_check_body(blockIdx.x, rhs, Hp, Du, p, res, n, st, gt_part, ns, nu);
 }
 
-// One refinement step in four launches (the same arithmetic as the batch form's eight):
+// One refinement step in four launches (the batch form's five carry the same arithmetic):
 // D_x o Gamma p (the scaling fused into the Gamma pass); the Gamma' pass's partials beside
 // H p; the residual with the partials added up in the check; p += (L L')^-1 res in the solve.
 int launch_refine_step(Problem& p) {
@@ -998,7 +984,7 @@ int launch_refine_step(Problem& p) {
                      p.stream, p.Gt, p.gpv, (long long)p.mx, p.gt_part, p.ns, p.nu, p.N,
                      p.gt_chunks, p.H, p.pv, p.Hv, p.n, skip);
   CMPC_LAUNCH_CHECK();
-  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(256), 0, p.stream, p.rhs, p.Hv, p.ref_gt,
+  hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(256), 0, p.stream, p.rhs, p.Hv,
                      p.Du, p.pv, p.ref_res, p.n, p.st, p.gt_part, p.ns, p.nu);
   CMPC_LAUNCH_CHECK();
   if (p.n <= kPotrsSingleMax)  // pv += the correction, in the solve's own store
@@ -1084,23 +1070,14 @@ __global__ __launch_bounds__(256) void prep_batch_kernel(const InstView* __restr
   CMPC_ITEMS_END
 }
 
-// which = 0: Gamma' [wx] (3 vectors) -> gt under st->done; which = 1: Gamma' gpv -> ref_gt
-// under st->ref_skip.
+// which = 0: Gamma' [wx] (3 vectors) -> partials under st->done; which = 1: Gamma' gpv ->
+// partials under st->ref_skip (added up in the refinement check).
 template <int NV>
 __global__ __launch_bounds__(256) void gamma_t_partial_batch_kernel(
     const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems) {
   CMPC_ITEMS_BEGIN
   gamma_t_partial_body<NV>(bid, V.Gt, NV == 3 ? V.wx : V.gpv, (long long)V.mx, V.gt_part,
                            V.ns, V.nu, V.N, gate_of(V, NV == 3 ? 0 : 1));
-  CMPC_ITEMS_END
-}
-
-template <int NV>
-__global__ __launch_bounds__(256) void gamma_t_reduce_batch_kernel(
-    const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems) {
-  CMPC_ITEMS_BEGIN
-  gamma_t_reduce_body<NV>(bid, V.gt_part, NV == 3 ? V.gt : V.ref_gt, V.n, V.ns, V.nu,
-                          gate_of(V, NV == 3 ? 0 : 1));
   CMPC_ITEMS_END
 }
 
@@ -1158,19 +1135,10 @@ __global__ __launch_bounds__(256) void update_batch_kernel(const InstView* __res
   CMPC_ITEMS_END
 }
 
-// refinement: gpv *= Dx (items over 256-row blocks of mx)
-__global__ __launch_bounds__(256) void scale_by_batch_kernel(const InstView* __restrict__ views,
-                                                             const WorkItem* __restrict__ items,
-                                                             int nitems) {
-  CMPC_ITEMS_BEGIN
-  scale_by_body(bid, V.gpv, V.Dx, V.mx, &V.st->ref_skip);
-  CMPC_ITEMS_END
-}
-
 __global__ __launch_bounds__(256) void refine_check_batch_kernel(
     const InstView* __restrict__ views, const WorkItem* __restrict__ items, int nitems) {
   CMPC_ITEMS_BEGIN
-  refine_check_body(bid, V.rhs, V.Hv, V.ref_gt, V.Du, V.pv, V.ref_res, V.n, V.st, V.gt_part,
+  refine_check_body(bid, V.rhs, V.Hv, V.Du, V.pv, V.ref_res, V.n, V.st, V.gt_part,
                     V.ns, V.nu);
   CMPC_ITEMS_END
 }
@@ -1229,10 +1197,6 @@ int launch_b_gamma_t_partial(const ListArg& L, int nv) {
   if (nv == 3) CMPC_LAUNCH_LIST(gamma_t_partial_batch_kernel<3>, L);
   CMPC_LAUNCH_LIST(gamma_t_partial_batch_kernel<1>, L);
 }
-int launch_b_gamma_t_reduce(const ListArg& L, int nv) {
-  if (nv == 3) CMPC_LAUNCH_LIST(gamma_t_reduce_batch_kernel<3>, L);
-  CMPC_LAUNCH_LIST(gamma_t_reduce_batch_kernel<1>, L);
-}
 int launch_b_hv(const ListArg& L, int gate) { CMPC_LAUNCH_LIST(hv_batch_kernel, L, gate); }
 int launch_b_mu_rhs(const ListArg& L) { CMPC_LAUNCH_LIST(mu_rhs_batch_kernel, L); }
 int launch_b_gamma_mv(const ListArg& L, int gate) {
@@ -1240,7 +1204,6 @@ int launch_b_gamma_mv(const ListArg& L, int gate) {
 }
 int launch_b_step(const ListArg& L) { CMPC_LAUNCH_LIST(step_batch_kernel, L); }
 int launch_b_update(const ListArg& L) { CMPC_LAUNCH_LIST(update_batch_kernel, L); }
-int launch_b_scale_by(const ListArg& L) { CMPC_LAUNCH_LIST(scale_by_batch_kernel, L); }
 int launch_b_refine_check(const ListArg& L) { CMPC_LAUNCH_LIST(refine_check_batch_kernel, L); }
 int launch_b_axpy(const ListArg& L) { CMPC_LAUNCH_LIST(axpy_batch_kernel, L); }
 

@@ -94,7 +94,7 @@ struct Problem {
   double *pv = nullptr, *ps = nullptr, *plam = nullptr, *pz = nullptr, *gpv = nullptr;
   double *rhs = nullptr, *Dx = nullptr, *Du = nullptr, *wx = nullptr, *wu = nullptr;
   double *gt = nullptr, *Hv = nullptr, *tmpn = nullptr, *tmpn2 = nullptr, *tmpmx = nullptr;
-  double *ref_res = nullptr, *ref_dlt = nullptr, *ref_gt = nullptr;  // refinement vectors (n)
+  double *ref_res = nullptr, *ref_dlt = nullptr;  // refinement vectors (n)
   double *norm_part = nullptr, *alpha_part = nullptr, *gt_part = nullptr;
   int n_prep_blocks = 0, n_step_blocks = 0, gt_chunks = 0;
   bool eq_on = false;               // this solve factors the equilibrated S K S
@@ -134,7 +134,7 @@ struct InstView {
   double *K, *Wdiag, *eqs;
   double *v, *s, *lam, *z, *gv, *pv, *ps, *plam, *pz, *gpv;
   double *rhs, *Dx, *Du, *wx, *wu, *gt, *Hv, *tmpn;
-  double *ref_res, *ref_dlt, *ref_gt;
+  double *ref_res, *ref_dlt;
   double *norm_part, *alpha_part, *gt_part;
   IpmState* st;
   const SyrkJob* jobs;
@@ -219,7 +219,6 @@ int launch_b_init(const ListArg& L, double tol, int max_iter, int low, double mu
                   double contract, int warm = 0, double mu0 = 0.0);
 int launch_b_prep(const ListArg& L);
 int launch_b_gamma_t_partial(const ListArg& L, int nv);
-int launch_b_gamma_t_reduce(const ListArg& L, int nv);
 int launch_b_hv(const ListArg& L, int gate);
 int launch_b_mu_rhs(const ListArg& L);
 // gate 0: gpv = Gamma pv under st->done; 1: the same under st->ref_skip; 2: gv = Gamma v for
@@ -227,7 +226,6 @@ int launch_b_mu_rhs(const ListArg& L);
 int launch_b_gamma_mv(const ListArg& L, int gate);
 int launch_b_step(const ListArg& L);
 int launch_b_update(const ListArg& L);
-int launch_b_scale_by(const ListArg& L);
 int launch_b_refine_check(const ListArg& L);
 int launch_b_axpy(const ListArg& L);
 int launch_b_publish(hipStream_t s, const InstView* views, int count, int* iter, int* flags,
