@@ -166,13 +166,17 @@ def batch_leg(steps: int, count: int = 512):
 def headline_batch_leg(count: int, steps: int):
     """`count` instances of the headline workload (the same A, B, weights and bounds; x0 of
     instances 0 .. count-1) solved together in FP64 by one batch (graph-replayed iterations,
-    converged instances predicated off): throughput, and the first three instances against
-    the same solves on the single-instance path (iterations and objectives)."""
+    converged instances predicated off) after the autotuner has chosen the batch's SYRK plan:
+    throughput, and the first three instances against the same solves on the single-instance
+    path (iterations and objectives; the single path here also follows the tuned plan)."""
     import torch
     from paper_2209_13049_amd import condmpc
     from paper_2209_13049_amd import workloads as W
     probs = [W.heat1d_config("1d", instance=k) for k in range(count)]
+    condmpc.tune_clear()
     b = condmpc.Batch(probs)
+    # the autotuner picks the batch's SYRK work quantum and grid policy (set-up, not timed)
+    tune = b.tune(condmpc.FP64)
     rc, res = b.solve()  # warm-up: work lists and graph capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -193,8 +197,11 @@ def headline_batch_leg(count: int, steps: int):
         diffs.append(abs(r["obj"] - res[k]["obj"]) / max(1.0, abs(r["obj"])))
     single.close()
     b.close()
+    condmpc.tune_clear()  # the other legs run on the default plans
     return {"workload": f"heat1d_ns1000_nu10_N50 x {count} (x0 of instances 0..{count - 1})",
             "instances": count, "precision": "fp64", "solves_per_s": count * steps / el,
+            "tune": {"quantum": tune["quantum"], "persistent": tune["persistent"],
+                     "syrk_us": tune["syrk_us"], "default_syrk_us": tune["default_us"]},
             "ms_per_batch": el * 1e3 / steps, "ms_per_batch_iter": el * 1e3 / max(1, iters),
             "max_iters": max(r["iters"] for r in res),
             "converged": sum(r["status"] == condmpc.OK for r in res),
