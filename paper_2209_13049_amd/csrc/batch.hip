@@ -220,7 +220,7 @@ static int build_lists(Batch& b) {
   add(b.syrk, [](const InstView& v) { return v.syrk_nwg; });
   add(b.fin, [&](const InstView& v) { return v.nt * (v.nt + 1) / 2 * 16; });
   add(b.n256, [](const InstView& v) { return ceil_div(v.n, 256); });
-  add(b.gmv, [](const InstView& v) { return gmv_blocks(v.ns, v.N); });
+  add(b.gmv, [](const InstView& v) { return gmv_blocks<kMvTBatch>(v.ns, v.N); });
   b.ntmax = 0;
   b.nmax = 0;
   for (const InstView& v : hv) {

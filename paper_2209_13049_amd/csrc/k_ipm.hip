@@ -204,38 +204,40 @@ int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int
 
 // ---------------------------------------------------------------- y = Gamma x
 // y[(t-1) ns + i] = sum_{e < t nu} Gt[e][i] x[(t-1-m) nu + k]  (e = m nu + k).  One
-// workgroup per (group of kMvT row blocks t = t_hi, t_hi - 1, ..., larger first; 64 rows):
-// lane = row i (coalesced rows of Gt), wavefront w takes the quarter [w T/4, (w+1) T/4) of e
-// (T = t_hi nu) for every row block of the group, so each row of Gt is read once for the
-// group; the x entries, the same in every lane, come through the scalar cache, issued with
-// the rows (16 e per pass); the four quarters are added in order.
+// workgroup per (group of MT row blocks t = t_hi, t_hi - 1, ..., larger first; 64 rows):
+// lane = row i (coalesced rows of Gt).  The range of e is cut into chunks of 16; wavefront w
+// takes the chunks c = w, w + 4, w + 8, ... in order (each row of Gt read once for the whole
+// group) and keeps one sum per row block of the group, and the four wavefronts' sums are added
+// in order.  Which wavefront adds which term, and in which order, depends only on e, so the
+// result does not depend on MT.  The x entries, the same in every lane, come through the
+// scalar cache, issued with the rows.
+template <int MT>
 __device__ __forceinline__ void gamma_mv_body(int bid, const double* __restrict__ Gt,
                                               const double* __restrict__ x,
                                               double* __restrict__ y, int ns, int nu, int N,
                                               const int* __restrict__ done,
                                               const double* __restrict__ scale = nullptr) {
-  __shared__ double red[4][kMvT][64];
+  __shared__ double red[4][MT][64];
   if (done != nullptr && *done) return;
   const int nbx = (ns + 63) >> 6;
   const int tb = bid / nbx, bx = bid - tb * nbx;
-  const int t_hi = N - kMvT * tb;
+  const int t_hi = N - MT * tb;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int i = 64 * bx + lane, ic = i < ns ? i : ns - 1;
   const int T = t_hi * nu;
-  const int e_begin = (w * T) >> 2, e_end = ((w + 1) * T) >> 2;
-  int m = e_begin / nu, k = e_begin - m * nu;
-  double acc[kMvT];
+  double acc[MT];
 #pragma unroll
-  for (int u = 0; u < kMvT; ++u) acc[u] = 0.0;
-  for (int e0 = e_begin; e0 < e_end; e0 += 16) {
-    double gv[16], xv[16][kMvT];
-    int mq = m, kq = k;
+  for (int u = 0; u < MT; ++u) acc[u] = 0.0;
+  for (int e0 = 16 * w; e0 < T; e0 += 64) {
+    double gv[16], xv[16][MT];
+    const int m0 = e0 / nu, k0 = e0 - m0 * nu;
+    int mq = m0, kq = k0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int e = e0 + q < e_end ? e0 + q : e_end - 1;
+      const int e = e0 + q < T ? e0 + q : T - 1;
       gv[q] = Gt[(long long)e * ns + ic];
 #pragma unroll
-      for (int u = 0; u < kMvT; ++u) {
+      for (int u = 0; u < MT; ++u) {
         const int xi = (t_hi - u - 1 - mq) * nu + kq;
         xv[q][u] = x[xi > 0 ? xi : 0];
       }
@@ -244,11 +246,12 @@ __device__ __forceinline__ void gamma_mv_body(int bid, const double* __restrict_
         ++mq;
       }
     }
+    int m = m0, k = k0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      if (e0 + q < e_end) {
+      if (e0 + q < T) {
 #pragma unroll
-        for (int u = 0; u < kMvT; ++u)
+        for (int u = 0; u < MT; ++u)
           if (m < t_hi - u) acc[u] = fma(gv[q], xv[q][u], acc[u]);
       }
       if (++k == nu) {
@@ -258,9 +261,9 @@ __device__ __forceinline__ void gamma_mv_body(int bid, const double* __restrict_
     }
   }
 #pragma unroll
-  for (int u = 0; u < kMvT; ++u) red[w][u][lane] = acc[u];
+  for (int u = 0; u < MT; ++u) red[w][u][lane] = acc[u];
   __syncthreads();
-  if (w < kMvT) {  // wavefront w writes row block t_hi - w
+  if (w < MT) {  // wavefront w writes row block t_hi - w
     const int t = t_hi - w;
     if (t >= 1 && i < ns) {
       const long long r = (long long)(t - 1) * ns + i;
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(256) void gamma_mv_kernel(const double* __restrict_
                                                        double* __restrict__ y, int ns, int nu,
                                                        int N, const int* __restrict__ done,
                                                        const double* __restrict__ scale) {
-  gamma_mv_body(blockIdx.x, Gt, x, y, ns, nu, N, done, scale);
+  gamma_mv_body<kMvT>(blockIdx.x, Gt, x, y, ns, nu, N, done, scale);
 }
 
 int launch_gamma_mv(Problem& p, const double* x, double* y, const int* done,
@@ -1106,9 +1109,9 @@ __global__ __launch_bounds__(256) void gamma_mv_batch_kernel(const InstView* __r
                                                              int nitems, int gate) {
   CMPC_ITEMS_BEGIN
   if (gate == 2)
-    gamma_mv_body(bid, V.Gt, V.v, V.gv, V.ns, V.nu, V.N, nullptr);
+    gamma_mv_body<kMvTBatch>(bid, V.Gt, V.v, V.gv, V.ns, V.nu, V.N, nullptr);
   else  // the refinement's pass (gate 1) is scaled by D_x, as in the single-instance step
-    gamma_mv_body(bid, V.Gt, V.pv, V.gpv, V.ns, V.nu, V.N, gate_of(V, gate),
+    gamma_mv_body<kMvTBatch>(bid, V.Gt, V.pv, V.gpv, V.ns, V.nu, V.N, gate_of(V, gate),
                   gate == 1 ? V.Dx : nullptr);
   CMPC_ITEMS_END
 }

@@ -156,12 +156,16 @@ inline int gt_chunk_count(int ns, int nu, int N) {
 }
 // Gamma x through the blocks of Gamma: block (t, j) is G_{t-1-j} = A^(t-1-j) B (zero for
 // j >= t), so Gamma is block Toeplitz and (Gamma x)_t = sum_{m<t} G_m x_{t-1-m}, read from Gt
-// (n x ns, rows e = m nu + k).  One workgroup per (kMvT row blocks, 64 rows); groups of 2
-// and 4 row blocks share the rows of Gt but were measured slower (longer chains per
-// wavefront at n = 500).
+// (n x ns, rows e = m nu + k).  One workgroup per (group of MT row blocks, 64 rows); the
+// blocks of a group share the rows of Gt.  A single solve uses MT = kMvT = 1 (groups of 2 and
+// 4 were measured slower at n = 500: longer chains per wavefront); a batch, whose instances
+// already fill the chip, uses kMvTBatch = 4 and reads a quarter of the rows.  The order of
+// every sum does not depend on MT, so both give the same bits.
 constexpr int kMvT = 1;
+constexpr int kMvTBatch = 4;
+template <int MT = kMvT>
 __host__ __device__ inline int gmv_blocks(int ns, int N) {
-  return ((ns + 63) / 64) * ((N + kMvT - 1) / kMvT);
+  return ((ns + 63) / 64) * ((N + MT - 1) / MT);
 }
 
 // One entry of a work list: block `local` of instance `inst`.
