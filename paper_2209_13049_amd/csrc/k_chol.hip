@@ -15,10 +15,10 @@
 // takes one step of iterative refinement against L_kk (refine_panel), so that the panel is as
 // accurate as a triangular solve; the redundant copies of a panel in different workgroups stay
 // identical.
-// A diagonal tile is factored by 4 wavefronts (wavefront w owns columns 16w..16w+15, lane
-// = row) with one barrier per column, and inverted by forward substitution with 4 lanes per
-// column (no barriers).  The inverses W_k are kept (nt x 64 x 64) so that the triangular
-// solves become block matrix-vector products.
+// A diagonal tile is factored by 4 wavefronts in 16 panels of 4 columns dealt round robin
+// (lane = row, one barrier per panel: chol_panels) and inverted in 16 x 16 blocks (inv64:
+// substitution for the diagonal blocks, MFMA products for the rest).  The inverses W_k are
+// kept (nt x 64 x 64) so that the triangular solves become block matrix-vector products.
 #include "problem.hpp"
 
 namespace cmpc {
