@@ -210,15 +210,25 @@ int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int
 // group) and keeps one sum per row block of the group, and the four wavefronts' sums are added
 // in order.  Which wavefront adds which term, and in which order, depends only on e, so the
 // result does not depend on MT.  The x entries, the same in every lane, come through the
-// scalar cache, issued with the rows.
+// scalar cache (MT = 1) or, for the groups' four times as many, from a copy of x in LDS
+// (broadcast reads; n <= kMvXs); the copy measured slower for MT = 1.
+constexpr int kMvXs = 4096;
 template <int MT>
 __device__ __forceinline__ void gamma_mv_body(int bid, const double* __restrict__ Gt,
-                                              const double* __restrict__ x,
+                                              const double* __restrict__ xg,
                                               double* __restrict__ y, int ns, int nu, int N,
                                               const int* __restrict__ done,
                                               const double* __restrict__ scale = nullptr) {
   __shared__ double red[4][MT][64];
+  __shared__ double xs[MT > 1 ? kMvXs : 1];
   if (done != nullptr && *done) return;
+  const int n = N * nu;
+  const bool in_lds = MT > 1 && n <= kMvXs;  // uniform
+  if (in_lds) {
+    for (int c = threadIdx.x; c < n; c += 256) xs[c] = xg[c];
+    __syncthreads();
+  }
+  const double* x = in_lds ? xs : xg;
   const int nbx = (ns + 63) >> 6;
   const int tb = bid / nbx, bx = bid - tb * nbx;
   const int t_hi = N - MT * tb;
