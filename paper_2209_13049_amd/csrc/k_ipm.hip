@@ -210,9 +210,11 @@ int launch_gamma_t(Problem& p, const double* w, int nvec, double* out, const int
 // group) and keeps one sum per row block of the group, and the four wavefronts' sums are added
 // in order.  Which wavefront adds which term, and in which order, depends only on e, so the
 // result does not depend on MT.  The x entries, the same in every lane, come through the
-// scalar cache (MT = 1) or, for the groups' four times as many, from a copy of x in LDS
-// (broadcast reads; n <= kMvXs); the copy measured slower for MT = 1.
-constexpr int kMvXs = 4096;
+// scalar cache, loaded with the rows (MT = 1), or, for the groups' four times as many, from a
+// copy of x in LDS read where each product needs it (broadcast reads; n <= kMvXs), which keeps
+// the registers, and so the waves in flight, of a single block's pass; the copy measured
+// slower for MT = 1.
+constexpr int kMvXs = 2048;
 template <int MT>
 __device__ __forceinline__ void gamma_mv_body(int bid, const double* __restrict__ Gt,
                                               const double* __restrict__ xg,
@@ -238,35 +240,61 @@ __device__ __forceinline__ void gamma_mv_body(int bid, const double* __restrict_
   double acc[MT];
 #pragma unroll
   for (int u = 0; u < MT; ++u) acc[u] = 0.0;
-  for (int e0 = 16 * w; e0 < T; e0 += 64) {
-    double gv[16], xv[16][MT];
-    const int m0 = e0 / nu, k0 = e0 - m0 * nu;
-    int mq = m0, kq = k0;
+  if constexpr (MT > 1) {  // x read where it is used (from LDS if it fits): few registers,
+                           // many waves in flight (loading the next chunk's rows ahead measured
+                           // slower: fewer waves)
+    for (int e0 = 16 * w; e0 < T; e0 += 64) {
+      double gv[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = e0 + q < T ? e0 + q : T - 1;
-      gv[q] = Gt[(long long)e * ns + ic];
-#pragma unroll
-      for (int u = 0; u < MT; ++u) {
-        const int xi = (t_hi - u - 1 - mq) * nu + kq;
-        xv[q][u] = x[xi > 0 ? xi : 0];
+      for (int q = 0; q < 16; ++q) {
+        const int e = e0 + q < T ? e0 + q : T - 1;
+        gv[q] = Gt[(long long)e * ns + ic];
       }
-      if (++kq == nu) {
-        kq = 0;
-        ++mq;
+      int m = e0 / nu, k = e0 - m * nu;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        if (e0 + q < T) {
+#pragma unroll
+          for (int u = 0; u < MT; ++u)
+            if (m < t_hi - u) acc[u] = fma(gv[q], x[(t_hi - u - 1 - m) * nu + k], acc[u]);
+        }
+        if (++k == nu) {
+          k = 0;
+          ++m;
+        }
       }
     }
-    int m = m0, k = k0;
+  } else {
+    for (int e0 = 16 * w; e0 < T; e0 += 64) {
+      double gv[16], xv[16][MT];
+      const int m0 = e0 / nu, k0 = e0 - m0 * nu;
+      int mq = m0, kq = k0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      if (e0 + q < T) {
+      for (int q = 0; q < 16; ++q) {
+        const int e = e0 + q < T ? e0 + q : T - 1;
+        gv[q] = Gt[(long long)e * ns + ic];
 #pragma unroll
-        for (int u = 0; u < MT; ++u)
-          if (m < t_hi - u) acc[u] = fma(gv[q], xv[q][u], acc[u]);
+        for (int u = 0; u < MT; ++u) {
+          const int xi = (t_hi - u - 1 - mq) * nu + kq;
+          xv[q][u] = x[xi > 0 ? xi : 0];
+        }
+        if (++kq == nu) {
+          kq = 0;
+          ++mq;
+        }
       }
-      if (++k == nu) {
-        k = 0;
-        ++m;
+      int m = m0, k = k0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        if (e0 + q < T) {
+#pragma unroll
+          for (int u = 0; u < MT; ++u)
+            if (m < t_hi - u) acc[u] = fma(gv[q], xv[q][u], acc[u]);
+        }
+        if (++k == nu) {
+          k = 0;
+          ++m;
+        }
       }
     }
   }
