@@ -212,45 +212,15 @@ static int build_lists(Batch& b) {
     }
     L.count = (int)all.size() - L.off;
   };
-  // The Gamma passes' items in XCD order: workgroups are dealt to the 8 XCDs round robin (a
-  // persistent grid is a multiple of 8), so item p runs on XCD p % 8; instance i's items are
-  // put at positions of XCD i % 8, in order, so that an XCD works through a few instances at
-  // a time and their blocks G_m stay in its L2 (a queue that runs out lends its positions to
-  // the longest remaining one).
-  auto add_xcd = [&](List& L, auto per) {
-    constexpr int kXcd = 8;
-    std::vector<std::vector<WorkItem>> q(kXcd);
-    size_t total = 0;
-    for (int i = 0; i < b.count; ++i) {
-      const int c = per(hv[i]);
-      for (int j = 0; j < c; ++j) q[i % kXcd].push_back(WorkItem{i, j});
-      total += (size_t)c;
-    }
-    L.off = (int)all.size();
-    std::vector<size_t> pos(kXcd, 0);
-    for (size_t p = 0; p < total; ++p) {
-      int x = (int)(p % kXcd);
-      if (pos[x] >= q[x].size()) {
-        size_t rem = 0;
-        for (int y = 0; y < kXcd; ++y)
-          if (q[y].size() - pos[y] > rem) {
-            rem = q[y].size() - pos[y];
-            x = y;
-          }
-      }
-      all.push_back(q[x][pos[x]++]);
-    }
-    L.count = (int)all.size() - L.off;
-  };
   add(b.init, [](const InstView& v) { return ceil_div(v.m, 256); });
   add(b.blk, [](const InstView& v) { return v.nblk; });
-  add_xcd(b.gt, [](const InstView& v) { return v.gt_chunks; });
+  add(b.gt, [](const InstView& v) { return v.gt_chunks; });
   add(b.n4, [](const InstView& v) { return ceil_div(v.n, 4); });
   add(b.one, [](const InstView&) { return 1; });
   add(b.syrk, [](const InstView& v) { return v.syrk_nwg; });
   add(b.fin, [&](const InstView& v) { return v.nt * (v.nt + 1) / 2 * 16; });
   add(b.n256, [](const InstView& v) { return ceil_div(v.n, 256); });
-  add_xcd(b.gmv, [](const InstView& v) { return gmv_blocks<kMvTBatch>(v.ns, v.N); });
+  add(b.gmv, [](const InstView& v) { return gmv_blocks<kMvTBatch>(v.ns, v.N); });
   b.ntmax = 0;
   b.nmax = 0;
   for (const InstView& v : hv) {
