@@ -10,7 +10,9 @@ Gamma pass lists.
 * FP64: every instance converges and equals its single-instance solve bit for bit (same
   iterates, same iteration count); two instances (9 and 12 tile columns) meet the oracle's bar;
 * FP32 start (default plans, no tuning): every instance converges to the FP64 batch's optimum
-  within the solve tolerance.
+  within the solve tolerance;
+* the benchmarked workload as a batch on the autotuner's FP64 plan equals single solves on the
+  same plan bit for bit.
 """
 import numpy as np
 import pytest
@@ -91,3 +93,32 @@ def test_large_batch_fp32_start_reaches_the_optimum(large):
         assert abs(a["iters"] - c["iters"]) <= 3
         u, _ = b[j].solution(with_x=False)
         assert rel_err(u, u64[j]) <= 1e-6
+
+
+def test_headline_batch_tuned_fp64_bitwise_single(lib):
+    """Four instances of the benchmarked workload (K 500 x 500, 50,000 state rows): the
+    autotuner's FP64 plan, then the batch against single solves that follow the same tuning
+    entry, bit for bit; the table is cleared afterwards."""
+    probs = [W.heat1d_config("1d", instance=k) for k in range(4)]
+    condmpc.tune_clear()
+    b = condmpc.Batch(probs)
+    try:
+        rep = b.tune(condmpc.FP64)
+        print(f"[batch-large] headline tune: {rep}", flush=True)
+        assert rep["quantum"] in (3000, 6000, 12000, 24000, 48000, 96000)
+        rc, results = b.solve(precision=condmpc.FP64)
+        assert rc == condmpc.OK
+        for j, p in enumerate(probs):
+            assert condmpc.tune_lookup(p.n, b[j].mx, condmpc.FP64) == (rep["quantum"],
+                                                                      rep["persistent"])
+            ub, _ = b[j].solution(with_x=False)
+            single = condmpc.Problem(p)
+            single.set_x0(p.x0)
+            r = single.solve()
+            us, _ = single.solution(with_x=False)
+            single.close()
+            assert results[j]["status"] == condmpc.OK and r["iters"] == results[j]["iters"]
+            assert np.array_equal(ub, us), f"instance {j}"
+    finally:
+        b.close()
+        condmpc.tune_clear()
